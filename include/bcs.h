@@ -1,0 +1,159 @@
+/* bcs.h -- batched Block-cells BiCGStab for (I - gamma*J) x = b on AMD gfx950.
+ *
+ * One small sparse linear system per grid cell.  All cells share one sparsity
+ * pattern (the chemical Jacobian's, Section 2.2: CAMP stores the Jacobian
+ * sparse, and in the multi-cell form each species y_ik belongs to a cell k);
+ * every cell has its own values.  Each cell is solved entirely inside one
+ * workgroup, with no communication between workgroups and no host round trip
+ * during the solve (the Block-cells arrangement of Section 3.1, whose BCG
+ * solver is realised here as BiCGStab).  The linear system is the Newton
+ * matrix of the BDF integrator, which needs one linear solve per step
+ * (Section 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Pattern arrays passed to bcs_plan_create are HOST pointers; they are
+ *     copied, the caller keeps ownership.
+ *   - Every per-cell array passed to a solve is a DEVICE pointer owned by the
+ *     caller (e.g. torch tensors); the library never allocates, frees or
+ *     retains them.  Layouts are row-major, cell-major: values [ncells, nnz]
+ *     in the CSR order of the plan's pattern, vectors [ncells, n].
+ *   - Solves are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream).  Outputs are valid once the stream has been synchronised.
+ *   - Return value: BCS_OK (0), or a negative BCS_ERR_* code for argument,
+ *     pattern, support or HIP runtime errors, detected synchronously before
+ *     any launch; bcs_last_error() then describes it (thread-local string).
+ *     Numerical outcomes are never return codes: they are per-cell in
+ *     `status`.
+ *   - ncells == 0 is a no-op that returns BCS_OK.
+ *   - Solves that share a plan and overlap in time (different streams, or
+ *     several host threads) race on the plan's work-queue counters: serialise
+ *     them, or create one plan per stream.
+ */
+#ifndef BCS_H
+#define BCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define BCS_OK 0
+#define BCS_ERR_ARG (-1)         /* bad argument (null pointer, size, option value) */
+#define BCS_ERR_PATTERN (-2)     /* invalid CSR pattern */
+#define BCS_ERR_UNSUPPORTED (-3) /* valid but outside what the kernels handle (e.g. n too large) */
+#define BCS_ERR_HIP (-4)         /* HIP runtime error (allocation, copy, launch) */
+
+/* per-cell status */
+#define BCS_CONVERGED 0 /* true relative residual ||b - A x||/||b|| <= rtol */
+#define BCS_MAXIT 1     /* stopped without reaching rtol (iteration or refinement budget spent) */
+#define BCS_BREAKDOWN 2 /* exact-zero rho, sigma, tau or omega after the allowed restarts */
+#define BCS_NONFINITE 3 /* a non-finite value appeared (NaN/Inf in inputs or iterates) */
+
+/* options */
+#define BCS_FP64 0        /* all arithmetic in FP64 */
+#define BCS_FP32_REFINE 1 /* FP32 inner BiCGStab, FP64 residual, scaling and update */
+#define BCS_PRECOND_NONE 0
+#define BCS_PRECOND_JACOBI 1 /* right preconditioning with M = diag(A) */
+#define BCS_J_GAMMA 0        /* values hold J; A = I - gamma*J (pattern must hold the diagonal) */
+#define BCS_A_DIRECT 1       /* values hold A itself; gamma is ignored */
+
+typedef struct bcs_options {
+  int32_t precision;            /* BCS_FP64 | BCS_FP32_REFINE                          */
+  int32_t precond;              /* BCS_PRECOND_NONE | BCS_PRECOND_JACOBI               */
+  int32_t matrix_kind;          /* BCS_J_GAMMA | BCS_A_DIRECT                          */
+  int32_t lanes_per_cell;       /* 0 = choose; else 16, 32 or 64 lanes own one cell   */
+  int32_t residual_replacement; /* 1: on a recurrence-only convergence, restart from
+                                   the true residual while iterations remain          */
+  int32_t breakdown_restarts;   /* restarts allowed after an exact breakdown          */
+  double inner_rtol;            /* FP32_REFINE: inner solve tolerance (relative)      */
+  int32_t max_refine;           /* FP32_REFINE: maximum number of inner solves        */
+  int32_t reserved[7];          /* must be zero                                       */
+} bcs_options;
+
+typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
+                                     work-queue counters (see the note above) */
+
+/* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
+ * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
+ * max_refine 10. */
+void bcs_options_default(bcs_options* opt);
+
+/* Create a plan for an n x n pattern with nnz entries in CSR form
+ * (row_ptr[n+1], col_idx[nnz], HOST int32 arrays).  The pattern must have
+ * row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing row_ptr, strictly
+ * increasing columns in [0, n) within each row, and (for BCS_J_GAMMA or
+ * Jacobi preconditioning) every diagonal entry.  opt == NULL means defaults.
+ * Allocates the plan's device tables on the current HIP device; the plan
+ * must be used on that device.  On error *out is set to NULL. */
+int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                    const bcs_options* opt, bcs_plan** out);
+
+/* Release a plan (NULL is allowed).  The caller must ensure no solve using it
+ * is still running. */
+void bcs_plan_destroy(bcs_plan* plan);
+
+/* Describe the plan's launch configuration (for logs and tests):
+ * lanes per cell, rows per lane, schedule steps per lane, cells per
+ * workgroup.  Any output pointer may be NULL. */
+int bcs_plan_info(const bcs_plan* plan, int32_t* lanes_per_cell, int32_t* rows_per_lane,
+                  int32_t* steps_per_lane, int32_t* cells_per_wg);
+
+/* Solve (I - gamma_c J_c) x_c = b_c (or A_c x_c = b_c) for every cell c by
+ * BiCGStab with x0 = 0, stopping when the relative residual ||r||/||b|| is
+ * <= rtol and confirming it on the true residual (Section 3.1's linear
+ * solve, one workgroup-resident solve per cell).
+ *   values [ncells, nnz]  device, FP64: J (BCS_J_GAMMA) or A (BCS_A_DIRECT)
+ *   gamma                 device, FP64: gamma of cell c is gamma[c*gamma_stride]
+ *                         (gamma_stride 0 = one shared value); unused for A_DIRECT
+ *   b [ncells, n]         device, FP64
+ *   rtol > 0, 1 <= maxit <= 1000000
+ *   x [ncells, n]         device, FP64 out: last iterate (also when not converged)
+ *   iters [ncells]        device, int32 out: BiCGStab iterations (half-step exit
+ *                         counts 1; FP32_REFINE: total inner iterations)
+ *   resid [ncells]        device, FP64 out: true relative residual ||b-Ax||/||b||
+ *                         recomputed in FP64 (0 when b = 0)
+ *   status [ncells]       device, int32 out: BCS_CONVERGED .. BCS_NONFINITE
+ *   refinements [ncells]  device, int32 out or NULL: FP32_REFINE inner solves
+ *                         performed (0 for FP64)
+ * The input arrays must not overlap the output arrays. */
+int bcs_solve_batch(const bcs_plan* plan, int64_t ncells, const double* values, const double* gamma,
+                    int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
+                    int32_t* iters, double* resid, int32_t* status, int32_t* refinements, void* stream);
+
+/* Adjoint of the solve for a loss L(x): given the forward solution x and
+ * g = dL/dx, solve A_c^T lambda_c = g_c by the same batched BiCGStab run on
+ * the transposed pattern (same workgroup layout, FP64), then write
+ *   grad_b [ncells, n]   = lambda                          (dL/db)
+ *   grad_A [ncells, nnz] = -lambda_i * x_j at entry (i, j) (dL/dA on the pattern)
+ * iters/resid/status describe the transposed solve.  The chain rule to J and
+ * gamma (A = I - gamma J) is left to the caller:
+ *   dL/dJ_k = -gamma * grad_A[k],  dL/dgamma = -sum_k J_k grad_A[k].
+ * Arguments as in bcs_solve_batch; x and g are device [ncells, n] FP64. */
+int bcs_solve_batch_adjoint(const bcs_plan* plan, int64_t ncells, const double* values,
+                            const double* gamma, int64_t gamma_stride, const double* x, const double* g,
+                            double rtol, int32_t maxit, double* grad_b, double* grad_A, int32_t* iters,
+                            double* resid, int32_t* status, void* stream);
+
+/* One persistent launch over several mechanisms (plans), each with its own
+ * cells: workgroups pull cells from per-mechanism work queues, so a cell
+ * slot that converges takes the next unsolved cell (the remainder kernel of
+ * Section 3.2 and the fixed cells-per-block choices of Table 1 replaced by
+ * work stealing).  Arrays are per mechanism m (host arrays of device
+ * pointers, length nmech); semantics per cell as in bcs_solve_batch.  All
+ * plans must use BCS_FP64.  nmech <= 8. */
+int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells,
+                    const double* const* values, const double* const* gamma, const int64_t* gamma_stride,
+                    const double* const* b, double rtol, int32_t maxit, double* const* x,
+                    int32_t* const* iters, double* const* resid, int32_t* const* status, void* stream);
+
+/* Description of the last error on this thread ("" if none). */
+const char* bcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCS_H */

@@ -1,0 +1,176 @@
+"""CPU oracle for batched (I - gamma*J) x = b solves -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It is a plain, slow, obviously correct FP64 (and, for
+the mixed form, FP32) implementation in C (``oracle.c``), loaded through
+ctypes.  It shares no code with the HIP library.
+
+Functions (all take/return numpy arrays):
+  solve_batch   BiCGStab per cell (FP64)                   -> x, iters, resid, status
+  lu_batch      dense LU with partial pivoting per cell   -> x (ground truth)
+  adjoint_batch lambda = A^-T g and dL/dA on the pattern   -> grad_b, grad_A, iters, resid, status
+  mixed_batch   FP32 inner BiCGStab + FP64 refinement      -> x, iters, refinements, resid, status
+  form_a        A = I - gamma*J on the pattern
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+J_GAMMA, A_DIRECT = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "bicgstab_body.h")]
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C, OpenMP, no FMA contraction)."""
+    with _lock:
+        if force or not os.path.exists(_LIB_PATH):
+            tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+            cmd = ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+                   "-std=c11", "-Wall", "-o", tmp, _SRC[0], "-lm"]
+            subprocess.run(cmd, check=True, cwd=_HERE)
+            os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_solve_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _dbl, _int, _int, _int,
+                                       _int, _D, _I, _D, _I, _int]
+    lib.oracle_solve_batch.restype = None
+    lib.oracle_lu_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _int, _D, _D, _I, _int]
+    lib.oracle_lu_batch.restype = None
+    lib.oracle_adjoint_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _D, _dbl, _int, _int,
+                                         _int, _int, _D, _D, _I, _D, _I, _int]
+    lib.oracle_adjoint_batch.restype = None
+    lib.oracle_mixed_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _dbl, _int, _dbl, _int,
+                                       _D, _I, _I, _D, _I, _int]
+    lib.oracle_mixed_batch.restype = None
+    lib.oracle_form_a.argtypes = [_int, _I, _I, _D, _dbl, _D]
+    lib.oracle_form_a.restype = None
+    lib.oracle_lu_solve.argtypes = [_int, _D, _D]
+    lib.oracle_lu_solve.restype = _int
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = _int
+    _lib = lib
+    return lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _prep(row_ptr, col_idx, values, gamma, b=None):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.shape[0] - 1
+    nnz = ci.shape[0]
+    vals = np.ascontiguousarray(values, dtype=np.float64).reshape(-1, nnz)
+    ncells = vals.shape[0]
+    g = np.ascontiguousarray(np.atleast_1d(np.asarray(gamma, dtype=np.float64)))
+    gstride = 0 if g.shape[0] == 1 and ncells != 1 else 1
+    if gstride == 1 and g.shape[0] != ncells:
+        raise ValueError("gamma must have 1 or ncells entries")
+    out = [rp, ci, n, nnz, vals, ncells, g, gstride]
+    if b is not None:
+        bb = np.ascontiguousarray(b, dtype=np.float64).reshape(ncells, n)
+        out.append(bb)
+    return out
+
+
+def solve_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, precond=0, kind=J_GAMMA,
+                residual_replacement=1, breakdown_restarts=1, nthreads=0):
+    rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
+    x = np.zeros((C, n))
+    iters = np.zeros(C, dtype=np.int32)
+    resid = np.zeros(C)
+    status = np.zeros(C, dtype=np.int32)
+    _load().oracle_solve_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, float(rtol), int(maxit), int(precond),
+                               int(residual_replacement), int(breakdown_restarts), x, iters, resid, status,
+                               int(nthreads))
+    return x, iters, resid, status
+
+
+def lu_batch(row_ptr, col_idx, values, gamma, b, kind=J_GAMMA, transpose=False, nthreads=0):
+    rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
+    x = np.zeros((C, n))
+    info = np.zeros(C, dtype=np.int32)
+    _load().oracle_lu_batch(C, n, nnz, rp, ci, vals, g, gs, kind, int(bool(transpose)), bb, x, info,
+                            int(nthreads))
+    return x, info
+
+
+def adjoint_batch(row_ptr, col_idx, values, gamma, x, g, rtol=1e-10, maxit=200, precond=0, kind=J_GAMMA,
+                  residual_replacement=1, breakdown_restarts=1, nthreads=0):
+    rp, ci, n, nnz, vals, C, gm, gs, gg = _prep(row_ptr, col_idx, values, gamma, g)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(C, n)
+    grad_b = np.zeros((C, n))
+    grad_A = np.zeros((C, nnz))
+    iters = np.zeros(C, dtype=np.int32)
+    resid = np.zeros(C)
+    status = np.zeros(C, dtype=np.int32)
+    _load().oracle_adjoint_batch(C, n, nnz, rp, ci, vals, gm, gs, kind, xx, gg, float(rtol), int(maxit),
+                                 int(precond), int(residual_replacement), int(breakdown_restarts), grad_b,
+                                 grad_A, iters, resid, status, int(nthreads))
+    return grad_b, grad_A, iters, resid, status
+
+
+def mixed_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, inner_rtol=1e-4, max_refine=10,
+                kind=J_GAMMA, nthreads=0):
+    rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
+    x = np.zeros((C, n))
+    iters = np.zeros(C, dtype=np.int32)
+    refin = np.zeros(C, dtype=np.int32)
+    resid = np.zeros(C)
+    status = np.zeros(C, dtype=np.int32)
+    _load().oracle_mixed_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, float(rtol), int(maxit),
+                               float(inner_rtol), int(max_refine), x, iters, refin, resid, status,
+                               int(nthreads))
+    return x, iters, refin, resid, status
+
+
+def form_a(row_ptr, col_idx, J, gamma):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    Jv = np.ascontiguousarray(J, dtype=np.float64)
+    A = np.zeros_like(Jv)
+    _load().oracle_form_a(rp.shape[0] - 1, rp, ci, Jv, float(gamma), A)
+    return A
+
+
+def lu_solve_dense(A, b):
+    """The oracle's own dense LU on one dense system (copies its inputs)."""
+    a = np.array(A, dtype=np.float64, order="C", copy=True)
+    x = np.array(b, dtype=np.float64, copy=True)
+    info = _load().oracle_lu_solve(a.shape[0], a, x)
+    return x, int(info)
+
+
+def to_dense(row_ptr, col_idx, vals):
+    """Scatter one cell's CSR values into an n x n array (test helper)."""
+    n = len(row_ptr) - 1
+    M = np.zeros((n, n))
+    for i in range(n):
+        for k in range(row_ptr[i], row_ptr[i + 1]):
+            M[i, col_idx[k]] = vals[k]
+    return M

@@ -1,0 +1,157 @@
+/* One BiCGStab solve of A x = b on a CSR matrix, written once and compiled for
+ * two element types by oracle.c (REAL = double for the FP64 oracle, REAL =
+ * float for the inner solve of the mixed-precision emulation).
+ *
+ * TEST INFRASTRUCTURE: part of the CPU oracle; nothing on the product path
+ * uses it.
+ *
+ * Method: BiCGStab of van der Vorst (1992), as given in the BiCGSTAB template
+ * of Barrett et al., "Templates for the Solution of Linear Systems" (SIAM
+ * 1994), with optional right Jacobi preconditioning M = diag(A).  The paper
+ * names its linear solver only as the BSC "Biconjugate Gradient" GPU solver
+ * (Section 3.1) and prints no algorithm, so the published BiCGStab is
+ * followed.  Readings taken where the paper is silent:
+ *   - initial guess x0 = 0 and shadow residual rhat = r0 = b;
+ *   - stop when ||s||/||b|| or ||r||/||b|| (2-norm, recurrence residual) is
+ *     <= rtol, then confirm on the true residual ||b - A x||/||b||;
+ *   - if the true residual misses rtol: residual replacement (r <- b - A x,
+ *     restart the recurrences) while iterations remain;
+ *   - breakdown = an exact zero rho, sigma, tau or omega: restart from the
+ *     true residual up to `brs` times, then stop with status BREAKDOWN;
+ *   - any non-finite scalar stops the cell with status NONFINITE;
+ *   - the iteration count counts loop entries (a half-step exit counts 1).
+ * Dot products and norms accumulate sequentially in index order.
+ */
+
+#ifndef REAL
+#error "define REAL before including bicgstab_body.h"
+#endif
+#ifndef SUFFIX
+#error "define SUFFIX before including bicgstab_body.h"
+#endif
+
+#define CAT2(a, b) a##b
+#define CAT(a, b) CAT2(a, b)
+#define FN(name) CAT(name, SUFFIX)
+
+static REAL FN(dot_)(int n, const REAL* a, const REAL* b) {
+  REAL s = 0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+static REAL FN(nrm2_)(int n, const REAL* a) { return (REAL)sqrt((double)FN(dot_)(n, a, a)); }
+
+/* y = A x on the CSR pattern (row order, column order within a row). */
+static void FN(spmv_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* xv, REAL* y) {
+  for (int i = 0; i < n; ++i) {
+    REAL acc = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) acc += A[k] * xv[ci[k]];
+    y[i] = acc;
+  }
+}
+
+/* Returns the iteration count.  w must hold 10*n elements. */
+static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, double rtol,
+                         int maxit, int precond, int rr, int brs, REAL* x, double* resid_out,
+                         int* status_out, REAL* w) {
+  REAL *r = w, *rh = w + n, *p = w + 2 * n, *v = w + 3 * n, *s = w + 4 * n;
+  REAL *t = w + 5 * n, *ph = w + 6 * n, *sh = w + 7 * n, *dinv = w + 8 * n, *rt = w + 9 * n;
+  for (int i = 0; i < n; ++i) x[i] = 0;
+  REAL bn = FN(nrm2_)(n, b);
+  if (!isfinite((double)bn)) {
+    *resid_out = NAN;
+    *status_out = OR_NONFINITE;
+    return 0;
+  }
+  if (bn == 0) {
+    *resid_out = 0.0;
+    *status_out = OR_CONVERGED;
+    return 0;
+  }
+  if (precond) {
+    for (int i = 0; i < n; ++i) {
+      REAL d = 0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d = A[k];
+      dinv[i] = (REAL)1 / d;
+    }
+  }
+  for (int i = 0; i < n; ++i) r[i] = b[i];
+
+  int it = 0, restarts_left = brs, ended = OR_MAXIT;
+  double res = 0.0;
+  for (;;) {
+    /* (re)start the recurrences from the current r */
+    for (int i = 0; i < n; ++i) rh[i] = r[i];
+    REAL rho_prev = 1, alpha = 1, omega = 1;
+    int first = 1;
+    ended = OR_MAXIT;
+    while (it < maxit) {
+      ++it;
+      REAL rho = FN(dot_)(n, rh, r);
+      if (!isfinite((double)rho)) { ended = OR_NONFINITE; break; }
+      if (rho == 0) { ended = OR_BREAKDOWN; break; }
+      if (first) {
+        for (int i = 0; i < n; ++i) p[i] = r[i];
+        first = 0;
+      } else {
+        REAL beta = (rho / rho_prev) * (alpha / omega);
+        for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      }
+      for (int i = 0; i < n; ++i) ph[i] = precond ? dinv[i] * p[i] : p[i];
+      FN(spmv_)(n, rp, ci, A, ph, v);
+      REAL sigma = FN(dot_)(n, rh, v);
+      if (!isfinite((double)sigma)) { ended = OR_NONFINITE; break; }
+      if (sigma == 0) { ended = OR_BREAKDOWN; break; }
+      alpha = rho / sigma;
+      for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+      REAL sn = FN(nrm2_)(n, s);
+      if (!isfinite((double)sn)) { ended = OR_NONFINITE; break; }
+      if ((double)sn / (double)bn <= rtol) {
+        for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
+        ended = OR_CONVERGED;
+        break;
+      }
+      for (int i = 0; i < n; ++i) sh[i] = precond ? dinv[i] * s[i] : s[i];
+      FN(spmv_)(n, rp, ci, A, sh, t);
+      REAL tau = FN(dot_)(n, t, t);
+      if (!isfinite((double)tau)) { ended = OR_NONFINITE; break; }
+      if (tau == 0) { ended = OR_BREAKDOWN; break; }
+      omega = FN(dot_)(n, t, s) / tau;
+      for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+      for (int i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+      REAL rn = FN(nrm2_)(n, r);
+      if (!isfinite((double)rn)) { ended = OR_NONFINITE; break; }
+      if ((double)rn / (double)bn <= rtol) { ended = OR_CONVERGED; break; }
+      if (omega == 0) { ended = OR_BREAKDOWN; break; }
+      rho_prev = rho;
+    }
+    /* true residual of the current iterate */
+    FN(spmv_)(n, rp, ci, A, x, rt);
+    for (int i = 0; i < n; ++i) rt[i] = b[i] - rt[i];
+    res = (double)FN(nrm2_)(n, rt) / (double)bn;
+    if (ended == OR_NONFINITE || !isfinite(res)) {
+      *resid_out = res;
+      *status_out = OR_NONFINITE;
+      return it;
+    }
+    if (res <= rtol) {
+      *resid_out = res;
+      *status_out = OR_CONVERGED;
+      return it;
+    }
+    if (it < maxit && ((ended == OR_CONVERGED && rr) || (ended == OR_BREAKDOWN && restarts_left > 0))) {
+      if (ended == OR_BREAKDOWN) --restarts_left;
+      for (int i = 0; i < n; ++i) r[i] = rt[i];
+      continue;
+    }
+    *resid_out = res;
+    *status_out = (ended == OR_BREAKDOWN) ? OR_BREAKDOWN : OR_MAXIT;
+    return it;
+  }
+}
+
+#undef FN
+#undef CAT
+#undef CAT2

@@ -1,0 +1,313 @@
+/* CPU oracle for the batched linear systems (I - gamma*J) x = b.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference that the
+ * HIP library is checked against; only tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code, header or table
+ * with the HIP library.  Build: gcc -O3 -ffp-contract=off -fopenmp -shared.
+ *
+ * What it computes (one independent system per grid cell, Sections 2.2 and
+ * 3.1: every cell has its own concentrations and Jacobian values on one shared
+ * sparsity pattern, and the BDF/Newton integrator needs one linear solve per
+ * step):
+ *   oracle_form_a      A = I - gamma*J on the pattern (the BDF Newton matrix)
+ *   oracle_solve_batch BiCGStab per cell (bicgstab_body.h), FP64
+ *   oracle_lu_batch    dense LU with partial pivoting per cell (ground truth)
+ *   oracle_adjoint_batch  lambda = A^-T g by BiCGStab on A^T, and the pattern
+ *                      gradient dL/dA_ij = -lambda_i x_j
+ *   oracle_mixed_batch FP32 inner BiCGStab + FP64 residual and refinement
+ * Readings of the paper taken here are listed in bicgstab_body.h and above
+ * each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_CONVERGED 0
+#define OR_MAXIT 1
+#define OR_BREAKDOWN 2
+#define OR_NONFINITE 3
+
+#define REAL double
+#define SUFFIX d
+#include "bicgstab_body.h"
+#undef REAL
+#undef SUFFIX
+
+#define REAL float
+#define SUFFIX f
+#include "bicgstab_body.h"
+#undef REAL
+#undef SUFFIX
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* A_k = delta_k - gamma * J_k, delta_k = 1 on diagonal positions, else 0.
+ * (Newton matrix of the BDF step, Section 2.2; gamma = h * beta_0 of the
+ * integrator, here given per cell.) */
+void oracle_form_a(int n, const int* rp, const int* ci, const double* J, double gamma, double* A) {
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) A[k] = (ci[k] == i ? 1.0 : 0.0) - gamma * J[k];
+}
+
+/* A of cell c: kind 0 = J mode (values are J, A = I - gamma*J), kind 1 = values are A. */
+static void cell_matrix(int n, int nnz, const int* rp, const int* ci, const double* values,
+                        const double* gamma, int64_t gamma_stride, int kind, int64_t c, double* A) {
+  const double* v = values + c * (int64_t)nnz;
+  if (kind == 1) {
+    memcpy(A, v, sizeof(double) * (size_t)nnz);
+  } else {
+    oracle_form_a(n, rp, ci, v, gamma[c * gamma_stride], A);
+  }
+}
+
+/* FP64 BiCGStab over a batch of cells (OpenMP over cells, static schedule). */
+void oracle_solve_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
+                        const double* gamma, int64_t gamma_stride, int kind, const double* b, double rtol,
+                        int maxit, int precond, int rr, int brs, double* x, int32_t* iters, double* resid,
+                        int32_t* status, int nthreads) {
+  set_threads(nthreads);
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * (size_t)nnz);
+    double* w = (double*)malloc(sizeof(double) * 10 * (size_t)n);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+      cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
+      int st = 0;
+      iters[c] = bicgstab_d(n, rp, ci, A, b + c * n, rtol, maxit, precond, rr, brs, x + c * n, &resid[c], &st, w);
+      status[c] = st;
+    }
+    free(A);
+    free(w);
+  }
+}
+
+/* Dense LU with partial pivoting (Doolittle; pivot = largest |a|, lowest row
+ * index on ties), then forward and back substitution.  a is n*n row-major
+ * and is overwritten; bx holds b on entry and x on return.  Returns 0, or
+ * k+1 if the k-th pivot is exactly zero. */
+int oracle_lu_solve(int n, double* a, double* bx) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = fabs(a[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double m = fabs(a[(size_t)i * n + k]);
+      if (m > best) { best = m; p = i; }
+    }
+    if (best == 0.0) return k + 1;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        double tmp = a[(size_t)k * n + j];
+        a[(size_t)k * n + j] = a[(size_t)p * n + j];
+        a[(size_t)p * n + j] = tmp;
+      }
+      double tb = bx[k]; bx[k] = bx[p]; bx[p] = tb;
+    }
+    double piv = a[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      double l = a[(size_t)i * n + k] / piv;
+      a[(size_t)i * n + k] = l;
+      for (int j = k + 1; j < n; ++j) a[(size_t)i * n + j] -= l * a[(size_t)k * n + j];
+      bx[i] -= l * bx[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = bx[i];
+    for (int j = i + 1; j < n; ++j) s -= a[(size_t)i * n + j] * bx[j];
+    bx[i] = s / a[(size_t)i * n + i];
+  }
+  return 0;
+}
+
+/* Dense LU solve per cell of A x = b (transpose = 0) or A^T x = b (transpose = 1).
+ * info[c] = oracle_lu_solve's return. */
+void oracle_lu_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
+                     const double* gamma, int64_t gamma_stride, int kind, int transpose, const double* b,
+                     double* x, int32_t* info, int nthreads) {
+  set_threads(nthreads);
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * (size_t)nnz);
+    double* D = (double*)malloc(sizeof(double) * (size_t)n * n);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+      cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
+      memset(D, 0, sizeof(double) * (size_t)n * n);
+      for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          if (transpose) D[(size_t)ci[k] * n + i] = A[k];
+          else D[(size_t)i * n + ci[k]] = A[k];
+        }
+      for (int i = 0; i < n; ++i) x[c * n + i] = b[c * n + i];
+      info[c] = oracle_lu_solve(n, D, x + c * n);
+    }
+    free(A);
+    free(D);
+  }
+}
+
+/* CSR of A^T from CSR of A: trp/tci describe the transposed pattern and
+ * perm[q] is the position in A of the q-th entry of A^T. */
+void oracle_transpose_pattern(int n, const int* rp, const int* ci, int* trp, int* tci, int* perm) {
+  int nnz = rp[n];
+  for (int j = 0; j <= n; ++j) trp[j] = 0;
+  for (int k = 0; k < nnz; ++k) trp[ci[k] + 1]++;
+  for (int j = 0; j < n; ++j) trp[j + 1] += trp[j];
+  int* fill = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  for (int j = 0; j < n; ++j) fill[j] = trp[j];
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int q = fill[ci[k]]++;
+      tci[q] = i;
+      perm[q] = k;
+    }
+  free(fill);
+}
+
+/* Adjoint of the solve with loss L(x): given x (the forward solution) and
+ * g = dL/dx, solve A^T lambda = g with the same BiCGStab, then
+ *   dL/db = lambda,  dL/dA_k = -lambda_i * x_j for pattern entry k = (i, j).
+ * (Differentiating A x = b: dx = A^-1 (db - dA x), so dL = lambda^T db -
+ * lambda^T dA x.) */
+void oracle_adjoint_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
+                          const double* gamma, int64_t gamma_stride, int kind, const double* x, const double* g,
+                          double rtol, int maxit, int precond, int rr, int brs, double* grad_b, double* grad_A,
+                          int32_t* iters, double* resid, int32_t* status, int nthreads) {
+  int* trp = (int*)malloc(sizeof(int) * (size_t)(n + 1));
+  int* tci = (int*)malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+  int* perm = (int*)malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+  oracle_transpose_pattern(n, rp, ci, trp, tci, perm);
+  set_threads(nthreads);
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * (size_t)nnz);
+    double* AT = (double*)malloc(sizeof(double) * (size_t)nnz);
+    double* w = (double*)malloc(sizeof(double) * 10 * (size_t)n);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+      cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
+      for (int q = 0; q < nnz; ++q) AT[q] = A[perm[q]];
+      int st = 0;
+      double* lam = grad_b + c * n;
+      iters[c] = bicgstab_d(n, trp, tci, AT, g + c * n, rtol, maxit, precond, rr, brs, lam, &resid[c], &st, w);
+      status[c] = st;
+      const double* xc = x + c * n;
+      for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) grad_A[c * nnz + k] = -lam[i] * xc[ci[k]];
+    }
+    free(A);
+    free(AT);
+    free(w);
+  }
+  free(trp);
+  free(tci);
+  free(perm);
+}
+
+/* Mixed precision: FP32 inner BiCGStab inside FP64 iterative refinement.
+ *   D = diag(A) (FP64); Ahat = A D^-1 (FP64 division, then rounded to float);
+ *   x = 0, r = b;
+ *   repeat up to max_refine times while ||r||/||b|| > rtol:
+ *     rhat32 = float(r / ||r||);
+ *     solve Ahat d = rhat32 in FP32 to inner_rtol (no residual replacement);
+ *     x_new = x + ||r|| * D^-1 * d (FP64); r_new = b - A x_new (FP64);
+ *     if ||r_new|| >= ||r||: stop (refinement stagnates; x is kept).
+ * iters = sum of inner iterations, refinements = inner solves performed.
+ * Status: CONVERGED if the final FP64 relative residual <= rtol, NONFINITE on
+ * non-finite values, otherwise MAXIT. */
+void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
+                        const double* gamma, int64_t gamma_stride, int kind, const double* b, double rtol,
+                        int maxit, double inner_rtol, int max_refine, double* x, int32_t* iters,
+                        int32_t* refinements, double* resid, int32_t* status, int nthreads) {
+  set_threads(nthreads);
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * (size_t)nnz);
+    float* A32 = (float*)malloc(sizeof(float) * (size_t)nnz);
+    double* dg = (double*)malloc(sizeof(double) * (size_t)n);
+    double* r = (double*)malloc(sizeof(double) * (size_t)n);
+    double* xn = (double*)malloc(sizeof(double) * (size_t)n);
+    double* rn_v = (double*)malloc(sizeof(double) * (size_t)n);
+    float* r32 = (float*)malloc(sizeof(float) * (size_t)n);
+    float* d32 = (float*)malloc(sizeof(float) * (size_t)n);
+    float* w32 = (float*)malloc(sizeof(float) * 10 * (size_t)n);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < ncells; ++c) {
+      cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
+      const double* bc = b + c * n;
+      double* xc = x + c * n;
+      int tot = 0, nref = 0, st = OR_MAXIT;
+      for (int i = 0; i < n; ++i) xc[i] = 0.0;
+      double bn = 0.0;
+      for (int i = 0; i < n; ++i) bn += bc[i] * bc[i];
+      bn = sqrt(bn);
+      double res;
+      if (!isfinite(bn)) {
+        res = NAN;
+        st = OR_NONFINITE;
+      } else if (bn == 0.0) {
+        res = 0.0;
+        st = OR_CONVERGED;
+      } else {
+        for (int i = 0; i < n; ++i) {
+          double d = 0.0;
+          for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) d = A[k];
+          dg[i] = d;
+        }
+        for (int i = 0; i < n; ++i)
+          for (int k = rp[i]; k < rp[i + 1]; ++k) A32[k] = (float)(A[k] / dg[ci[k]]);
+        for (int i = 0; i < n; ++i) r[i] = bc[i];
+        double rn = bn;
+        while (1) {
+          if (!isfinite(rn)) { st = OR_NONFINITE; break; }
+          if (rn / bn <= rtol) { st = OR_CONVERGED; break; }
+          if (nref >= max_refine) { st = OR_MAXIT; break; }
+          for (int i = 0; i < n; ++i) r32[i] = (float)(r[i] / rn);
+          double ires;
+          int ist;
+          tot += bicgstab_f(n, rp, ci, A32, r32, inner_rtol, maxit, 0, 0, 1, d32, &ires, &ist, w32);
+          ++nref;
+          if (ist == OR_NONFINITE) { st = OR_NONFINITE; break; }
+          for (int i = 0; i < n; ++i) xn[i] = xc[i] + rn * ((double)d32[i] / dg[i]);
+          for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) acc += A[k] * xn[ci[k]];
+            rn_v[i] = bc[i] - acc;
+          }
+          double rnn = 0.0;
+          for (int i = 0; i < n; ++i) rnn += rn_v[i] * rn_v[i];
+          rnn = sqrt(rnn);
+          if (!(rnn < rn)) { st = isfinite(rnn) ? OR_MAXIT : OR_NONFINITE; break; }
+          for (int i = 0; i < n; ++i) { xc[i] = xn[i]; r[i] = rn_v[i]; }
+          rn = rnn;
+        }
+        res = rn / bn;
+        if (st == OR_NONFINITE) res = NAN;
+      }
+      iters[c] = tot;
+      refinements[c] = nref;
+      resid[c] = res;
+      status[c] = st;
+    }
+    free(A); free(A32); free(dg); free(r); free(xn); free(rn_v); free(r32); free(d32); free(w32);
+  }
+}

@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* dense LU against LAPACK (numpy.linalg.solve) and Cramer's rule;
+* BiCGStab against dense LU on tiny random systems (kappa-scaled tolerance);
+* finite termination: on a matrix whose minimal polynomial has degree k,
+  BiCGStab (like the BiCG it is built on) terminates within k iterations --
+  any dropped term, wrong sign or transposed operand in the recurrences
+  destroys this;
+* closed forms: gamma = 0 gives x = b in one half-step; a diagonal A with
+  Jacobi gives x_i = b_i / A_ii in one half-step;
+* the classic exact breakdown ([[0,1],[-1,0]], b = e_1);
+* forced failures (NaN, maxit = 1, b = 0, singular cells);
+* the mass-action conservation invariant 1^T A = 1^T on solutions;
+* adjoint: LU of A^T, duality g^T x = lambda^T b, central finite differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import BREAKDOWN, CONVERGED, MAXIT, NONFINITE, A_DIRECT, J_GAMMA
+from workload import config_inputs
+
+RNG = np.random.default_rng(20240527)
+
+
+def dense_to_csr(M):
+    n = M.shape[0]
+    rp = [0]
+    ci = []
+    vals = []
+    for i in range(n):
+        for j in range(n):
+            if M[i, j] != 0.0 or i == j:
+                ci.append(j)
+                vals.append(M[i, j])
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32), np.array(vals)
+
+
+def random_sparse(n, density, rng):
+    M = np.where(rng.uniform(size=(n, n)) < density, rng.standard_normal((n, n)), 0.0)
+    M[np.arange(n), np.arange(n)] = rng.uniform(1.0, 3.0, n) * rng.choice([-1, 1], n)
+    return M
+
+
+# ---------------------------------------------------------------- dense LU ---
+
+def test_lu_matches_lapack():
+    for n in range(1, 13):
+        for _ in range(20):
+            A = RNG.standard_normal((n, n))
+            b = RNG.standard_normal(n)
+            x, info = oracle.lu_solve_dense(A, b)
+            assert info == 0
+            xr = np.linalg.solve(A, b)
+            assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.cond(A) * np.linalg.norm(xr)
+
+
+def test_lu_matches_cramer_rule():
+    def det2(M):
+        return M[0, 0] * M[1, 1] - M[0, 1] * M[1, 0]
+
+    def det3(M):
+        return (M[0, 0] * (M[1, 1] * M[2, 2] - M[1, 2] * M[2, 1])
+                - M[0, 1] * (M[1, 0] * M[2, 2] - M[1, 2] * M[2, 0])
+                + M[0, 2] * (M[1, 0] * M[2, 1] - M[1, 1] * M[2, 0]))
+
+    for n, det in ((2, det2), (3, det3)):
+        for _ in range(50):
+            A = RNG.standard_normal((n, n))
+            b = RNG.standard_normal(n)
+            x, _ = oracle.lu_solve_dense(A, b)
+            d = det(A)
+            for j in range(n):
+                Aj = A.copy()
+                Aj[:, j] = b
+                assert abs(x[j] - det(Aj) / d) <= 1e-9 * (1 + abs(x[j])) * np.linalg.cond(A)
+
+
+def test_lu_pivots_on_zero_leading_entry_and_flags_singular():
+    A = np.array([[0.0, 2.0], [3.0, 1.0]])
+    x, info = oracle.lu_solve_dense(A, np.array([2.0, 4.0]))
+    assert info == 0 and np.allclose(x, [1.0, 1.0], rtol=0, atol=1e-15)
+    _, info = oracle.lu_solve_dense(np.array([[1.0, 2.0], [2.0, 4.0]]), np.array([1.0, 1.0]))
+    assert info == 2
+
+
+def test_lu_batch_transpose_solves_transposed_system():
+    M = random_sparse(7, 0.4, RNG)
+    rp, ci, vals = dense_to_csr(M)
+    b = RNG.standard_normal(7)
+    x, info = oracle.lu_batch(rp, ci, vals[None], [0.0], b[None], kind=A_DIRECT, transpose=True)
+    assert info[0] == 0
+    assert np.allclose(x[0], np.linalg.solve(M.T, b), rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------- BiCGStab vs dense LU --
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_bicgstab_matches_lu_on_tiny_random_systems(precond):
+    checked = 0
+    for trial in range(2000):
+        n = int(RNG.integers(1, 9))
+        M = random_sparse(n, 0.5, RNG)
+        kappa = np.linalg.cond(M)
+        if kappa > 1e6:
+            continue
+        rp, ci, vals = dense_to_csr(M)
+        b = RNG.standard_normal(n)
+        x, it, res, st = oracle.solve_batch(rp, ci, vals[None], [0.0], b[None], rtol=1e-12, maxit=400,
+                                            precond=precond, kind=A_DIRECT)
+        xr = np.linalg.solve(M, b)
+        if st[0] == BREAKDOWN:
+            continue  # an exact breakdown is a legitimate outcome; covered separately
+        assert st[0] == CONVERGED, (trial, it, res)
+        assert res[0] <= 1e-12
+        assert np.linalg.norm(x[0] - xr) <= 4 * kappa * max(res[0], 1e-15) * np.linalg.norm(xr) + 1e-14
+        checked += 1
+    assert checked > 1500
+
+
+def test_returned_residual_is_the_true_residual():
+    mech, cells = config_inputs(1)[0]
+    x, it, res, st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"],
+                                        precond=1)
+    for c in range(0, 100, 7):
+        A = oracle.to_dense(mech.row_ptr, mech.col_idx,
+                            oracle.form_a(mech.row_ptr, mech.col_idx, cells["values"][c], cells["gamma"][c]))
+        r = cells["b"][c] - A @ x[c]
+        rel = np.linalg.norm(r) / np.linalg.norm(cells["b"][c])
+        assert abs(rel - res[c]) <= 1e-3 * rel + 1e-15
+
+
+# --------------------------------------------------------- finite termination
+
+def _eig_construct(eigs, n, rng, symmetric):
+    d = np.array([eigs[i % len(eigs)] for i in range(n)])
+    if symmetric:
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        return Q @ np.diag(d) @ Q.T
+    Q = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    return Q @ np.diag(d) @ np.linalg.inv(Q)
+
+
+@pytest.mark.parametrize("k,symmetric", [(1, True), (2, True), (3, True), (4, True), (5, True),
+                                         (1, False), (2, False), (3, False)])
+def test_finite_termination_within_degree_of_minimal_polynomial(k, symmetric):
+    # For SPD A and rhat = r0, BiCG reproduces CG, so its residual polynomial
+    # vanishes after k steps when A has k distinct eigenvalues; BiCGStab's
+    # half-step residual s_k contains that factor and is zero too.  For
+    # non-normal A the same holds in exact arithmetic; with rounding it stays
+    # reliable for k <= 3 on these eigenvector matrices.
+    eigs = [1.0, 2.5, 4.0, 6.0, 9.0][:k]
+    for trial in range(40):
+        n = 12
+        M = _eig_construct(eigs, n, RNG, symmetric)
+        rp, ci, vals = dense_to_csr(M)
+        b = RNG.standard_normal(n)
+        x, it, res, st = oracle.solve_batch(rp, ci, vals[None], [0.0], b[None], rtol=1e-9, maxit=50,
+                                            kind=A_DIRECT)
+        assert st[0] == CONVERGED
+        assert it[0] <= k, (k, it[0])
+
+
+def test_rank_one_update_converges_in_two_iterations():
+    n = 40
+    for _ in range(20):
+        u = RNG.standard_normal(n)
+        v = RNG.standard_normal(n)
+        M = np.eye(n) + np.outer(u, v) / n
+        if abs(1 + v @ u / n) < 0.1:
+            continue
+        rp, ci, vals = dense_to_csr(M)
+        b = RNG.standard_normal(n)
+        x, it, res, st = oracle.solve_batch(rp, ci, vals[None], [0.0], b[None], rtol=1e-10, kind=A_DIRECT)
+        assert st[0] == CONVERGED and it[0] <= 2
+        assert np.allclose(x[0], np.linalg.solve(M, b), rtol=1e-8, atol=1e-10)
+
+
+# ------------------------------------------------------------- closed forms --
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_gamma_zero_gives_b_in_one_half_step(precond):
+    mech, cells = config_inputs(1, ncells=5)[0]
+    x, it, res, st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], np.zeros(5), cells["b"],
+                                        precond=precond)
+    assert np.all(st == CONVERGED) and np.all(it == 1)
+    assert np.array_equal(x, cells["b"])
+    assert np.all(res == 0.0)
+
+
+def test_diagonal_with_jacobi_is_exact_in_one_step():
+    n = 17
+    d = RNG.uniform(1.0, 1e4, n)
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    b = RNG.standard_normal(n)
+    x, it, res, st = oracle.solve_batch(rp, ci, d[None], [0.0], b[None], precond=1, kind=A_DIRECT)
+    assert st[0] == CONVERGED and it[0] == 1
+    assert np.allclose(x[0], b / d, rtol=4e-16, atol=0)
+
+
+def test_two_species_isomerisation_closed_form():
+    # A <-> B with rates k1 (A->B) and k2 (B->A): J = [[-k1, k2], [k1, -k2]].
+    k1, k2, g = 3.0, 0.5, 0.7
+    J = np.array([-k1, k2, k1, -k2])
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    b = np.array([1.0, 2.0])
+    x, it, res, st = oracle.solve_batch(rp, ci, J[None], [g], b[None], rtol=1e-14)
+    # (I - gJ) x = b solved by hand: det = 1 + g (k1 + k2)
+    det = 1 + g * (k1 + k2)
+    x0 = ((1 + g * k2) * b[0] + g * k2 * b[1]) / det
+    x1 = (g * k1 * b[0] + (1 + g * k1) * b[1]) / det
+    assert st[0] == CONVERGED
+    assert np.allclose(x[0], [x0, x1], rtol=1e-13, atol=0)
+    assert abs(x[0].sum() - b.sum()) <= 1e-13  # molecule conservation
+
+
+# ------------------------------------------------- breakdown and failures ----
+
+def test_exact_breakdown_of_rotation_matrix():
+    A = np.array([0.0, 1.0, -1.0, 0.0])
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    b = np.array([1.0, 0.0])
+    x, it, res, st = oracle.solve_batch(rp, ci, A[None], [0.0], b[None], kind=A_DIRECT)
+    assert st[0] == BREAKDOWN and it[0] == 2 and np.all(x[0] == 0) and res[0] == 1.0
+    # the same system in J mode: A = I - gamma J with gamma = 1, J = I - A
+    J = np.array([1.0, -1.0, 1.0, 1.0])
+    x2, it2, res2, st2 = oracle.solve_batch(rp, ci, J[None], [1.0], b[None])
+    assert st2[0] == BREAKDOWN and it2[0] == 2
+    # no restarts allowed: breakdown after one iteration
+    _, it3, _, st3 = oracle.solve_batch(rp, ci, A[None], [0.0], b[None], kind=A_DIRECT, breakdown_restarts=0)
+    assert st3[0] == BREAKDOWN and it3[0] == 1
+
+
+def test_nan_cell_is_isolated():
+    mech, cells = config_inputs(1, ncells=6)[0]
+    vals = cells["values"].copy()
+    vals[3, 5] = np.nan
+    args = (mech.row_ptr, mech.col_idx)
+    x, it, res, st = oracle.solve_batch(*args, vals, cells["gamma"], cells["b"], precond=1)
+    x0, it0, res0, st0 = oracle.solve_batch(*args, cells["values"], cells["gamma"], cells["b"], precond=1)
+    assert st[3] == NONFINITE
+    keep = [0, 1, 2, 4, 5]
+    assert np.array_equal(x[keep], x0[keep]) and np.array_equal(it[keep], it0[keep])
+    b = cells["b"].copy()
+    b[2, 0] = np.inf
+    _, _, _, st2 = oracle.solve_batch(*args, cells["values"], cells["gamma"], b, precond=1)
+    assert st2[2] == NONFINITE
+
+
+def test_maxit_one_and_zero_rhs():
+    mech, cells = config_inputs(1, ncells=4)[0]
+    b = cells["b"].copy()
+    b[1] = 0.0
+    x, it, res, st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], b,
+                                        maxit=1, precond=1)
+    assert st[1] == CONVERGED and it[1] == 0 and res[1] == 0.0 and np.all(x[1] == 0.0)
+    hard = [c for c in (0, 2, 3) if st[c] != CONVERGED]
+    assert hard and all(st[c] == MAXIT and it[c] == 1 for c in hard)
+
+
+def test_singular_diagonal_cell():
+    n, g = 4, 0.5
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    J = np.full(n, 1.0 / g)  # A = I - g J = 0
+    b = np.ones(n)
+    _, _, _, st = oracle.solve_batch(rp, ci, J[None], [g], b[None], precond=0)
+    assert st[0] == BREAKDOWN
+    _, _, _, st = oracle.solve_batch(rp, ci, J[None], [g], b[None], precond=1)
+    assert st[0] == NONFINITE
+
+
+# ----------------------------------------------- mass-action workloads -------
+
+@pytest.mark.parametrize("cfg", [1, 4])
+def test_mass_action_cells_match_lu_and_conserve(cfg):
+    for mech, cells in config_inputs(cfg, ncells=120):
+        rp, ci = mech.row_ptr, mech.col_idx
+        x, it, res, st = oracle.solve_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], precond=1)
+        xl, info = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+        assert np.all(info == 0)
+        assert np.mean(st == CONVERGED) >= 0.99
+        for c in np.nonzero(st == CONVERGED)[0]:
+            A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+            kappa = np.linalg.cond(A)
+            rlu = np.linalg.norm(cells["b"][c] - A @ xl[c]) / np.linalg.norm(cells["b"][c])
+            err = np.linalg.norm(x[c] - xl[c]) / np.linalg.norm(xl[c])
+            assert err <= max(1e-8, 4 * kappa * max(res[c], rlu))
+            # 1^T A = 1^T  =>  sum(x) - sum(b) = -sum(b - A x)
+            bn = np.linalg.norm(cells["b"][c])
+            slack = np.sqrt(mech.n) * res[c] * bn + 1e3 * np.finfo(float).eps * (np.abs(A) @ np.abs(x[c])).sum()
+            assert abs(x[c].sum() - cells["b"][c].sum()) <= slack
+
+
+def test_ideal_cells_give_identical_results():
+    mech, cells = config_inputs(1, ncells=16, mode="ideal")[0]
+    x, it, res, st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"],
+                                        precond=1)
+    assert np.all(x == x[0]) and np.all(it == it[0]) and np.all(res == res[0])
+
+
+def test_permuting_cells_permutes_results_bitwise():
+    mech, cells = config_inputs(1, ncells=10)[0]
+    perm = RNG.permutation(10)
+    a = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], precond=1)
+    b = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][perm], cells["gamma"][perm],
+                           cells["b"][perm], precond=1)
+    for u, v in zip(a, b):
+        assert np.array_equal(u[perm], v)
+
+
+# ------------------------------------------------------------------ adjoint --
+
+def _loss_lu(rp, ci, vals, gamma, b, w):
+    x, info = oracle.lu_batch(rp, ci, vals[None], [gamma], b[None])
+    return float(w @ x[0])
+
+
+def test_adjoint_matches_transposed_lu_and_duality():
+    mech, cells = config_inputs(5, ncells=40)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    x, _, _, st = oracle.solve_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], precond=1)
+    w = cells["w"]
+    gb, gA, it, res, sta = oracle.adjoint_batch(rp, ci, cells["values"], cells["gamma"], x, w, precond=1)
+    lam_lu, info = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], w, transpose=True)
+    for c in range(40):
+        if sta[c] != CONVERGED or st[c] != CONVERGED:
+            continue
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        kappa = np.linalg.cond(A)
+        err = np.linalg.norm(gb[c] - lam_lu[c]) / np.linalg.norm(lam_lu[c])
+        assert err <= max(1e-8, 4 * kappa * res[c] + 1e-12 * kappa)
+        # duality: w^T x = lambda^T b (both equal w^T A^-1 b)
+        lhs, rhs = w[c] @ x[c], gb[c] @ cells["b"][c]
+        scale = np.linalg.norm(w[c]) * np.linalg.norm(x[c]) + np.linalg.norm(gb[c]) * np.linalg.norm(cells["b"][c])
+        assert abs(lhs - rhs) <= 1e-8 * scale
+        # pattern gradient is -lambda_i x_j
+        for i in range(0, mech.n, 13):
+            for k in range(rp[i], rp[i + 1]):
+                assert gA[c, k] == -gb[c, i] * x[c, ci[k]]
+
+
+def test_adjoint_matches_central_finite_differences():
+    mech, cells = config_inputs(5, ncells=12)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    rng = np.random.Generator(np.random.PCG64(5))
+    for c in rng.choice(12, size=4, replace=False):
+        vals, g, b, w = cells["values"][c], cells["gamma"][c], cells["b"][c], cells["w"][c]
+        A = oracle.form_a(rp, ci, vals, g)
+        x, _ = oracle.lu_batch(rp, ci, A[None], [0.0], b[None], kind=A_DIRECT)
+        gb, gA, it, res, st = oracle.adjoint_batch(rp, ci, A[None], [0.0], x, w[None], rtol=1e-12, precond=1,
+                                                   kind=A_DIRECT)
+        amax = np.abs(gA[0]).max()
+
+        def L(Av, bv):
+            xx, _ = oracle.lu_batch(rp, ci, Av[None], [0.0], bv[None], kind=A_DIRECT)
+            return float(w @ xx[0])
+
+        L0 = abs(L(A, b))
+        # a relative step 1e-6*|A_k| moves L by about 1e-6*|A_k*dL/dA_k|; keep
+        # entries where that is far above the rounding of L (about 1e-16*|L|)
+        resolvable = np.nonzero(1e-6 * np.abs(A * gA[0]) > 1e-8 * L0)[0]
+        assert resolvable.size >= 12
+        for k in rng.choice(resolvable, size=12, replace=False):
+            eps = 1e-6 * abs(A[k])
+            Ap, Am = A.copy(), A.copy()
+            Ap[k] += eps
+            Am[k] -= eps
+            fd = (L(Ap, b) - L(Am, b)) / (2 * eps)
+            assert abs(fd - gA[0, k]) <= 1e-5 * max(abs(gA[0, k]), 1e-3 * amax), (k, fd, gA[0, k])
+        for i in rng.choice(mech.n, size=6, replace=False):
+            e = np.zeros(mech.n)
+            e[i] = 1e-6
+            fd = (L(A, b + e) - L(A, b - e)) / 2e-6
+            assert abs(fd - gb[0, i]) <= 1e-5 * max(abs(gb[0, i]), 1e-3 * np.abs(gb[0]).max())
+
+
+# -------------------------------------------------------------- mixed form ---
+
+def test_mixed_reaches_fp64_residual_on_well_conditioned_cells():
+    mech, cells = config_inputs(1)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    xm, itm, ref, res, st = oracle.mixed_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    ok = st == CONVERGED
+    assert ok.mean() >= 0.9
+    assert np.all(res[ok] <= 1e-10)
+    assert np.all(ref[ok] >= 2)  # FP32 alone cannot reach 1e-10
+    for c in np.nonzero(ok)[0]:
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        kappa = np.linalg.cond(A)
+        err = np.linalg.norm(xm[c] - xl[c]) / np.linalg.norm(xl[c])
+        assert err <= max(1e-8, 4 * kappa * 1e-10)
+
+
+def test_mixed_refinement_count_on_rank_one_update():
+    # eigenvalues {1, 1 + v.u/n}: each FP32 inner solve is exact to FP32
+    # rounding, so every refinement gains about 7 digits: 1e-10 needs <= 3.
+    n = 30
+    u = RNG.standard_normal(n)
+    v = np.abs(RNG.standard_normal(n))
+    M = np.eye(n) + np.outer(np.abs(u), v) / n
+    rp, ci, vals = dense_to_csr(M)
+    b = RNG.standard_normal(n)
+    x, it, ref, res, st = oracle.mixed_batch(rp, ci, vals[None], [0.0], b[None], kind=A_DIRECT)
+    assert st[0] == CONVERGED and 2 <= ref[0] <= 3 and res[0] <= 1e-10
+    assert np.allclose(x[0], np.linalg.solve(M, b), rtol=1e-9, atol=1e-12)
+
+
+def test_mixed_zero_rhs_and_nan():
+    mech, cells = config_inputs(1, ncells=3)[0]
+    b = cells["b"].copy()
+    b[0] = 0
+    vals = cells["values"].copy()
+    vals[2, 0] = np.nan
+    x, it, ref, res, st = oracle.mixed_batch(mech.row_ptr, mech.col_idx, vals, cells["gamma"], b)
+    assert st[0] == CONVERGED and ref[0] == 0 and np.all(x[0] == 0)
+    assert st[2] == NONFINITE
