@@ -1,0 +1,223 @@
+"""Benchmark: cell-systems solved per second at relative residual 1e-10.
+
+Workload: 100,000 cells of the synthetic n = 80 mass-action mechanism (150
+reactions), h log-uniform in [1e-3, 100] s (gamma = h/2), b ~ N(0, 1), Jacobi
+right preconditioning, rtol 1e-10, maxit 200.  A step is one batched FP64
+Block-cells BiCGStab solve of all cells (stage A = I - gamma J, iterate,
+confirm the true residual, write x / iterations / residuals / statuses), with
+every input already resident in device memory.  The FP32-inner /
+FP64-refinement form is timed on the same inputs and reported beside it.
+
+Prints ONE JSON line.  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "cell-systems solved/s at rel. residual 1e-10, 100k cells (FP64 vs FP32+refine)"
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
+FP64_VALU_PEAK = 78.6     # MI355X FP64 vector, TFLOP/s
+RTOL = 1e-10
+MAXIT = 200
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ncells", type=int, default=100_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")
+    ap.add_argument("--lanes", type=int, default=0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_cell(n: int, nnz: int) -> int:
+    # read J values, b, gamma; write x, resid, iters, status (A stays on chip)
+    return 8 * nnz + 8 * n + 8 + 8 * n + 8 + 4 + 4
+
+
+def flops_per_cell(n: int, nnz: int, iters: np.ndarray, status: np.ndarray) -> float:
+    # per full iteration: 2 SpMV (2*nnz FMA each) + 6 dots/norms + 4 vector
+    # updates = 4 nnz + 24 n; staging (form A, column scaling, ||b||) and the
+    # true-residual check = about 3 nnz + 7 n + (2 nnz + 3 n) per confirmation
+    it = iters.astype(np.float64)
+    return float(np.sum(it * (4 * nnz + 24 * n) + (5 * nnz + 10 * n)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2405_17363_amd as bcs
+    from workload import config_inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    mech, cells = config_inputs(3, ncells=None if args.ncells == 100_000 else args.ncells)[0]
+    C, n, nnz = cells["b"].shape[0], mech.n, mech.nnz
+    print(f"# generated {C} cells n={n} nnz={nnz} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    values = torch.as_tensor(cells["values"], device=dev)
+    gamma = torch.as_tensor(cells["gamma"], device=dev)
+    b = torch.as_tensor(cells["b"], device=dev)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", lanes_per_cell=args.lanes)
+    out = [torch.empty((C, n), dtype=torch.float64, device=dev), torch.empty(C, dtype=torch.int32, device=dev),
+           torch.empty(C, dtype=torch.float64, device=dev), torch.empty(C, dtype=torch.int32, device=dev),
+           torch.empty(C, dtype=torch.int32, device=dev)]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bcs.solve_batch(plan, values, gamma, b, RTOL, MAXIT, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # per-launch durations with events on the launch stream
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kern_ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    ms_per_step = 1e3 * wall / args.steps
+    x, iters, resid, status, _ = [t.cpu().numpy() for t in out]
+    solved = int(np.sum((status == 0) & (resid <= RTOL)))
+    value = solved / (ms_per_step * 1e-3)
+    avg_launch_s = float(np.mean(kern_ms)) * 1e-3
+    bytes_launch = algorithmic_bytes_per_cell(n, nnz) * C
+    flops_launch = flops_per_cell(n, nnz, iters, status)
+    hbm_gbs = bytes_launch / avg_launch_s / 1e9
+    valu_tfs = flops_launch / avg_launch_s / 1e12
+    info = plan.info()
+
+    traffic = None
+    tr_path = os.path.join(HERE, "profiles", "traffic_fp64_solve_100k.json")
+    if os.path.exists(tr_path):
+        with open(tr_path) as f:
+            tr = json.load(f)
+        if tr.get("plan") == info and tr.get("ncells") == C:
+            traffic = tr.get("hbm_bytes_per_launch")
+
+    fracs = {"hbm": hbm_gbs / HBM_PEAK_GBS, "alu": valu_tfs / FP64_VALU_PEAK}
+    bound = max(fracs, key=fracs.get)
+    roofline = {
+        "bound": bound,
+        "achieved": round(hbm_gbs if bound == "hbm" else valu_tfs, 3),
+        "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_VALU_PEAK,
+        "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+        "frac": round(fracs[bound], 4),
+        "traffic": traffic,
+        "kernel": "k_fp64<%d,%d,%d>" % (info["lanes_per_cell"], info["rows_per_lane"], info["steps_per_lane"]),
+        "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+        "hbm_gbs": round(hbm_gbs, 2),
+        "hbm_frac": round(fracs["hbm"], 4),
+        "fp64_tflops": round(valu_tfs, 3),
+        "fp64_frac": round(fracs["alu"], 4),
+        "algorithmic_bytes_per_launch": bytes_launch,
+        "algorithmic_flops_per_launch": flops_launch,
+    }
+
+    mixed = None
+    if not args.no_mixed:
+        try:
+            mplan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", precision="fp32_refine",
+                             lanes_per_cell=args.lanes)
+            mout = [torch.empty_like(o) for o in out]
+
+            def mstep():
+                bcs.solve_batch(mplan, values, gamma, b, RTOL, MAXIT, out=mout)
+
+            for _ in range(args.warmup):
+                mstep()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                mstep()
+            torch.cuda.synchronize()
+            mms = 1e3 * (time.perf_counter() - t1) / args.steps
+            mx, mit, mres, mst, mref = [t.cpu().numpy() for t in mout]
+            msolved = int(np.sum((mst == 0) & (mres <= RTOL)))
+            both = (mst == 0) & (status == 0)
+            err = np.linalg.norm(mx[both] - x[both], axis=1) / np.linalg.norm(x[both], axis=1)
+            mixed = {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4),
+                     "solved_fraction": round(msolved / C, 5), "iters_mean": round(float(mit.mean()), 2),
+                     "refinements_mean": round(float(mref.mean()), 3),
+                     "rel_diff_vs_fp64_max": float(err.max()) if err.size else None,
+                     "rel_diff_vs_fp64_p99": float(np.percentile(err, 99)) if err.size else None}
+        except bcs.BcsError as e:
+            mixed = {"error": str(e)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        # pilot on 2000 cells, then a sample sized for about 10 s of CPU work
+        S0 = min(2000, C)
+        t1 = time.perf_counter()
+        oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][:S0], cells["gamma"][:S0],
+                           cells["b"][:S0], RTOL, MAXIT, precond=1, nthreads=nthreads)
+        pilot = time.perf_counter() - t1
+        S = int(min(C, max(S0, S0 * 10.0 / max(pilot, 1e-6))))
+        times = []
+        for _ in range(3 if S * pilot / S0 < 5 else 1):
+            t1 = time.perf_counter()
+            _, ci_it, ci_res, ci_st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][:S],
+                                                         cells["gamma"][:S], cells["b"][:S], RTOL, MAXIT,
+                                                         precond=1, nthreads=nthreads)
+            times.append(time.perf_counter() - t1)
+        tcpu = float(np.median(times))
+        csolved = int(np.sum((ci_st == 0) & (ci_res <= RTOL)))
+        cpu = {"value": round(csolved / tcpu, 1), "unit": "cells/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"first {S} of the {C} cells, FP64 BiCGStab + Jacobi, OpenMP static over cells, "
+                         f"median of {len(times)} runs ({tcpu:.2f} s)"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "100k cells, n=80 mass-action mechanism (150 reactions), h in [1e-3,100] s, "
+                               "A = I - gamma J, Jacobi, rtol 1e-10, maxit 200",
+                   "ncells": C, "n": n, "nnz": nnz, "precision": "fp64", "plan": info},
+        "solved_fraction": round(solved / C, 5),
+        "iters_mean": round(float(iters.mean()), 2),
+        "iters_p99": float(np.percentile(iters, 99)),
+        "iters_max": int(iters.max()),
+        "status_counts": np.bincount(status, minlength=4).tolist(),
+        "roofline": roofline,
+        "fp32_refine": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

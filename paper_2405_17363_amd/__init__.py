@@ -1,0 +1,33 @@
+"""Batched Block-cells BiCGStab for (I - gamma*J) x = b on AMD gfx950.
+
+Thin Python binding over the C-ABI library ``libbcs.so`` (include/bcs.h).
+Every step of a solve runs in the library's HIP kernels; this module only
+marshals torch tensors (device memory) and the current HIP stream.  There is
+no fallback: if the library is missing or fails to load, the import of the
+entry points raises.
+
+    plan = Plan(row_ptr, col_idx, precond="jacobi")          # shared pattern
+    x, iters, resid, status = solve_batch(plan, J, gamma, b)  # per-cell values
+    x = BatchedSolve.apply(J, gamma, b, plan)                 # differentiable
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    BCS_A_DIRECT,
+    BCS_BREAKDOWN,
+    BCS_CONVERGED,
+    BCS_FP32_REFINE,
+    BCS_FP64,
+    BCS_J_GAMMA,
+    BCS_MAXIT,
+    BCS_NONFINITE,
+    BcsError,
+    BatchedSolve,
+    Plan,
+    exported_symbols,
+    lib,
+    library_path,
+    solve_batch,
+    solve_batch_adjoint,
+    solve_multi,
+)

@@ -1,0 +1,313 @@
+"""ctypes binding of libbcs.so: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbcs.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "bcs.h")
+
+BCS_OK = 0
+BCS_CONVERGED, BCS_MAXIT, BCS_BREAKDOWN, BCS_NONFINITE = 0, 1, 2, 3
+BCS_FP64, BCS_FP32_REFINE = 0, 1
+BCS_PRECOND_NONE, BCS_PRECOND_JACOBI = 0, 1
+BCS_J_GAMMA, BCS_A_DIRECT = 0, 1
+
+_PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI}
+_PRECISION = {"fp64": BCS_FP64, "fp32_refine": BCS_FP32_REFINE}
+_KIND = {"j_gamma": BCS_J_GAMMA, "a_direct": BCS_A_DIRECT}
+
+
+class BcsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bcs error {code}: {msg}")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("matrix_kind", ctypes.c_int32),
+        ("lanes_per_cell", ctypes.c_int32),
+        ("residual_replacement", ctypes.c_int32),
+        ("breakdown_restarts", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double),
+        ("max_refine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libbcs.so (building it first if it does not exist)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+
+            _build.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P, I32, I64, D, VP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        L.bcs_options_default.argtypes = [ctypes.POINTER(_Options)]
+        L.bcs_options_default.restype = None
+        L.bcs_plan_create.argtypes = [I32, I32, P, P, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]
+        L.bcs_plan_create.restype = ctypes.c_int
+        L.bcs_plan_destroy.argtypes = [P]
+        L.bcs_plan_destroy.restype = None
+        L.bcs_plan_info.argtypes = [P, P, P, P, P]
+        L.bcs_plan_info.restype = ctypes.c_int
+        L.bcs_solve_batch.argtypes = [P, I64, P, P, I64, P, D, I32, P, P, P, P, P, VP]
+        L.bcs_solve_batch.restype = ctypes.c_int
+        L.bcs_solve_batch_adjoint.argtypes = [P, I64, P, P, I64, P, P, D, I32, P, P, P, P, P, VP]
+        L.bcs_solve_batch_adjoint.restype = ctypes.c_int
+        L.bcs_solve_multi.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, VP]
+        L.bcs_solve_multi.restype = ctypes.c_int
+        L.bcs_last_error.argtypes = []
+        L.bcs_last_error.restype = ctypes.c_char_p
+        _lib = L
+        return L
+
+
+def exported_symbols() -> list:
+    """Function names declared in include/bcs.h."""
+    with open(_HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(bcs_[a-z_]+)\s*\(", text)))
+
+
+def _check(rc: int) -> None:
+    if rc != BCS_OK:
+        raise BcsError(rc, lib().bcs_last_error().decode())
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Plan:
+    """A shared CSR pattern plus solver options (bcs_plan_create)."""
+
+    def __init__(self, row_ptr, col_idx, precond: str = "jacobi", precision: str = "fp64",
+                 matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
+                 breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10):
+        L = lib()
+        rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+        ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
+        self.n = int(rp.shape[0] - 1)
+        self.nnz = int(ci.shape[0])
+        self.row_ptr, self.col_idx = rp, ci
+        opt = _Options()
+        L.bcs_options_default(ctypes.byref(opt))
+        opt.precision = _PRECISION[precision]
+        opt.precond = _PRECOND[precond]
+        opt.matrix_kind = _KIND[matrix_kind]
+        opt.lanes_per_cell = int(lanes_per_cell)
+        opt.residual_replacement = int(bool(residual_replacement))
+        opt.breakdown_restarts = int(breakdown_restarts)
+        opt.inner_rtol = float(inner_rtol)
+        opt.max_refine = int(max_refine)
+        self.options = opt
+        self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
+        h = ctypes.c_void_p()
+        rc = L.bcs_plan_create(self.n, self.nnz, rp.ctypes.data, ci.ctypes.data if self.nnz else None,
+                               ctypes.byref(opt), ctypes.byref(h))
+        self._h = None
+        _check(rc)
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().bcs_plan_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(lanes_per_cell=v[0].value, rows_per_lane=v[1].value, steps_per_lane=v[2].value,
+                    cells_per_wg=v[3].value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.bcs_plan_destroy(h)
+            self._h = None
+
+
+def _gamma_arg(gamma, ncells, device):
+    torch = _torch()
+    if not isinstance(gamma, torch.Tensor):
+        gamma = torch.tensor([float(gamma)], dtype=torch.float64, device=device)
+    _dev(gamma, torch.float64, "gamma")
+    if gamma.numel() == 1:
+        return gamma, 0
+    if gamma.numel() != ncells:
+        raise ValueError("gamma must have 1 or ncells elements")
+    return gamma, 1
+
+
+def solve_batch(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 200, out=None):
+    """Solve every cell's system; returns (x, iters, resid, status, refinements)."""
+    torch = _torch()
+    values = _dev(values, torch.float64, "values")
+    ncells = values.shape[0] if values.dim() == 2 else 0
+    _dev(values, torch.float64, "values", (ncells, plan.nnz))
+    _dev(b, torch.float64, "b", (ncells, plan.n))
+    g, gs = _gamma_arg(gamma, ncells, values.device)
+    if out is None:
+        x = torch.empty((ncells, plan.n), dtype=torch.float64, device=values.device)
+        iters = torch.empty(ncells, dtype=torch.int32, device=values.device)
+        resid = torch.empty(ncells, dtype=torch.float64, device=values.device)
+        status = torch.empty(ncells, dtype=torch.int32, device=values.device)
+        refin = torch.empty(ncells, dtype=torch.int32, device=values.device)
+    else:
+        x, iters, resid, status, refin = out
+    rc = lib().bcs_solve_batch(plan.handle, ncells, values.data_ptr(), g.data_ptr(), gs, b.data_ptr(),
+                               float(rtol), int(maxit), x.data_ptr(), iters.data_ptr(), resid.data_ptr(),
+                               status.data_ptr(), refin.data_ptr() if refin is not None else None,
+                               _stream_handle())
+    _check(rc)
+    return x, iters, resid, status, refin
+
+
+def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, maxit: int = 200):
+    """Adjoint solve: returns (grad_b = lambda, grad_A, iters, resid, status)."""
+    torch = _torch()
+    values = _dev(values, torch.float64, "values")
+    ncells = values.shape[0]
+    _dev(x, torch.float64, "x", (ncells, plan.n))
+    _dev(g, torch.float64, "g", (ncells, plan.n))
+    gm, gs = _gamma_arg(gamma, ncells, values.device)
+    dev = values.device
+    grad_b = torch.empty((ncells, plan.n), dtype=torch.float64, device=dev)
+    grad_A = torch.empty((ncells, plan.nnz), dtype=torch.float64, device=dev)
+    iters = torch.empty(ncells, dtype=torch.int32, device=dev)
+    resid = torch.empty(ncells, dtype=torch.float64, device=dev)
+    status = torch.empty(ncells, dtype=torch.int32, device=dev)
+    rc = lib().bcs_solve_batch_adjoint(plan.handle, ncells, values.data_ptr(), gm.data_ptr(), gs, x.data_ptr(),
+                                       g.data_ptr(), float(rtol), int(maxit), grad_b.data_ptr(),
+                                       grad_A.data_ptr(), iters.data_ptr(), resid.data_ptr(), status.data_ptr(),
+                                       _stream_handle())
+    _check(rc)
+    return grad_b, grad_A, iters, resid, status
+
+
+def solve_multi(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence, rtol: float = 1e-10,
+                maxit: int = 200):
+    """One persistent launch over several mechanisms; per mechanism (x, iters, resid, status)."""
+    torch = _torch()
+    m = len(plans)
+    outs = []
+    arrs = {k: (ctypes.c_void_p * m)() for k in ("plans", "values", "gamma", "b", "x", "iters", "resid", "status")}
+    nc = (ctypes.c_int64 * m)()
+    gst = (ctypes.c_int64 * m)()
+    for i, (pl, v, g, b) in enumerate(zip(plans, values, gammas, bs)):
+        _dev(v, torch.float64, "values")
+        C = v.shape[0]
+        _dev(v, torch.float64, "values", (C, pl.nnz))
+        _dev(b, torch.float64, "b", (C, pl.n))
+        gg, gs = _gamma_arg(g, C, v.device)
+        x = torch.empty((C, pl.n), dtype=torch.float64, device=v.device)
+        it = torch.empty(C, dtype=torch.int32, device=v.device)
+        rs = torch.empty(C, dtype=torch.float64, device=v.device)
+        st = torch.empty(C, dtype=torch.int32, device=v.device)
+        outs.append((x, it, rs, st))
+        nc[i] = C
+        gst[i] = gs
+        for k, t in (("values", v), ("gamma", gg), ("b", b), ("x", x), ("iters", it), ("resid", rs),
+                     ("status", st)):
+            arrs[k][i] = t.data_ptr()
+        arrs["plans"][i] = pl.handle.value
+    keep = (values, gammas, bs)  # noqa: F841  (tensors stay alive across the call)
+    rc = lib().bcs_solve_multi(m, arrs["plans"], nc, arrs["values"], arrs["gamma"], gst, arrs["b"], float(rtol),
+                               int(maxit), arrs["x"], arrs["iters"], arrs["resid"], arrs["status"],
+                               _stream_handle())
+    _check(rc)
+    return outs
+
+
+class BatchedSolve:
+    """Differentiable batched solve x = (I - gamma J)^-1 b (J mode) or A^-1 b.
+
+    ``BatchedSolve.apply(values, gamma, b, plan, rtol, maxit)`` returns x.
+    Backward runs the library's adjoint solve (transposed BiCGStab) and maps
+    dL/dA to the inputs: in J mode dL/dJ = -gamma dL/dA and
+    dL/dgamma = -sum_k J_k dL/dA_k per cell; in A mode dL/dA is returned as is.
+    """
+
+    _fn = None
+
+    @classmethod
+    def _function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, values, gamma, b, plan, rtol=1e-10, maxit=200):
+                    x, iters, resid, status, _ = solve_batch(plan, values.contiguous(), gamma, b.contiguous(),
+                                                             rtol, maxit)
+                    ctx.plan, ctx.rtol, ctx.maxit = plan, rtol, maxit
+                    ctx.save_for_backward(values, gamma if isinstance(gamma, torch.Tensor) else None, x)
+                    ctx.gamma_obj = gamma
+                    return x
+
+                @staticmethod
+                def backward(ctx, gx):
+                    values, gamma_t, x = ctx.saved_tensors
+                    plan = ctx.plan
+                    gamma = gamma_t if gamma_t is not None else ctx.gamma_obj
+                    grad_b, grad_A, _, _, _ = solve_batch_adjoint(plan, values, gamma, x, gx.contiguous(),
+                                                                  ctx.rtol, ctx.maxit)
+                    if plan.matrix_kind == "a_direct":
+                        return grad_A, None, grad_b, None, None, None
+                    g = gamma_t.reshape(-1, 1) if gamma_t is not None else float(gamma)
+                    grad_J = -g * grad_A
+                    grad_gamma = None
+                    if gamma_t is not None and ctx.needs_input_grad[1]:
+                        per_cell = -(values * grad_A).sum(dim=1)
+                        grad_gamma = per_cell if gamma_t.numel() > 1 else per_cell.sum().reshape(gamma_t.shape)
+                    return grad_J, grad_gamma, grad_b, None, None, None
+
+            cls._fn = _F
+        return cls._fn
+
+    @classmethod
+    def apply(cls, values, gamma, b, plan, rtol=1e-10, maxit=200):
+        return cls._function().apply(values, gamma, b, plan, rtol, maxit)

@@ -1,0 +1,158 @@
+// Device building blocks of the batched Block-cells solvers (gfx950, wave64).
+//
+// Layout of a cell on chip.  A cell is owned by LANES consecutive lanes of a
+// wavefront (16, 32 or 64; 64/LANES cells per wave).  Rows are dealt to
+// (slot j, lane l) by decreasing length, RPL slots per lane, so that slot j
+// covers the same schedule steps on every lane: the matrix is held as a
+// sliced-ELL block whose slice height is LANES.  The cell's matrix values
+// live in VGPRs (a[s], one per schedule step), its Krylov vectors in VGPRs
+// (one value per owned row), and only the SpMV operand is staged in the
+// cell's LDS slice, from which every lane gathers its columns.
+#pragma once
+
+#include "bcs_internal.h"
+
+namespace bcs {
+namespace dev {
+
+// Make this wave's LDS writes visible to its own later reads (and keep the
+// compiler from moving LDS accesses across the point).  A wavefront's LDS
+// instructions complete in order, so no s_barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)u, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF,
+                                             false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                         false));
+}
+
+// All-reduce sum over the LANES lanes of a cell.  Butterfly: every lane adds
+// the same two partial sums (in either order, and IEEE addition commutes), so
+// all lanes of the cell end with bitwise the same value, and the result of a
+// cell never depends on which slot or wave it ran in.
+template <int LANES, typename T>
+__device__ __forceinline__ T gsum(T v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror: quads 0<->1 within each 8 lanes
+  v += dpp<0x140>(v);  // row_mirror: halves 0<->1 within each 16-lane row
+  if constexpr (LANES >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (LANES >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Hide a wave-uniform value from the optimiser so that conditions derived
+// from it are evaluated where they are used instead of being hoisted and kept
+// live across the whole kernel (which exhausts the scalar registers).
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// Copy a lane's packed words so that values unpacked from the copy are
+// recomputed at this use instead of being hoisted and kept live unpacked.
+template <int N>
+__device__ __forceinline__ void opaque_copy(const uint32_t (&in)[N], uint32_t (&out)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    out[q] = in[q];
+    asm volatile("" : "+v"(out[q]));
+  }
+}
+
+// 16-bit LDS byte address of step s from packed words.
+template <int N>
+__device__ __forceinline__ uint32_t step_addr(const uint32_t (&ad)[N], int s) {
+  return (s & 1) ? (ad[s >> 1] >> 16) : (ad[s >> 1] & 0xffffu);
+}
+
+__device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
+  return s < 64 ? ((f0 >> s) & 1ull) != 0 : ((f1 >> (s - 64)) & 1ull) != 0;
+}
+
+constexpr int kGatherChunk = 8;
+
+// Number of 32-bit words holding a lane's per-step LDS gather addresses
+// (16-bit byte addresses, two per word).
+template <int KMAX>
+constexpr int addr_words() { return (KMAX + 1) / 2; }
+
+// out = M * in for the cell's matrix held as schedule values a[] (this
+// lane's KMAX steps; padding steps hold 0) and packed LDS byte addresses
+// ad[] (two 16-bit addresses per word).  `in` and `out` are this lane's
+// owned rows (padding rows are staged into the spare element n of the
+// slice).  xb is the cell's operand slice, yb its result slice (RPL x LANES
+// elements, slot-major), lds the workgroup's LDS base.  The steps of slot j
+// end where bit s of (f0, f1) is set: the finished row sum is written to
+// yb[j*LANES + lane] (a uniform branch around one LDS store, so no register
+// array is indexed at run time), and the lane reads its RPL sums back.
+// Gathers are issued a chunk at a time, ahead of the chunk's FMAs.
+template <int LANES, int RPL, int KMAX, typename T>
+__device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
+                                     uint64_t f0_, uint64_t f1_, const char* lds, T* xb, T* yb, int gl,
+                                     const int (&rows)[RPL], const T (&in)[RPL], T (&out)[RPL]) {
+  constexpr int NW = addr_words<KMAX>();
+  const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
+  uint32_t ad[NW];
+  opaque_copy<NW>(ad_, ad);
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
+  wave_sync();
+  T acc = 0;
+  T* ydst = yb + gl;
+#pragma unroll
+  for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
+    constexpr int C = kGatherChunk;
+    T g[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const int s = s0 + i;
+      if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
+    }
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const int s = s0 + i;
+      if (s < KMAX) {
+        acc = __builtin_fma(a[s], g[i], acc);
+        if (flush_bit(f0, f1, s)) {
+          *ydst = acc;
+          ydst += LANES;
+          acc = 0;
+        }
+      }
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) out[j] = yb[j * LANES + gl];
+  wave_sync();
+}
+
+template <int RPL, typename T>
+__device__ __forceinline__ T ldot(const T (&u)[RPL], const T (&v)[RPL]) {
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) s = __builtin_fma(u[j], v[j], s);
+  return s;
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
+
+}  // namespace dev
+}  // namespace bcs

@@ -1,0 +1,292 @@
+// FP64 batched Block-cells BiCGStab kernel (forward solve and adjoint solve).
+//
+// One launch solves every cell: a persistent grid whose cell slots (LANES
+// lanes each) pull cell indices from a device work queue, iterate that cell's
+// BiCGStab to completion without any inter-workgroup communication or host
+// round trip (the Block-cells arrangement, Section 3.1), write the cell's
+// outputs and pull the next cell.  Slots of one wave advance independently:
+// a slot whose cell has converged refills while its neighbours iterate.
+//
+// Per iteration (right preconditioning M = diag(A) when enabled):
+//   rho = (rhat, r);  p = r + beta (p - omega v);  v = A M^-1 p;  sigma = (rhat, v)
+//   alpha = rho / sigma;  s = r - alpha v;  stop if ||s|| <= rtol ||b||
+//   t = A M^-1 s;  omega = (t, s) / (t, t);  x += alpha M^-1 p + omega M^-1 s
+//   r = s - omega t;  stop if ||r|| <= rtol ||b||
+// then the true residual ||b - A x|| confirms convergence; a cell whose true
+// residual misses rtol restarts from it (residual replacement) while
+// iterations remain, and an exact breakdown restarts a bounded number of
+// times.  The adjoint mode runs the same loop on A^T (a transposed schedule
+// over the same per-cell values) with g as right-hand side and then writes
+// dL/dA_ij = -lambda_i x_j.
+#pragma once
+
+#include "bcs_device.h"
+
+namespace bcs {
+
+template <int LANES, int RPL, int KMAX>
+__global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
+  using namespace dev;
+  constexpr int G = 64 / LANES;
+  constexpr int NW = addr_words<KMAX>();
+  extern __shared__ double lds[];
+  const char* ldsb = (const char*)lds;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int gl = lane & (LANES - 1);
+  const int grp = lane / LANES;
+  const int slot_base = (wv * G + grp) * P.xs;  // in doubles
+  double* xb = lds + slot_base;          // SpMV operand (n + spare)
+  double* yb = xb + P.yoff;               // SpMV result, slot-major RPL x LANES
+
+  const uint64_t f0 = P.sched.flush[0], f1 = P.sched.flush[1];
+  const int n = P.n, nnz = P.nnz;
+
+  // This lane's LDS gather addresses (the schedule is shared by every cell
+  // of the plan and padded to exactly KMAX steps).
+  uint32_t ad[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int s = 2 * q + i;
+      if (s < KMAX) w |= (uint32_t)((slot_base + P.sched.col[s * LANES + gl]) * 8) << (16 * i);
+    }
+    ad[q] = w;
+  }
+  // Owned rows; a padding row (-1) stages into the spare LDS element n.
+  int rows[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const int rj = P.sched.row[j * LANES + gl];
+    rows[j] = rj >= 0 ? rj : n;
+  }
+
+  double a[KMAX];
+  // Krylov state of this lane's rows.  With Jacobi the matrix is staged
+  // column-scaled (Ahat = A D^-1, right preconditioning), so xv holds
+  // xhat = D x and x = D^-1 xhat is formed when the cell finishes.
+  double xv[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];
+  double bn = 0, rho_prev = 1, alpha = 1, omega = 1;
+  int it = 0, restarts_left = 0;
+  bool first = true, active = false, dead = false;
+  int64_t cell = 0;
+
+  // diag(A)^-1 of this lane's rows (0 for padding rows).
+  auto diag_inv = [&](int j) -> double {
+    const bool real = rows[j] < n;
+    const double dv = P.values[cell * nnz + (P.diag_pos[real ? rows[j] : 0] & kEntPosMask)];
+    const double g = (P.kind == BCS_J_GAMMA) ? P.gamma[cell * P.gamma_stride] : 0.0;
+    const double d = (P.kind == BCS_J_GAMMA) ? 1.0 - g * dv : dv;
+    return real ? 1.0 / d : 0.0;
+  };
+
+  // Write the cell's outputs and free the slot.
+  auto finish = [&](int st, double res) {
+    if (P.precond) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) xv[j] = diag_inv(j) * xv[j];
+    }
+    if (P.adjoint) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        xb[rows[j]] = xv[j];
+        xb[P.xoff2 + rows[j]] = (rows[j] < n) ? P.xin[cell * n + rows[j]] : 0.0;
+      }
+      wave_sync();
+      for (int k = gl; k < nnz; k += LANES)
+        P.grad_a[cell * nnz + k] = -xb[P.coo_row[k]] * xb[P.xoff2 + P.coo_col[k]];
+      wave_sync();
+    }
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+      if (rows[j] < n) P.x[cell * n + rows[j]] = xv[j];
+    if (gl == 0) {
+      P.iters[cell] = it;
+      P.resid[cell] = res;
+      P.status[cell] = st;
+      if (P.refinements) P.refinements[cell] = 0;
+    }
+    active = false;
+  };
+
+  // Restart the recurrences from the current r.
+  auto restart = [&]() {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      rh[j] = r[j];
+      p[j] = 0;
+      v[j] = 0;
+    }
+    rho_prev = alpha = omega = 1;
+    first = true;
+  };
+
+  for (;;) {
+    if (!active && !dead) {
+      unsigned long long c = 0;
+      if (gl == 0) c = atomicAdd(P.queue, 1ull);
+      c = __shfl(c, grp * LANES, 64);
+      if (c >= (unsigned long long)P.ncells) {
+        dead = true;
+      } else {
+        cell = (int64_t)c;
+        // Stage the cell: A = I - gamma J (or A) into registers, b, diag(A)^-1.
+        // Loads are unconditional (padding entries read position 0 and are
+        // zeroed) so that they issue back to back.
+        const double* vals = P.values + cell * nnz;
+        const double g = (P.kind == BCS_J_GAMMA) ? P.gamma[cell * P.gamma_stride] : 0.0;
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+          const int32_t e = P.sched.ent[s * LANES + gl];
+          const double jv = vals[e & kEntPosMask];
+          const double av = (P.kind == BCS_J_GAMMA) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
+          a[s] = (e & kEntPad) ? 0.0 : av;
+          if ((s % kGatherChunk) == kGatherChunk - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        if (P.precond) {
+          // column scaling by diag(A)^-1, gathered through the LDS slice
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) xb[rows[j]] = diag_inv(j);
+          wave_sync();
+          uint32_t ado[NW];
+          opaque_copy<NW>(ad, ado);
+#pragma unroll
+          for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr(ado, s));
+          wave_sync();
+        }
+        const double* bc = P.b + cell * n;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const bool real = rows[j] < n;
+          const double bj = bc[real ? rows[j] : 0];
+          r[j] = real ? bj : 0.0;
+          xv[j] = 0;
+        }
+        bn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
+        it = 0;
+        restarts_left = P.brs;
+        restart();
+        active = true;
+        if (!finite(bn)) {
+          finish(BCS_NONFINITE, __builtin_nan(""));
+        } else if (bn == 0.0) {
+          finish(BCS_CONVERGED, 0.0);
+        }
+      }
+    }
+    if (__ballot(!dead) == 0ull) break;
+    if (!active) continue;
+
+    // ---- one BiCGStab iteration of this slot's cell ----
+    ++it;
+    int ended = -1;  // -1 = continue, else BCS_CONVERGED / BCS_BREAKDOWN / BCS_NONFINITE
+    const double rho = gsum<LANES>(ldot<RPL>(rh, r));
+    if (!finite(rho)) {
+      ended = BCS_NONFINITE;
+    } else if (rho == 0.0) {
+      ended = BCS_BREAKDOWN;
+    } else {
+      if (first) {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) p[j] = r[j];
+        first = false;
+      } else {
+        const double beta = (rho / rho_prev) * (alpha / omega);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
+      }
+      spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, p, v);
+      const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
+      if (!finite(sigma)) {
+        ended = BCS_NONFINITE;
+      } else if (sigma == 0.0) {
+        ended = BCS_BREAKDOWN;
+      } else {
+        alpha = rho / sigma;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
+        const double sn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
+        if (!finite(sn)) {
+          ended = BCS_NONFINITE;
+        } else if (sn / bn <= P.rtol) {
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) xv[j] = xv[j] + alpha * p[j];
+          ended = BCS_CONVERGED;
+        } else {
+          spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, r, t);
+          const double tt = gsum<LANES>(ldot<RPL>(t, t));
+          const double ts = gsum<LANES>(ldot<RPL>(t, r));
+          if (!finite(tt)) {
+            ended = BCS_NONFINITE;
+          } else if (tt == 0.0) {
+            ended = BCS_BREAKDOWN;
+          } else {
+            omega = ts / tt;
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+              xv[j] = xv[j] + alpha * p[j] + omega * r[j];
+              r[j] = r[j] - omega * t[j];
+            }
+            const double rn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
+            if (!finite(rn)) {
+              ended = BCS_NONFINITE;
+            } else if (rn / bn <= P.rtol) {
+              ended = BCS_CONVERGED;
+            } else if (omega == 0.0) {
+              ended = BCS_BREAKDOWN;
+            } else {
+              rho_prev = rho;
+            }
+          }
+        }
+      }
+    }
+    if (ended < 0 && it >= P.maxit) ended = BCS_MAXIT;
+    if (ended >= 0) {
+      // The true residual of the current iterate decides (t is free here).
+      spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, xv, t);
+      {
+        const double* bc = P.b + cell * n;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const bool real = rows[j] < n;
+          const double bj = bc[real ? rows[j] : 0];
+          t[j] = (real ? bj : 0.0) - t[j];
+        }
+      }
+      const double res = __builtin_sqrt(gsum<LANES>(ldot<RPL>(t, t))) / bn;
+      if (ended == BCS_NONFINITE || !finite(res)) {
+        finish(BCS_NONFINITE, res);
+      } else if (res <= P.rtol) {
+        finish(BCS_CONVERGED, res);
+      } else if (it < P.maxit && ((ended == BCS_CONVERGED && P.rr) || (ended == BCS_BREAKDOWN && restarts_left > 0))) {
+        if (ended == BCS_BREAKDOWN) --restarts_left;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) r[j] = t[j];
+        restart();
+      } else {
+        finish(ended == BCS_BREAKDOWN ? BCS_BREAKDOWN : BCS_MAXIT, res);
+      }
+    }
+  }
+
+  // The last wave to finish re-arms the work queue for the next launch.
+  if (lane == 0) {
+    const unsigned long long done = atomicAdd(P.queue + 1, 1ull);
+    if (done == (unsigned long long)(P.total_waves - 1)) {
+      atomicExch(P.queue, 0ull);
+      atomicExch(P.queue + 1, 0ull);
+    }
+  }
+}
+
+template <int LANES, int RPL, int KMAX>
+hipError_t launch_fp64(const KParams& P, int grid, hipStream_t stream) {
+  const size_t lds = (size_t)kWavesPerWg * (64 / LANES) * P.xs * sizeof(double);
+  hipLaunchKernelGGL((k_fp64<LANES, RPL, KMAX>), dim3(grid), dim3(kWgThreads), lds, stream, P);
+  return hipGetLastError();
+}
+
+}  // namespace bcs

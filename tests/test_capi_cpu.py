@@ -1,0 +1,75 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+patterns and options before touching a device (runs without a GPU)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2405_17363_amd as bcs
+from paper_2405_17363_amd._binding import _Options
+
+
+def test_library_exports_every_declared_symbol():
+    L = bcs.lib()
+    names = bcs.exported_symbols()
+    assert {"bcs_plan_create", "bcs_solve_batch", "bcs_solve_batch_adjoint", "bcs_solve_multi",
+            "bcs_last_error", "bcs_plan_destroy", "bcs_options_default", "bcs_plan_info"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_options_struct_layout_and_defaults():
+    L = bcs.lib()
+    o = _Options()
+    L.bcs_options_default(ctypes.byref(o))
+    assert o.precision == bcs.BCS_FP64 and o.precond == 1 and o.matrix_kind == bcs.BCS_J_GAMMA
+    assert o.residual_replacement == 1 and o.breakdown_restarts == 1
+    assert o.inner_rtol == 1e-4 and o.max_refine == 10
+    assert ctypes.sizeof(_Options) == 64
+
+
+def _create(rp, ci, **kw):
+    L = bcs.lib()
+    o = _Options()
+    L.bcs_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    rp = np.asarray(rp, np.int32)
+    ci = np.asarray(ci, np.int32)
+    h = ctypes.c_void_p()
+    rc = L.bcs_plan_create(len(rp) - 1, len(ci), rp.ctypes.data, ci.ctypes.data, ctypes.byref(o), ctypes.byref(h))
+    return rc, L.bcs_last_error().decode(), h
+
+
+@pytest.mark.parametrize("rp,ci,what", [
+    ([1, 2, 3], [0, 1], "row_ptr[0]"),
+    ([0, 2, 3], [0, 1], "row_ptr[n]"),
+    ([0, 2, 1], [0], "row_ptr decreases"),
+    ([0, 2, 4], [1, 0, 0, 1], "strictly increasing"),
+    ([0, 2, 4], [0, 0, 0, 1], "strictly increasing"),
+    ([0, 2, 4], [0, 2, 0, 1], "out of range"),
+    ([0, 1, 2], [1, 0], "diagonal"),
+])
+def test_invalid_patterns_are_rejected(rp, ci, what):
+    rc, msg, h = _create(rp, ci)
+    assert rc in (-1, -2), msg
+    assert what.split()[0] in msg
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("precision", 7), ("precond", 5), ("matrix_kind", 3),
+                                          ("lanes_per_cell", 8), ("residual_replacement", 2),
+                                          ("breakdown_restarts", -1)])
+def test_invalid_options_are_rejected(field, value):
+    rc, msg, h = _create([0, 1, 2], [0, 1], **{field: value})
+    assert rc == -1, msg
+    assert not h.value
+
+
+def test_missing_diagonal_allowed_without_jacobi_in_a_mode():
+    # A_DIRECT + no preconditioner does not need the diagonal: validation
+    # passes and only the (absent) device can stop the plan.
+    rc, msg, h = _create([0, 1, 2], [1, 0], matrix_kind=1, precond=0)
+    assert rc in (0, -4), msg
+    if rc == 0:
+        bcs.lib().bcs_plan_destroy(h)

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP batched BiCGStab (through the C-ABI) against the CPU oracle.
+
+x is compared with the oracle's dense LU within the bound the residual
+implies, max(1e-8, 4 kappa_2 max(resid, rho_LU)) (rho_LU = the LU solution's
+own relative residual), statuses with the oracle's BiCGStab, and iteration
+counts within max(3, 15%) on >= 95% of cells (BiCGStab's iteration count is
+rounding-sensitive; beyond that it is parity unpinned).  Bitwise properties
+(ideal cells, permutations, repeated runs, lanes/slot independence) are exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workload import config_inputs, gen_cells, gen_mechanism
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts too
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_17363_amd as bcs  # noqa: E402
+
+RTOL = 1e-10
+
+
+def gpu(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def run(plan, values, gamma, b, rtol=RTOL, maxit=200):
+    x, it, res, st, ref = bcs.solve_batch(plan, gpu(values), gpu(np.atleast_1d(gamma)), gpu(b), rtol, maxit)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), it.cpu().numpy(), res.cpu().numpy(), st.cpu().numpy()
+
+
+def dense_a(rp, ci, vals, gamma, kind=oracle.J_GAMMA):
+    v = vals if kind == oracle.A_DIRECT else oracle.form_a(rp, ci, vals, gamma)
+    return oracle.to_dense(rp, ci, v)
+
+
+def check_against_lu(rp, ci, values, gamma, b, x, res, st, sample, kind=oracle.J_GAMMA):
+    """kappa-aware comparison of GPU x with the oracle's dense LU on `sample` cells."""
+    gam = np.broadcast_to(np.atleast_1d(gamma), (values.shape[0],))
+    xl, info = oracle.lu_batch(rp, ci, values[sample], gam[sample], b[sample], kind=kind)
+    worst = 0.0
+    for q, c in enumerate(sample):
+        if st[c] != bcs.BCS_CONVERGED:
+            continue
+        A = dense_a(rp, ci, values[c], gam[c], kind)
+        kappa = np.linalg.cond(A)
+        bn = np.linalg.norm(b[c])
+        rlu = np.linalg.norm(b[c] - A @ xl[q]) / bn
+        err = np.linalg.norm(x[c] - xl[q]) / np.linalg.norm(xl[q])
+        bound = max(1e-8, 4 * kappa * max(res[c], rlu))
+        assert err <= bound, (c, err, bound, kappa, res[c], rlu)
+        # reported residual is the true residual of the returned x
+        rel = np.linalg.norm(b[c] - A @ x[c]) / bn
+        slack = 64 * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(x[c])) / bn
+        assert rel <= RTOL + slack, (c, rel, res[c])
+        worst = max(worst, err / bound)
+    return worst
+
+
+def check_against_oracle(mech, cells, x, it, res, st, precond=1, min_status_agree=0.99):
+    xo, ito, reso, sto = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"],
+                                            cells["b"], precond=precond)
+    agree = np.mean(st == sto)
+    assert agree >= min_status_agree, (agree, np.bincount(st, minlength=4), np.bincount(sto, minlength=4))
+    both = (st == bcs.BCS_CONVERGED) & (sto == bcs.BCS_CONVERGED)
+    assert np.all(res[st == bcs.BCS_CONVERGED] <= RTOL)
+    close = np.abs(it[both] - ito[both]) <= np.maximum(3, 0.15 * ito[both])
+    assert np.mean(close) >= 0.95, np.mean(close)
+    return xo, ito, reso, sto
+
+
+# ---------------------------------------------------------------- configs ----
+
+@pytest.mark.parametrize("lanes", [0, 16, 32, 64])
+def test_config1_100_cells_all_lane_layouts(lanes):
+    mech, cells = config_inputs(1)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=lanes)
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    print("plan", plan.info(), "status", np.bincount(st, minlength=4), "iters mean", it.mean())
+    check_against_oracle(mech, cells, x, it, res, st)
+    check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                     np.arange(100))
+
+
+def test_config2_10k_cells():
+    mech, cells = config_inputs(2)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    check_against_oracle(mech, cells, x, it, res, st)
+    rng = np.random.default_rng(2)
+    check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                     rng.choice(10_000, 400, replace=False))
+    assert np.mean(st == bcs.BCS_CONVERGED) >= 0.99
+
+
+def test_config3_100k_cells_sampled():
+    mech, cells = config_inputs(3)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    conv = st == bcs.BCS_CONVERGED
+    assert conv.mean() >= 0.99
+    assert np.all(res[conv] <= RTOL)
+    # mass-action conservation on every converged cell: 1^T A = 1^T
+    bn = np.linalg.norm(cells["b"], axis=1)
+    drift = np.abs(x.sum(1) - cells["b"].sum(1))
+    assert np.all(drift[conv] <= np.sqrt(mech.n) * res[conv] * bn[conv] * 1.01 + 1e-6 * np.abs(x[conv]).sum(1))
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(100_000, 600, replace=False))
+    sub = {k: cells[k][sample] for k in ("values", "gamma", "b")}
+    xo, ito, reso, sto = oracle.solve_batch(mech.row_ptr, mech.col_idx, sub["values"], sub["gamma"], sub["b"],
+                                            precond=1)
+    assert np.mean(st[sample] == sto) >= 0.98
+    check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                     sample[:300])
+
+
+def test_config4_three_mechanisms_separately():
+    for mech, cells in config_inputs(4, ncells=8000):
+        plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+        x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+        print("n", mech.n, plan.info(), np.bincount(st, minlength=4))
+        check_against_oracle(mech, cells, x, it, res, st, min_status_agree=0.98)
+        rng = np.random.default_rng(mech.n)
+        check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                         rng.choice(len(st), 120, replace=False))
+
+
+def test_precond_none_matches_oracle():
+    mech, cells = config_inputs(1)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="none")
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    check_against_oracle(mech, cells, x, it, res, st, precond=0, min_status_agree=0.95)
+    check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                     np.arange(100))
+
+
+# ------------------------------------------------------- small systems -------
+
+def _csr_dense(M):
+    n = M.shape[0]
+    rp, ci, vals = [0], [], []
+    for i in range(n):
+        for j in range(n):
+            if M[i, j] != 0 or i == j:
+                ci.append(j)
+                vals.append(M[i, j])
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32), np.array(vals)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_tiny_random_systems_vs_lu(precond):
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(1, 13))
+        M = np.where(rng.uniform(size=(n, n)) < 0.5, rng.standard_normal((n, n)), 0.0)
+        M[np.arange(n), np.arange(n)] = rng.uniform(1, 3, n) * rng.choice([-1, 1], n)
+        rp, ci, vals = _csr_dense(M)
+        C = 37  # several cells of the same pattern, different values
+        V = vals[None, :] * rng.uniform(0.5, 1.5, (C, vals.size))
+        b = rng.standard_normal((C, n))
+        plan = bcs.Plan(rp, ci, precond=precond, matrix_kind="a_direct")
+        x, it, res, st = run(plan, V, [0.0], b, rtol=1e-12, maxit=400)
+        xo, ito, reso, sto = oracle.solve_batch(rp, ci, V, [0.0], b, rtol=1e-12, maxit=400,
+                                                precond=int(precond == "jacobi"), kind=oracle.A_DIRECT)
+        for c in range(C):
+            A = oracle.to_dense(rp, ci, V[c])
+            if np.linalg.cond(A) > 1e6 or sto[c] == oracle.BREAKDOWN:
+                continue
+            assert st[c] == bcs.BCS_CONVERGED, (trial, c, st[c], it[c], res[c])
+            xr = np.linalg.solve(A, b[c])
+            assert np.linalg.norm(x[c] - xr) <= 4 * np.linalg.cond(A) * max(res[c], 1e-15) * np.linalg.norm(xr) \
+                + 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_finite_termination_on_gpu(k):
+    # SPD with k distinct eigenvalues: BiCGStab stops within k iterations
+    rng = np.random.default_rng(k)
+    n = 12
+    eigs = np.array([1.0, 2.5, 4.0, 6.0][:k])
+    C = 16
+    Ms = []
+    for c in range(C):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        Ms.append(Q @ np.diag(eigs[np.arange(n) % k]) @ Q.T)
+    rp, ci, _ = _csr_dense(np.ones((n, n)))
+    V = np.stack([M.reshape(-1) for M in Ms])
+    b = rng.standard_normal((C, n))
+    plan = bcs.Plan(rp, ci, precond="none", matrix_kind="a_direct")
+    x, it, res, st = run(plan, V, [0.0], b, rtol=1e-9, maxit=50)
+    assert np.all(st == bcs.BCS_CONVERGED) and np.all(it <= k), it
+
+
+# ----------------------------------------------------- closed forms / edges --
+
+def test_gamma_zero_returns_b_in_one_iteration():
+    mech, cells = config_inputs(1, ncells=64)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    x, it, res, st = run(plan, cells["values"], np.zeros(64), cells["b"])
+    assert np.all(st == 0) and np.all(it == 1) and np.array_equal(x, cells["b"]) and np.all(res == 0)
+
+
+def test_scalar_gamma_equals_broadcast_gamma():
+    mech, cells = config_inputs(1, ncells=50)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    a = run(plan, cells["values"], [0.3], cells["b"])
+    b = run(plan, cells["values"], np.full(50, 0.3), cells["b"])
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_diagonal_system_with_jacobi():
+    n = 40
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    rng = np.random.default_rng(5)
+    d = rng.uniform(1, 1e4, (9, n))
+    b = rng.standard_normal((9, n))
+    plan = bcs.Plan(rp, ci, matrix_kind="a_direct")
+    x, it, res, st = run(plan, d, [0.0], b)
+    assert np.all(st == 0) and np.all(it == 1)
+    assert np.allclose(x, b / d, rtol=4e-16, atol=0)
+
+
+def test_edge_cases_nan_zero_rhs_maxit():
+    mech, cells = config_inputs(1, ncells=40)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    vals, b = cells["values"].copy(), cells["b"].copy()
+    vals[3, 7] = np.nan
+    b[5] = 0.0
+    b[9, 2] = np.inf
+    x, it, res, st = run(plan, vals, cells["gamma"], b)
+    assert st[3] == bcs.BCS_NONFINITE and st[9] == bcs.BCS_NONFINITE
+    assert st[5] == bcs.BCS_CONVERGED and it[5] == 0 and res[5] == 0 and np.all(x[5] == 0)
+    clean = run(plan, cells["values"], cells["gamma"], cells["b"])
+    keep = [c for c in range(40) if c not in (3, 5, 9)]
+    for u, v in zip((x, it, res, st), clean):
+        assert np.array_equal(u[keep], v[keep])
+    x1, it1, res1, st1 = run(plan, cells["values"], cells["gamma"], cells["b"], maxit=1)
+    assert np.all(it1 == 1) and np.all((st1 == bcs.BCS_MAXIT) | (st1 == bcs.BCS_CONVERGED))
+
+
+def test_exact_breakdown_and_singular_cells():
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    A = np.array([[0.0, 1.0, -1.0, 0.0]])
+    plan = bcs.Plan(rp, ci, precond="none", matrix_kind="a_direct")
+    x, it, res, st = run(plan, A, [0.0], np.array([[1.0, 0.0]]))
+    assert st[0] == bcs.BCS_BREAKDOWN and it[0] == 2 and np.all(x[0] == 0) and res[0] == 1.0
+    # J mode, diagonal pattern, A = I - g J = 0
+    n, g = 4, 0.5
+    rpd = np.arange(n + 1, dtype=np.int32)
+    cid = np.arange(n, dtype=np.int32)
+    J = np.full((1, n), 1.0 / g)
+    x, it, res, st = run(bcs.Plan(rpd, cid, precond="none"), J, [g], np.ones((1, n)))
+    assert st[0] == bcs.BCS_BREAKDOWN
+    x, it, res, st = run(bcs.Plan(rpd, cid, precond="jacobi"), J, [g], np.ones((1, n)))
+    assert st[0] == bcs.BCS_NONFINITE
+
+
+def test_zero_cells_is_a_noop():
+    mech = gen_mechanism(30, 50)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    x, it, res, st = run(plan, np.zeros((0, mech.nnz)), [0.1], np.zeros((0, mech.n)))
+    assert x.shape == (0, mech.n)
+
+
+# ------------------------------------------------------ bitwise properties ---
+
+def test_ideal_cells_bitwise_identical_and_slot_independent():
+    mech, cells = config_inputs(2, ncells=3000, mode="ideal")[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    assert np.all(x == x[0]) and np.all(it == it[0]) and np.all(res == res[0]) and np.all(st == st[0])
+
+
+def test_permutation_and_repetition_bitwise():
+    mech, cells = config_inputs(2, ncells=5000)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    a = run(plan, cells["values"], cells["gamma"], cells["b"])
+    a2 = run(plan, cells["values"], cells["gamma"], cells["b"])
+    perm = np.random.default_rng(9).permutation(5000)
+    p = run(plan, cells["values"][perm], cells["gamma"][perm], cells["b"][perm])
+    for u, v, w in zip(a, a2, p):
+        assert np.array_equal(u, v)
+        assert np.array_equal(u[perm], w)
