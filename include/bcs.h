@@ -70,7 +70,16 @@ typedef struct bcs_options {
   int32_t breakdown_restarts;   /* restarts allowed after an exact breakdown          */
   double inner_rtol;            /* FP32_REFINE: inner solve tolerance (relative)      */
   int32_t max_refine;           /* FP32_REFINE: maximum number of inner solves        */
-  int32_t reserved[7];          /* must be zero                                       */
+  int32_t jit;                  /* 1: compile kernels specialised to this pattern at
+                                   plan creation (hipRTC; cached on disk under
+                                   $BCS_JIT_CACHE or ~/.cache/bcs_jit); 0: use the
+                                   precompiled generic kernels                       */
+  int32_t autotune;             /* 1: with lanes_per_cell == 0, time the candidate
+                                   layouts on a synthetic batch of this pattern (a
+                                   spread of diagonally dominant cells) and keep the
+                                   fastest; 0: choose by a cost model; see also
+                                   bcs_plan_autotune for tuning on real data        */
+  int32_t reserved[5];          /* must be zero                                       */
 } bcs_options;
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
@@ -78,7 +87,7 @@ typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for
 
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
- * max_refine 10. */
+ * max_refine 10, jit 1, autotune 1. */
 void bcs_options_default(bcs_options* opt);
 
 /* Create a plan for an n x n pattern with nnz entries in CSR form
@@ -94,6 +103,17 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
 /* Release a plan (NULL is allowed).  The caller must ensure no solve using it
  * is still running. */
 void bcs_plan_destroy(bcs_plan* plan);
+
+/* Autotuner on the caller's data: time the forward solve of this batch with
+ * every lanes-per-cell layout that holds the pattern (16, 32, 64 lanes per
+ * cell, i.e. 16, 8 or 4 cells per workgroup of four waves) and keep the
+ * fastest in the plan, adjoint included.  Arguments as in bcs_solve_batch
+ * (x/iters/resid/status serve as scratch and hold one solve's outputs
+ * afterwards); synchronises the device; *lanes_out (may be NULL) receives the
+ * chosen lanes per cell.  Not to be called while solves with the plan run. */
+int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, const double* gamma,
+                      int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
+                      int32_t* iters, double* resid, int32_t* status, int32_t* lanes_out);
 
 /* Describe the plan's launch configuration (for logs and tests):
  * lanes per cell, rows per lane, schedule steps per lane, cells per

@@ -40,7 +40,9 @@ class _Options(ctypes.Structure):
         ("breakdown_restarts", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double),
         ("max_refine", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("jit", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -70,6 +72,8 @@ def lib():
         L.bcs_plan_create.restype = ctypes.c_int
         L.bcs_plan_destroy.argtypes = [P]
         L.bcs_plan_destroy.restype = None
+        L.bcs_plan_autotune.argtypes = [P, I64, P, P, I64, P, D, I32, P, P, P, P, P]
+        L.bcs_plan_autotune.restype = ctypes.c_int
         L.bcs_plan_info.argtypes = [P, P, P, P, P]
         L.bcs_plan_info.restype = ctypes.c_int
         L.bcs_solve_batch.argtypes = [P, I64, P, P, I64, P, D, I32, P, P, P, P, P, VP]
@@ -127,7 +131,8 @@ class Plan:
 
     def __init__(self, row_ptr, col_idx, precond: str = "jacobi", precision: str = "fp64",
                  matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
-                 breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10):
+                 breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10,
+                 jit: bool = True, autotune: bool = True):
         L = lib()
         rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
         ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
@@ -144,6 +149,8 @@ class Plan:
         opt.breakdown_restarts = int(breakdown_restarts)
         opt.inner_rtol = float(inner_rtol)
         opt.max_refine = int(max_refine)
+        opt.jit = int(bool(jit))
+        opt.autotune = int(bool(autotune))
         self.options = opt
         self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
         h = ctypes.c_void_p()
@@ -161,7 +168,25 @@ class Plan:
         v = [ctypes.c_int32() for _ in range(4)]
         _check(lib().bcs_plan_info(self._h, *[ctypes.byref(x) for x in v]))
         return dict(lanes_per_cell=v[0].value, rows_per_lane=v[1].value, steps_per_lane=v[2].value,
-                    cells_per_wg=v[3].value)
+                    cells_per_wg=v[3].value, jit=bool(self.options.jit))
+
+    def autotune(self, values, gamma, b, rtol: float = 1e-10, maxit: int = 200) -> int:
+        """Time every lanes-per-cell layout on this batch and keep the fastest; returns lanes per cell."""
+        torch = _torch()
+        values = _dev(values, torch.float64, "values", (values.shape[0], self.nnz))
+        C = values.shape[0]
+        _dev(b, torch.float64, "b", (C, self.n))
+        g, gs = _gamma_arg(gamma, C, values.device)
+        x = torch.empty((C, self.n), dtype=torch.float64, device=values.device)
+        it = torch.empty(C, dtype=torch.int32, device=values.device)
+        rs = torch.empty(C, dtype=torch.float64, device=values.device)
+        st = torch.empty(C, dtype=torch.int32, device=values.device)
+        lanes = ctypes.c_int32()
+        torch.cuda.synchronize()
+        _check(lib().bcs_plan_autotune(self._h, C, values.data_ptr(), g.data_ptr(), gs, b.data_ptr(), float(rtol),
+                                       int(maxit), x.data_ptr(), it.data_ptr(), rs.data_ptr(), st.data_ptr(),
+                                       ctypes.byref(lanes)))
+        return lanes.value
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -1,11 +1,14 @@
-// Host side of the library: pattern validation, schedule construction, plan
-// objects and the C-ABI entry points declared in include/bcs.h.
+// Host side of the library: pattern validation, schedule construction, kernel
+// selection (precompiled variants, or pattern-specialised kernels compiled at
+// plan creation), the layout autotuner, plan objects and the C-ABI entry
+// points declared in include/bcs.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -13,18 +16,12 @@
 
 #include "bcs_internal.h"
 
-namespace bcs {
-const Variant* variants_l16(int* count);
-const Variant* variants_l32(int* count);
-const Variant* variants_l64(int* count);
-}  // namespace bcs
-
 namespace {
 
 thread_local std::string g_err;
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
+  char buf[640];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof(buf), fmt, ap);
@@ -33,15 +30,18 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
     if (e_ != hipSuccess) return fail(BCS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+bool verbose() { return std::getenv("BCS_VERBOSE") != nullptr; }
 
 // Host form of a schedule (see DevSchedule).
 struct HostSchedule {
   int lanes = 0, rpl = 0, ksteps = 0;
+  std::vector<int> seg;  // slot segment lengths
   std::vector<int32_t> ent;
   std::vector<uint8_t> col;
   std::vector<int16_t> row;
@@ -52,8 +52,10 @@ struct HostSchedule {
 // pos[k]) to `rpl` slots of `lanes` lanes, longest rows first, and list each
 // lane's entries slot after slot.  Slot j spans the same LEN_j steps on every
 // lane, LEN_j = longest row in the slot (at least 1); shorter rows and absent
-// rows are padded with entries of value 0 that gather column 0, and the last
-// slot is extended so that every lane runs exactly kmax steps.
+// rows are padded with entries of value 0 that gather column 0.  If kmax > 0
+// the last slot is extended so that every lane runs exactly kmax steps (the
+// precompiled variants); kmax = 0 keeps the natural length (specialised
+// kernels).  ksteps > kmax on return means the pattern does not fit.
 HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector<int>& ci,
                             const std::vector<int>& pos, int lanes, int rpl, int kmax) {
   HostSchedule S;
@@ -77,11 +79,13 @@ HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector
   int ks = 0;
   for (int j = 0; j < rpl; ++j) ks += len[j];
   S.ksteps = ks;
-  if (ks > kmax) return S;  // does not fit; the caller checks ksteps
-  // pad the last slot so that every lane runs exactly kmax steps
-  len[rpl - 1] += kmax - ks;
-  ks = kmax;
-  S.ksteps = ks;
+  if (kmax > 0) {
+    if (ks > kmax) return S;
+    len[rpl - 1] += kmax - ks;
+    ks = kmax;
+    S.ksteps = ks;
+  }
+  S.seg = len;
   S.ent.assign((size_t)ks * lanes, bcs::kEntPad);
   S.col.assign((size_t)ks * lanes, 0);
   int s0 = 0;
@@ -99,93 +103,11 @@ HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector
     const int last = s0 + len[j] - 1;
     if (last < 64)
       S.flush[0] |= 1ull << last;
-    else
+    else if (last < 128)
       S.flush[1] |= 1ull << (last - 64);
     s0 += len[j];
   }
   return S;
-}
-
-struct DeviceSchedule {
-  bcs::DevSchedule d;
-  const bcs::Variant* var = nullptr;
-  int max_blocks = 0;  // resident workgroups per CU for this variant
-  void* buf = nullptr;
-};
-
-}  // namespace
-
-struct bcs_plan {
-  int n = 0, nnz = 0;
-  int device = 0;
-  int num_cu = 0;
-  bcs_options opt{};
-  std::vector<int> rp, ci;
-  DeviceSchedule fwd, adj;
-  int32_t* diag_pos = nullptr;
-  int16_t* coo_row = nullptr;
-  int16_t* coo_col = nullptr;
-  unsigned long long* queue = nullptr;  // [0..1] forward solves, [2..3] adjoint solves
-};
-
-namespace {
-
-const bcs::Variant* all_variants(int* count) {
-  static std::vector<bcs::Variant> all;
-  static std::once_flag once;
-  std::call_once(once, [] {
-    int c = 0;
-    const bcs::Variant* v = bcs::variants_l16(&c);
-    all.insert(all.end(), v, v + c);
-    v = bcs::variants_l32(&c);
-    all.insert(all.end(), v, v + c);
-    v = bcs::variants_l64(&c);
-    all.insert(all.end(), v, v + c);
-  });
-  *count = (int)all.size();
-  return all.data();
-}
-
-// Smallest compiled variant for `lanes` that holds the pattern; builds the
-// schedule for it.  Returns nullptr if none fits.
-const bcs::Variant* pick_variant(int n, const std::vector<int>& rp, const std::vector<int>& ci,
-                                 const std::vector<int>& pos, int lanes, HostSchedule* out) {
-  int nv = 0;
-  const bcs::Variant* vs = all_variants(&nv);
-  const int need_rpl = (n + lanes - 1) / lanes;
-  const bcs::Variant* best = nullptr;
-  for (int q = 0; q < nv; ++q) {
-    const bcs::Variant& v = vs[q];
-    if (v.lanes != lanes || v.rpl < need_rpl) continue;
-    HostSchedule S = build_schedule(n, rp, ci, pos, lanes, v.rpl, v.kmax);
-    if (S.ksteps > v.kmax) continue;
-    if (!best || v.rpl < best->rpl || (v.rpl == best->rpl && v.kmax < best->kmax)) {
-      best = &v;
-      *out = std::move(S);
-    }
-  }
-  return best;
-}
-
-int upload_schedule(const HostSchedule& S, const bcs::Variant* var, DeviceSchedule* D) {
-  const size_t ne = S.ent.size();
-  const size_t bytes = ne * 4 + ne + S.row.size() * 2 + 64;
-  void* buf = nullptr;
-  HIP_TRY(hipMalloc(&buf, bytes));
-  D->buf = buf;
-  char* p = (char*)buf;
-  HIP_TRY(hipMemcpy(p, S.ent.data(), ne * 4, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p + ne * 4, S.row.data(), S.row.size() * 2, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p + ne * 4 + S.row.size() * 2, S.col.data(), ne, hipMemcpyHostToDevice));
-  D->d.ent = (const int32_t*)p;
-  D->d.row = (const int16_t*)(p + ne * 4);
-  D->d.col = (const uint8_t*)(p + ne * 4 + S.row.size() * 2);
-  D->d.ksteps = S.ksteps;
-  D->d.rpl = S.rpl;
-  D->d.flush[0] = S.flush[0];
-  D->d.flush[1] = S.flush[1];
-  D->var = var;
-  return BCS_OK;
 }
 
 // LDS layout of one cell slot, in doubles: the SpMV operand (n values plus
@@ -206,33 +128,301 @@ SlotLayout slot_layout(int n, int lanes, int rpl, int adjoint) {
   return L;
 }
 
-size_t slot_lds_bytes(const bcs::Variant* v, int n, int adjoint) {
-  return (size_t)bcs::kWavesPerWg * (64 / v->lanes) * slot_layout(n, v->lanes, v->rpl, adjoint).stride *
-         sizeof(double);
+// Cell slots of the workgroup plus the LDS copy of the schedule entries.
+size_t lds_bytes(int n, int lanes, int rpl, int ksteps, int adjoint) {
+  return (size_t)bcs::kWavesPerWg * (64 / lanes) * slot_layout(n, lanes, rpl, adjoint).stride * sizeof(double) +
+         (size_t)ksteps * lanes * 4;
 }
 
-int occupancy(const bcs::Variant* v, int n, int adjoint, int* blocks) {
-  // gather addresses are 16-bit LDS byte addresses
-  if (slot_lds_bytes(v, n, adjoint) > 65536)
-    return fail(BCS_ERR_UNSUPPORTED, "workgroup LDS of %zu bytes exceeds 64 KiB", slot_lds_bytes(v, n, adjoint));
-  int nb = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fp64_kernel, bcs::kWgThreads,
-                                                       slot_lds_bytes(v, n, adjoint)));
-  *blocks = std::max(nb, 1);
+// Largest per-lane step count a specialised kernel is compiled for (the
+// matrix values of a lane's steps live in VGPRs).
+constexpr int kMaxJitSteps = 160;
+
+// One launchable solve kernel with its schedule on the device.
+struct Kernel {
+  int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
+  const bcs::Variant* var = nullptr;  // precompiled variant, or
+  bcs::JitKernel jit;                 // specialised kernel
+  int max_blocks = 1;                 // resident workgroups per CU
+  size_t lds = 0;
+  bcs::DevSchedule d{};
+  void* buf = nullptr;  // device schedule arrays
+
+  hipError_t launch(const bcs::KParams& P, int grid, hipStream_t stream) const {
+    if (var) return var->fp64(P, grid, stream);
+    bcs::KParams copy = P;
+    void* args[] = {&copy};
+    return hipModuleLaunchKernel(jit.fn, grid, 1, 1, bcs::kWgThreads, 1, 1, (unsigned)lds, stream, args, nullptr);
+  }
+};
+
+const bcs::Variant* all_variants(int* count) {
+  static std::vector<bcs::Variant> all;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int c = 0;
+    const bcs::Variant* v = bcs::variants_l16(&c);
+    all.insert(all.end(), v, v + c);
+    v = bcs::variants_l32(&c);
+    all.insert(all.end(), v, v + c);
+    v = bcs::variants_l64(&c);
+    all.insert(all.end(), v, v + c);
+  });
+  *count = (int)all.size();
+  return all.data();
+}
+
+int upload_schedule(const HostSchedule& S, Kernel* K) {
+  const size_t ne = S.ent.size();
+  const size_t bytes = ne * 4 + ne + S.row.size() * 2 + 64;
+  void* buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, bytes));
+  K->buf = buf;
+  char* p = (char*)buf;
+  HIP_TRY(hipMemcpy(p, S.ent.data(), ne * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + ne * 4, S.row.data(), S.row.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + ne * 4 + S.row.size() * 2, S.col.data(), ne, hipMemcpyHostToDevice));
+  K->d.ent = (const int32_t*)p;
+  K->d.row = (const int16_t*)(p + ne * 4);
+  K->d.col = (const uint8_t*)(p + ne * 4 + S.row.size() * 2);
+  K->d.ksteps = S.ksteps;
+  K->d.rpl = S.rpl;
+  K->d.flush[0] = S.flush[0];
+  K->d.flush[1] = S.flush[1];
   return BCS_OK;
 }
+
+void free_kernel(Kernel* K) {
+  if (K->buf) (void)hipFree(K->buf);
+  K->buf = nullptr;
+}
+
+// Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
+// Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
+int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
+                int lanes, int adjoint, bool use_jit, int waves_per_eu, Kernel* out) {
+  const int rpl = (n + lanes - 1) / lanes;
+  Kernel K;
+  K.lanes = lanes;
+  K.adjoint = adjoint;
+  HostSchedule S;
+  if (use_jit) {
+    S = build_schedule(n, rp, ci, pos, lanes, rpl, 0);
+    if (S.ksteps > kMaxJitSteps) return BCS_ERR_UNSUPPORTED;
+    K.rpl = rpl;
+    K.ksteps = S.ksteps;
+    K.lds = lds_bytes(n, lanes, rpl, S.ksteps, adjoint);
+    if (K.lds > 65536) return BCS_ERR_UNSUPPORTED;  // gather addresses are 16-bit
+    char err[512] = {0};
+    const int rc = bcs::jit_fp64_kernel(lanes, S.seg.data(), rpl, waves_per_eu, K.lds, &K.jit, err, sizeof(err));
+    if (rc != BCS_OK) return fail(rc, "%s", err);
+    K.max_blocks = K.jit.max_blocks;
+  } else {
+    int nv = 0;
+    const bcs::Variant* vs = all_variants(&nv);
+    const bcs::Variant* best = nullptr;
+    for (int q = 0; q < nv; ++q) {
+      const bcs::Variant& v = vs[q];
+      if (v.lanes != lanes || v.rpl < rpl) continue;
+      HostSchedule T = build_schedule(n, rp, ci, pos, lanes, v.rpl, v.kmax);
+      if (T.ksteps > v.kmax || lds_bytes(n, lanes, v.rpl, v.kmax, adjoint) > 65536) continue;
+      if (!best || v.rpl < best->rpl || (v.rpl == best->rpl && v.kmax < best->kmax)) {
+        best = &v;
+        S = std::move(T);
+      }
+    }
+    if (!best) return BCS_ERR_UNSUPPORTED;
+    K.var = best;
+    K.rpl = best->rpl;
+    K.ksteps = best->kmax;
+    K.lds = lds_bytes(n, lanes, best->rpl, best->kmax, adjoint);
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, best->fp64_kernel, bcs::kWgThreads, K.lds));
+    K.max_blocks = std::max(nb, 1);
+  }
+  // tuning override: resident workgroups per CU assumed when sizing the grid
+  if (const char* e = std::getenv("BCS_BLOCKS_PER_CU")) {
+    const int o = std::atoi(e);
+    if (o > 0) K.max_blocks = o;
+  }
+  const int rc = upload_schedule(S, &K);
+  if (rc != BCS_OK) {
+    free_kernel(&K);
+    return rc;
+  }
+  if (verbose())
+    std::fprintf(stderr, "[bcs] kernel %s lanes=%d rpl=%d steps=%d adjoint=%d lds=%zu blocks/CU=%d\n",
+                 use_jit ? "jit" : "precompiled", lanes, K.rpl, K.ksteps, adjoint, K.lds, K.max_blocks);
+  *out = K;
+  return BCS_OK;
+}
+
+}  // namespace
+
+struct bcs_plan {
+  int n = 0, nnz = 0;
+  int device = 0;
+  int num_cu = 0;
+  bcs_options opt{};
+  std::vector<int> rp, ci;
+  Kernel fwd, adj;
+  int32_t* diag_pos = nullptr;
+  int16_t* coo_row = nullptr;
+  int16_t* coo_col = nullptr;
+  unsigned long long* queue = nullptr;  // [0..1] forward solves, [2..3] adjoint solves
+};
+
+namespace {
 
 void release(bcs_plan* p) {
   if (!p) return;
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
-  if (p->fwd.buf) (void)hipFree(p->fwd.buf);
-  if (p->adj.buf) (void)hipFree(p->adj.buf);
+  free_kernel(&p->fwd);
+  free_kernel(&p->adj);
   if (p->diag_pos) (void)hipFree(p->diag_pos);
   if (p->coo_row) (void)hipFree(p->coo_row);
   if (p->queue) (void)hipFree(p->queue);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
+}
+
+bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
+                         int64_t gamma_stride, double rtol, int32_t maxit) {
+  bcs::KParams P{};
+  P.ncells = ncells;
+  P.n = p->n;
+  P.nnz = p->nnz;
+  P.values = values;
+  P.gamma = gamma;
+  P.gamma_stride = gamma_stride;
+  P.rtol = rtol;
+  P.maxit = maxit;
+  P.precond = p->opt.precond;
+  P.kind = p->opt.matrix_kind;
+  P.rr = p->opt.residual_replacement;
+  P.brs = p->opt.breakdown_restarts;
+  P.inner_rtol = p->opt.inner_rtol;
+  P.max_refine = p->opt.max_refine;
+  P.diag_pos = p->diag_pos;
+  P.coo_row = p->coo_row;
+  P.coo_col = p->coo_col;
+  return P;
+}
+
+int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
+  const int64_t cells_per_wg = (int64_t)bcs::kWavesPerWg * (64 / K.lanes);
+  const int64_t need = (ncells + cells_per_wg - 1) / cells_per_wg;
+  const int64_t cap = (int64_t)K.max_blocks * p->num_cu;
+  return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+// Fill the launch-specific fields and launch kernel K (forward or adjoint).
+int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, unsigned long long* queue, hipStream_t stream) {
+  P.sched = K.d;
+  P.adjoint = K.adjoint;
+  const SlotLayout L = slot_layout(p->n, K.lanes, K.rpl, K.adjoint);
+  P.xs = L.stride;
+  P.xoff2 = L.xoff2;
+  P.yoff = L.yoff;
+  P.queue = queue;
+  const int grid = grid_for(p, K, P.ncells);
+  P.total_waves = grid * bcs::kWavesPerWg;
+  const hipError_t e = K.launch(P, grid, stream);
+  if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve launch: %s", hipGetErrorString(e));
+  return BCS_OK;
+}
+
+// Time one launch of kernel K (forward) on a batch already on the device:
+// a warm-up launch, then the best of `reps` timed launches.
+int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P, int reps, double* seconds) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(BCS_ERR_HIP, "autotune: event creation failed");
+  }
+  double best = 1e300;
+  int rc = BCS_OK;
+  for (int rep = 0; rep <= reps && rc == BCS_OK; ++rep) {
+    (void)hipEventRecord(e0, nullptr);
+    rc = launch(p, K, P, p->queue, nullptr);
+    (void)hipEventRecord(e1, nullptr);
+    if (rc != BCS_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(BCS_ERR_HIP, "autotune launch failed");
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0) best = std::min(best, (double)ms * 1e-3);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *seconds = best;
+  return rc;
+}
+
+// Time kernel K on a synthetic batch of the plan's pattern.  Cell c has unit
+// diagonal and off-diagonal entries s_c * u / (row length), u uniform in
+// [-1, 1] and s_c uniform in [0, 0.95): row diagonally dominant, with a
+// spread of conditioning so that cells need widely different iteration
+// counts at rtol 1e-10 -- the regime in which slots refill at different
+// times.  Returns seconds per launch.
+int time_kernel_synthetic(const bcs_plan* p, const Kernel& K, double* seconds) {
+  const int64_t C = (int64_t)std::max(8192, 96 * p->num_cu);
+  const int n = p->n, nnz = p->nnz;
+  std::vector<double> hv((size_t)C * nnz), hb((size_t)C * n);
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  auto rnd = [&s]() {  // splitmix64 -> [0, 1)
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  for (int64_t c = 0; c < C; ++c) {
+    const double sc = 0.95 * rnd();
+    for (int i = 0; i < n; ++i) {
+      const int len = std::max(1, p->rp[i + 1] - p->rp[i] - 1);
+      for (int k = p->rp[i]; k < p->rp[i + 1]; ++k)
+        hv[(size_t)c * nnz + k] = (p->ci[k] == i) ? 1.0 : sc * (2.0 * rnd() - 1.0) / len;
+    }
+    for (int i = 0; i < n; ++i) hb[(size_t)c * n + i] = rnd() - 0.5;
+  }
+  double *dv = nullptr, *db = nullptr, *dg = nullptr, *dx = nullptr, *dr = nullptr;
+  int32_t *di = nullptr, *ds = nullptr;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)dv, (void*)db, (void*)dg, (void*)dx, (void*)dr, (void*)di, (void*)ds})
+      if (q) (void)hipFree(q);
+  };
+  hipError_t e = hipMalloc((void**)&dv, hv.size() * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&db, hb.size() * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&dg, 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&dx, hb.size() * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&dr, C * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&di, C * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&ds, C * 4);
+  if (e == hipSuccess) e = hipMemcpy(dv, hv.data(), hv.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db, hb.data(), hb.size() * 8, hipMemcpyHostToDevice);
+  const double g0 = 0.0;
+  if (e == hipSuccess) e = hipMemcpy(dg, &g0, 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(BCS_ERR_HIP, "autotune setup: %s", hipGetErrorString(e));
+  }
+  bcs::KParams P = base_params(p, C, dv, dg, 0, 1e-10, 200);
+  P.kind = bcs::kADirect;
+  P.b = db;
+  P.xin = dx;
+  P.x = dx;
+  P.iters = di;
+  P.resid = dr;
+  P.status = ds;
+  P.grad_a = nullptr;
+  const int rc = time_launches(p, K, P, 2, seconds);
+  cleanup();
+  return rc;
 }
 
 }  // namespace
@@ -252,6 +442,8 @@ void bcs_options_default(bcs_options* o) {
   o->breakdown_restarts = 1;
   o->inner_rtol = 1e-4;
   o->max_refine = 10;
+  o->jit = 1;
+  o->autotune = 1;
 }
 
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -264,7 +456,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (opt) o = *opt;
   if (n <= 0) return fail(BCS_ERR_ARG, "n must be positive (got %d)", n);
   if (nnz < 1) return fail(BCS_ERR_ARG, "nnz must be at least 1 (got %d)", nnz);
-  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(BCS_ERR_ARG, "row_ptr/col_idx is NULL");
+  if (!row_ptr || !col_idx) return fail(BCS_ERR_ARG, "row_ptr/col_idx is NULL");
   if (o.precision != BCS_FP64 && o.precision != BCS_FP32_REFINE)
     return fail(BCS_ERR_ARG, "unknown precision %d", o.precision);
   if (o.precond != BCS_PRECOND_NONE && o.precond != BCS_PRECOND_JACOBI)
@@ -279,7 +471,9 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     return fail(BCS_ERR_ARG, "breakdown_restarts must be in [0, 1000]");
   if (o.precision == BCS_FP32_REFINE && (!(o.inner_rtol > 0.0 && o.inner_rtol < 1.0) || o.max_refine < 1))
     return fail(BCS_ERR_ARG, "FP32_REFINE needs 0 < inner_rtol < 1 and max_refine >= 1");
-  for (int i = 0; i < 7; ++i)
+  if (o.jit != 0 && o.jit != 1) return fail(BCS_ERR_ARG, "jit must be 0 or 1");
+  if (o.autotune != 0 && o.autotune != 1) return fail(BCS_ERR_ARG, "autotune must be 0 or 1");
+  for (int i = 0; i < 5; ++i)
     if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
   // pattern
@@ -303,6 +497,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     for (int i = 0; i < n; ++i)
       if (diag[i] < 0) return fail(BCS_ERR_PATTERN, "row %d has no diagonal entry", i);
   if (n > 256) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 256 rows per cell", n);
+  if (o.precision != BCS_FP64) return fail(BCS_ERR_UNSUPPORTED, "FP32_REFINE is not available yet");
 
   bcs_plan* p = new bcs_plan();
   p->n = n;
@@ -317,6 +512,30 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
     delete p;
     return fail(BCS_ERR_HIP, "cannot query the compute unit count");
+  }
+
+  // device tables shared by every kernel of the plan
+  std::vector<int16_t> crow(nnz), ccol(nnz);
+  for (int i = 0; i < n; ++i)
+    for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
+      crow[k] = (int16_t)i;
+      ccol[k] = (int16_t)p->ci[k];
+    }
+  for (int i = 0; i < n; ++i) diag[i] = std::max(diag[i], 0);  // absent diagonal: never read, keep in bounds
+  hipError_t e = hipMalloc((void**)&p->diag_pos, sizeof(int32_t) * n);
+  if (e == hipSuccess) e = hipMemcpy(p->diag_pos, diag.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->coo_row, sizeof(int16_t) * 2 * nnz);
+  if (e == hipSuccess) {
+    p->coo_col = p->coo_row + nnz;
+    e = hipMemcpy(p->coo_row, crow.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(p->coo_col, ccol.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->queue, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(p->queue, 0, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    release(p);
+    return fail(BCS_ERR_HIP, "plan allocation: %s", hipGetErrorString(e));
   }
 
   // A and A^T patterns with value positions
@@ -335,60 +554,55 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
       }
   }
 
-  // lanes per cell: fewest wave-steps per cell among the variants that fit
-  HostSchedule fs, as;
-  const bcs::Variant* fv = nullptr;
-  const bcs::Variant* av = nullptr;
+  // Lanes per cell.  Candidates that fit are either timed on a synthetic
+  // batch (autotune) or ranked by wave-steps per cell (ksteps * lanes / 64).
+  const bool jit = o.jit == 1;
+  Kernel best;
   double best_cost = 1e300;
+  int rc = BCS_OK;
   const int cand[3] = {16, 32, 64};
   for (int L : cand) {
     if (o.lanes_per_cell != 0 && o.lanes_per_cell != L) continue;
-    HostSchedule f1, a1;
-    const bcs::Variant* v1 = pick_variant(n, p->rp, p->ci, pos, L, &f1);
-    const bcs::Variant* v2 = pick_variant(n, trp, tci, tpos, L, &a1);
-    if (!v1 || !v2) continue;
-    const double cost = (double)f1.ksteps * L / 64.0 + 0.25 * v1->rpl;
+    Kernel K;
+    g_err.clear();
+    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, &K);
+    if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
+    if (r != BCS_OK) {
+      rc = r;
+      break;
+    }
+    double cost = (double)K.ksteps * L / 64.0;
+    if (o.autotune == 1 && o.lanes_per_cell == 0) {
+      r = time_kernel_synthetic(p, K, &cost);
+      if (r != BCS_OK) {
+        free_kernel(&K);
+        rc = r;
+        break;
+      }
+      if (verbose()) std::fprintf(stderr, "[bcs] autotune lanes=%d: %.1f us per launch\n", L, cost * 1e6);
+    }
     if (cost < best_cost) {
+      free_kernel(&best);
+      best = K;
       best_cost = cost;
-      fv = v1;
-      av = v2;
-      fs = std::move(f1);
-      as = std::move(a1);
+    } else {
+      free_kernel(&K);
     }
   }
-  if (!fv) {
-    release(p);
-    return fail(BCS_ERR_UNSUPPORTED, "no compiled kernel variant holds this pattern (n = %d, nnz = %d)", n, nnz);
+  if (rc == BCS_OK && !best.buf)
+    rc = fail(BCS_ERR_UNSUPPORTED, "no kernel layout holds this pattern (n = %d, nnz = %d)", n, nnz);
+  if (rc == BCS_OK) {
+    p->fwd = best;
+    g_err.clear();
+    rc = make_kernel(n, trp, tci, tpos, best.lanes, 1, jit, 0, &p->adj);
+    if (rc == BCS_ERR_UNSUPPORTED && g_err.empty())
+      rc = fail(BCS_ERR_UNSUPPORTED, "no kernel layout holds the transposed pattern");
+  } else {
+    free_kernel(&best);
   }
-  int rc = upload_schedule(fs, fv, &p->fwd);
-  if (rc == BCS_OK) rc = upload_schedule(as, av, &p->adj);
-  if (rc == BCS_OK) rc = occupancy(fv, n, 0, &p->fwd.max_blocks);
-  if (rc == BCS_OK) rc = occupancy(av, n, 1, &p->adj.max_blocks);
   if (rc != BCS_OK) {
     release(p);
     return rc;
-  }
-  std::vector<int16_t> crow(std::max(nnz, 1)), ccol(std::max(nnz, 1));
-  for (int i = 0; i < n; ++i)
-    for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
-      crow[k] = (int16_t)i;
-      ccol[k] = (int16_t)p->ci[k];
-    }
-  for (int i = 0; i < n; ++i) diag[i] = std::max(diag[i], 0);  // absent diagonal: never read, keep in bounds
-  hipError_t e = hipMalloc((void**)&p->diag_pos, sizeof(int32_t) * n);
-  if (e == hipSuccess) e = hipMemcpy(p->diag_pos, diag.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->coo_row, sizeof(int16_t) * 2 * crow.size());
-  if (e == hipSuccess) {
-    p->coo_col = p->coo_row + crow.size();
-    e = hipMemcpy(p->coo_row, crow.data(), sizeof(int16_t) * crow.size(), hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess) e = hipMemcpy(p->coo_col, ccol.data(), sizeof(int16_t) * ccol.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->queue, 4 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMemset(p->queue, 0, 4 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    release(p);
-    return fail(BCS_ERR_HIP, "plan allocation: %s", hipGetErrorString(e));
   }
   *out = p;
   return BCS_OK;
@@ -396,12 +610,86 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
 
 void bcs_plan_destroy(bcs_plan* plan) { release(plan); }
 
+int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
+                      int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
+                      int32_t* iters, double* resid, int32_t* status, int32_t* lanes_out) {
+  g_err.clear();
+  if (!p) return fail(BCS_ERR_ARG, "plan is NULL");
+  if (ncells <= 0) return fail(BCS_ERR_ARG, "autotune needs ncells > 0");
+  if (!values || !b || !x || !iters || !resid || !status || (p->opt.matrix_kind == BCS_J_GAMMA && !gamma))
+    return fail(BCS_ERR_ARG, "values/gamma/b/x/iters/resid/status is NULL");
+  if (!(rtol > 0.0) || maxit < 1) return fail(BCS_ERR_ARG, "bad rtol/maxit");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+    return fail(BCS_ERR_ARG, "the plan belongs to device %d, current device is %d", p->device, cur);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(BCS_ERR_HIP, "device synchronisation failed");
+  bcs::KParams P = base_params(p, ncells, values, gamma, gamma_stride, rtol, maxit);
+  P.b = b;
+  P.x = x;
+  P.iters = iters;
+  P.resid = resid;
+  P.status = status;
+  P.refinements = nullptr;
+  std::vector<int> pos(p->nnz);
+  for (int k = 0; k < p->nnz; ++k) pos[k] = k;
+  const bool jit = p->opt.jit == 1;
+  int best_lanes = p->fwd.lanes;
+  double best = 1e300;
+  int rc = time_launches(p, p->fwd, P, 2, &best);
+  if (rc != BCS_OK) return rc;
+  if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
+  const int cand[3] = {16, 32, 64};
+  for (int L : cand) {
+    if (L == p->fwd.lanes) continue;
+    Kernel K;
+    g_err.clear();
+    int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, &K);
+    if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
+    if (r != BCS_OK) return r;
+    double t = 0;
+    r = time_launches(p, K, P, 2, &t);
+    if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", L, t * 1e6);
+    if (r != BCS_OK) {
+      free_kernel(&K);
+      return r;
+    }
+    if (t < best) {
+      best = t;
+      best_lanes = L;
+      free_kernel(&p->fwd);
+      p->fwd = K;
+    } else {
+      free_kernel(&K);
+    }
+  }
+  if (p->adj.lanes != best_lanes) {
+    std::vector<int> trp(p->n + 1, 0), tci(p->nnz), tpos(p->nnz);
+    for (int k = 0; k < p->nnz; ++k) trp[p->ci[k] + 1]++;
+    for (int j = 0; j < p->n; ++j) trp[j + 1] += trp[j];
+    std::vector<int> fill(trp.begin(), trp.end() - 1);
+    for (int i = 0; i < p->n; ++i)
+      for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
+        const int q = fill[p->ci[k]]++;
+        tci[q] = i;
+        tpos[q] = k;
+      }
+    Kernel A;
+    g_err.clear();
+    rc = make_kernel(p->n, trp, tci, tpos, best_lanes, 1, jit, 0, &A);
+    if (rc != BCS_OK) return g_err.empty() ? fail(rc, "no kernel layout holds the transposed pattern") : rc;
+    free_kernel(&p->adj);
+    p->adj = A;
+  }
+  if (lanes_out) *lanes_out = best_lanes;
+  return BCS_OK;
+}
+
 int bcs_plan_info(const bcs_plan* p, int32_t* lanes, int32_t* rpl, int32_t* steps, int32_t* cells_per_wg) {
   if (!p) return fail(BCS_ERR_ARG, "plan is NULL");
-  if (lanes) *lanes = p->fwd.var->lanes;
-  if (rpl) *rpl = p->fwd.d.rpl;
-  if (steps) *steps = p->fwd.d.ksteps;
-  if (cells_per_wg) *cells_per_wg = bcs::kWavesPerWg * (64 / p->fwd.var->lanes);
+  if (lanes) *lanes = p->fwd.lanes;
+  if (rpl) *rpl = p->fwd.rpl;
+  if (steps) *steps = p->fwd.ksteps;
+  if (cells_per_wg) *cells_per_wg = bcs::kWavesPerWg * (64 / p->fwd.lanes);
   return BCS_OK;
 }
 
@@ -412,7 +700,7 @@ static int check_common(const bcs_plan* p, int64_t ncells, const double* values,
   if (ncells > ((int64_t)1 << 40)) return fail(BCS_ERR_ARG, "ncells too large");
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(BCS_ERR_ARG, "rtol must be positive and finite");
   if (maxit < 1 || maxit > 1000000) return fail(BCS_ERR_ARG, "maxit must be in [1, 1000000]");
-  if (ncells > 0 && !values && p->nnz > 0) return fail(BCS_ERR_ARG, "values is NULL");
+  if (ncells > 0 && !values) return fail(BCS_ERR_ARG, "values is NULL");
   if (p->opt.matrix_kind == BCS_J_GAMMA) {
     if (ncells > 0 && !gamma) return fail(BCS_ERR_ARG, "gamma is NULL");
     if (gamma_stride < 0) return fail(BCS_ERR_ARG, "gamma_stride must be >= 0");
@@ -423,36 +711,6 @@ static int check_common(const bcs_plan* p, int64_t ncells, const double* values,
   return BCS_OK;
 }
 
-static bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
-                                int64_t gamma_stride, double rtol, int32_t maxit) {
-  bcs::KParams P{};
-  P.ncells = ncells;
-  P.n = p->n;
-  P.nnz = p->nnz;
-  P.values = values;
-  P.gamma = gamma;
-  P.gamma_stride = gamma_stride;
-  P.rtol = rtol;
-  P.maxit = maxit;
-  P.precond = p->opt.precond;
-  P.kind = p->opt.matrix_kind;
-  P.rr = p->opt.residual_replacement;
-  P.brs = p->opt.breakdown_restarts;
-  P.inner_rtol = p->opt.inner_rtol;
-  P.max_refine = p->opt.max_refine;
-  P.diag_pos = p->diag_pos;
-  P.coo_row = p->coo_row;
-  P.coo_col = p->coo_col;
-  return P;
-}
-
-static int grid_for(const bcs_plan* p, const DeviceSchedule& D, int64_t ncells) {
-  const int64_t cells_per_wg = (int64_t)bcs::kWavesPerWg * (64 / D.var->lanes);
-  const int64_t need = (ncells + cells_per_wg - 1) / cells_per_wg;
-  const int64_t cap = (int64_t)D.max_blocks * p->num_cu;
-  return (int)std::max<int64_t>(1, std::min(need, cap));
-}
-
 int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
                     int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x, int32_t* iters,
                     double* resid, int32_t* status, int32_t* refinements, void* stream) {
@@ -461,7 +719,6 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   if (rc != BCS_OK) return rc;
   if (ncells == 0) return BCS_OK;
   if (!b || !x || !iters || !resid || !status) return fail(BCS_ERR_ARG, "b/x/iters/resid/status is NULL");
-  if (p->opt.precision != BCS_FP64) return fail(BCS_ERR_UNSUPPORTED, "FP32_REFINE is not available yet");
   bcs::KParams P = base_params(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   P.b = b;
   P.x = x;
@@ -469,20 +726,7 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   P.resid = resid;
   P.status = status;
   P.refinements = refinements;
-  P.sched = p->fwd.d;
-  P.adjoint = 0;
-  {
-    const SlotLayout L = slot_layout(p->n, p->fwd.var->lanes, p->fwd.var->rpl, 0);
-    P.xs = L.stride;
-    P.xoff2 = L.xoff2;
-    P.yoff = L.yoff;
-  }
-  P.queue = p->queue;
-  const int grid = grid_for(p, p->fwd, ncells);
-  P.total_waves = grid * bcs::kWavesPerWg;
-  hipError_t e = p->fwd.var->fp64(P, grid, (hipStream_t)stream);
-  if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve launch: %s", hipGetErrorString(e));
-  return BCS_OK;
+  return launch(p, p->fwd, P, p->queue, (hipStream_t)stream);
 }
 
 int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
@@ -493,7 +737,7 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   int rc = check_common(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   if (rc != BCS_OK) return rc;
   if (ncells == 0) return BCS_OK;
-  if (!x || !g || !grad_b || !iters || !resid || !status || (!grad_A && p->nnz > 0))
+  if (!x || !g || !grad_b || !grad_A || !iters || !resid || !status)
     return fail(BCS_ERR_ARG, "x/g/grad_b/grad_A/iters/resid/status is NULL");
   bcs::KParams P = base_params(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   P.b = g;
@@ -504,20 +748,7 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
-  P.sched = p->adj.d;
-  P.adjoint = 1;
-  {
-    const SlotLayout L = slot_layout(p->n, p->adj.var->lanes, p->adj.var->rpl, 1);
-    P.xs = L.stride;
-    P.xoff2 = L.xoff2;
-    P.yoff = L.yoff;
-  }
-  P.queue = p->queue + 2;
-  const int grid = grid_for(p, p->adj, ncells);
-  P.total_waves = grid * bcs::kWavesPerWg;
-  hipError_t e = p->adj.var->fp64(P, grid, (hipStream_t)stream);
-  if (e != hipSuccess) return fail(BCS_ERR_HIP, "adjoint launch: %s", hipGetErrorString(e));
-  return BCS_OK;
+  return launch(p, p->adj, P, p->queue + 2, (hipStream_t)stream);
 }
 
 int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells,

@@ -10,7 +10,7 @@
 // cell's LDS slice, from which every lane gathers its columns.
 #pragma once
 
-#include "bcs_internal.h"
+#include "bcs_kdefs.h"
 
 namespace bcs {
 namespace dev {
@@ -92,56 +92,131 @@ constexpr int kGatherChunk = 8;
 template <int KMAX>
 constexpr int addr_words() { return (KMAX + 1) / 2; }
 
-// out = M * in for the cell's matrix held as schedule values a[] (this
-// lane's KMAX steps; padding steps hold 0) and packed LDS byte addresses
-// ad[] (two 16-bit addresses per word).  `in` and `out` are this lane's
-// owned rows (padding rows are staged into the spare element n of the
-// slice).  xb is the cell's operand slice, yb its result slice (RPL x LANES
-// elements, slot-major), lds the workgroup's LDS base.  The steps of slot j
-// end where bit s of (f0, f1) is set: the finished row sum is written to
-// yb[j*LANES + lane] (a uniform branch around one LDS store, so no register
-// array is indexed at run time), and the lane reads its RPL sums back.
-// Gathers are issued a chunk at a time, ahead of the chunk's FMAs.
-template <int LANES, int RPL, int KMAX, typename T>
-__device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
-                                     uint64_t f0_, uint64_t f1_, const char* lds, T* xb, T* yb, int gl,
-                                     const int (&rows)[RPL], const T (&in)[RPL], T (&out)[RPL]) {
-  constexpr int NW = addr_words<KMAX>();
-  const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
-  uint32_t ad[NW];
-  opaque_copy<NW>(ad_, ad);
+// Schedule policies.  Both run out = M * in for the cell's matrix held as
+// schedule values a[] (this lane's KMAX steps) and packed LDS byte addresses
+// ad[] (two 16-bit addresses per word).  `in` and `out` are this lane's owned
+// rows (padding rows are staged into the spare element n of the slice); xb is
+// the cell's operand slice, yb its result slice (RPL x LANES, slot-major),
+// lds the workgroup's LDS base.  Gathers are issued a chunk at a time, ahead
+// of the chunk's FMAs.
+
+// Slot boundaries known only at run time (precompiled generic variants): the
+// steps of slot j end where bit s of (f0, f1) is set; the finished row sum is
+// written to yb[j*LANES + lane] (a uniform branch around one LDS store, so no
+// register array is indexed at run time) and read back at the end.
+template <int LANES_, int RPL_, int KMAX_>
+struct DynSched {
+  static constexpr int LANES = LANES_, RPL = RPL_, KMAX = KMAX_;
+  uint64_t f0_, f1_;
+  __device__ explicit DynSched(const DevSchedule& d) : f0_(d.flush[0]), f1_(d.flush[1]) {}
+
+  template <typename T>
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
+                                       const char* lds, T* xb, T* yb, int gl, const int (&rows)[RPL],
+                                       const T (&in)[RPL], T (&out)[RPL]) const {
+    constexpr int NW = addr_words<KMAX>();
+    const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
+    uint32_t ad[NW];
+    opaque_copy<NW>(ad_, ad);
 #pragma unroll
-  for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
-  wave_sync();
-  T acc = 0;
-  T* ydst = yb + gl;
+    for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
+    wave_sync();
+    T acc = 0;
+    T* ydst = yb + gl;
 #pragma unroll
-  for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
-    constexpr int C = kGatherChunk;
-    T g[C];
+    for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
+      constexpr int C = kGatherChunk;
+      T g[C];
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-      const int s = s0 + i;
-      if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
-    }
+      for (int i = 0; i < C; ++i) {
+        const int s = s0 + i;
+        if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
+      }
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-      const int s = s0 + i;
-      if (s < KMAX) {
-        acc = __builtin_fma(a[s], g[i], acc);
-        if (flush_bit(f0, f1, s)) {
-          *ydst = acc;
-          ydst += LANES;
-          acc = 0;
+      for (int i = 0; i < C; ++i) {
+        const int s = s0 + i;
+        if (s < KMAX) {
+          acc = __builtin_fma(a[s], g[i], acc);
+          if (flush_bit(f0, f1, s)) {
+            *ydst = acc;
+            ydst += LANES;
+            acc = 0;
+          }
         }
       }
     }
-  }
-  wave_sync();
+    wave_sync();
 #pragma unroll
-  for (int j = 0; j < RPL; ++j) out[j] = yb[j * LANES + gl];
-  wave_sync();
-}
+    for (int j = 0; j < RPL; ++j) out[j] = yb[j * LANES + gl];
+    wave_sync();
+  }
+};
+
+// Slot segment lengths known at compile time (kernels compiled for one
+// pattern at plan creation): straight-line code, row sums land directly in
+// out[j].
+template <int LANES_, int... SEG>
+struct StaticSched {
+  static constexpr int LANES = LANES_;
+  static constexpr int RPL = sizeof...(SEG);
+  static constexpr int KMAX = (SEG + ...);
+  __device__ explicit StaticSched(const DevSchedule&) {}
+
+  // slot of step s, and whether s is the last step of its slot
+  static constexpr int slot_of(int s) {
+    constexpr int seg[RPL] = {SEG...};
+    int e = 0;
+    for (int j = 0; j < RPL; ++j) {
+      e += seg[j];
+      if (s < e) return j;
+    }
+    return RPL - 1;
+  }
+  static constexpr bool ends_slot(int s) {
+    constexpr int seg[RPL] = {SEG...};
+    int e = 0;
+    for (int j = 0; j < RPL; ++j) {
+      e += seg[j];
+      if (s == e - 1) return true;
+    }
+    return false;
+  }
+
+  template <typename T>
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
+                                       const char* lds, T* xb, T* /*yb*/, int /*gl*/, const int (&rows)[RPL],
+                                       const T (&in)[RPL], T (&out)[RPL]) const {
+    constexpr int NW = addr_words<KMAX>();
+    uint32_t ad[NW];
+    opaque_copy<NW>(ad_, ad);
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
+    wave_sync();
+    T acc = 0;
+#pragma unroll
+    for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
+      constexpr int C = kGatherChunk;
+      T g[C];
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        const int s = s0 + i;
+        if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
+      }
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        const int s = s0 + i;
+        if (s < KMAX) {
+          acc = __builtin_fma(a[s], g[i], acc);
+          if (ends_slot(s)) {
+            out[slot_of(s)] = acc;
+            acc = 0;
+          }
+        }
+      }
+    }
+    wave_sync();
+  }
+};
 
 template <int RPL, typename T>
 __device__ __forceinline__ T ldot(const T (&u)[RPL], const T (&v)[RPL]) {

@@ -24,10 +24,12 @@
 
 namespace bcs {
 
-template <int LANES, int RPL, int KMAX>
-__global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
+template <class S>
+__device__ __forceinline__ void fp64_body(const KParams& P) {
   using namespace dev;
+  constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
   constexpr int G = 64 / LANES;
+  const S sch(P.sched);
   constexpr int NW = addr_words<KMAX>();
   extern __shared__ double lds[];
   const char* ldsb = (const char*)lds;
@@ -39,7 +41,6 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
   double* xb = lds + slot_base;          // SpMV operand (n + spare)
   double* yb = xb + P.yoff;               // SpMV result, slot-major RPL x LANES
 
-  const uint64_t f0 = P.sched.flush[0], f1 = P.sched.flush[1];
   const int n = P.n, nnz = P.nnz;
 
   // This lane's LDS gather addresses (the schedule is shared by every cell
@@ -63,6 +64,15 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
     rows[j] = rj >= 0 ? rj : n;
   }
 
+  // The schedule's value positions, shared by every cell slot of the
+  // workgroup, copied once into LDS after the cell slots.
+  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
+  for (int i = threadIdx.x; i < KMAX * LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
+  __syncthreads();
+  int dpos[RPL];  // CSR position of the diagonal of each owned row
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) dpos[j] = P.diag_pos[rows[j] < n ? rows[j] : 0] & kEntPosMask;
+
   double a[KMAX];
   // Krylov state of this lane's rows.  With Jacobi the matrix is staged
   // column-scaled (Ahat = A D^-1, right preconditioning), so xv holds
@@ -75,11 +85,10 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
 
   // diag(A)^-1 of this lane's rows (0 for padding rows).
   auto diag_inv = [&](int j) -> double {
-    const bool real = rows[j] < n;
-    const double dv = P.values[cell * nnz + (P.diag_pos[real ? rows[j] : 0] & kEntPosMask)];
-    const double g = (P.kind == BCS_J_GAMMA) ? P.gamma[cell * P.gamma_stride] : 0.0;
-    const double d = (P.kind == BCS_J_GAMMA) ? 1.0 - g * dv : dv;
-    return real ? 1.0 / d : 0.0;
+    const double dvj = P.values[cell * nnz + dpos[j]];
+    const double g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
+    const double d = (P.kind == kJGamma) ? 1.0 - g * dvj : dvj;
+    return rows[j] < n ? 1.0 / d : 0.0;
   };
 
   // Write the cell's outputs and free the slot.
@@ -132,23 +141,38 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
         dead = true;
       } else {
         cell = (int64_t)c;
-        // Stage the cell: A = I - gamma J (or A) into registers, b, diag(A)^-1.
-        // Loads are unconditional (padding entries read position 0 and are
-        // zeroed) so that they issue back to back.
+        // Stage the cell: A = I - gamma J (or A) into registers, b, and the
+        // Jacobi column scaling.  Value positions come from the LDS copy of
+        // the schedule, so every global load of the cell is independent and
+        // they all issue back to back (one memory latency per refill).
         const double* vals = P.values + cell * nnz;
-        const double g = (P.kind == BCS_J_GAMMA) ? P.gamma[cell * P.gamma_stride] : 0.0;
+        const double g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) a[s] = vals[ent_lds[s * LANES + gl] & kEntPosMask];
+        const double* bc = P.b + cell * n;
+        double dv[RPL];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const bool real = rows[j] < n;
+          const double bj = bc[real ? rows[j] : 0];
+          dv[j] = vals[dpos[j]];
+          r[j] = real ? bj : 0.0;
+          xv[j] = 0;
+        }
+        asm volatile("" ::: "memory");  // re-read the flags below instead of keeping them live
 #pragma unroll
         for (int s = 0; s < KMAX; ++s) {
-          const int32_t e = P.sched.ent[s * LANES + gl];
-          const double jv = vals[e & kEntPosMask];
-          const double av = (P.kind == BCS_J_GAMMA) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
+          const int32_t e = ent_lds[s * LANES + gl];
+          const double av = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * a[s]) : a[s];
           a[s] = (e & kEntPad) ? 0.0 : av;
-          if ((s % kGatherChunk) == kGatherChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
         if (P.precond) {
           // column scaling by diag(A)^-1, gathered through the LDS slice
 #pragma unroll
-          for (int j = 0; j < RPL; ++j) xb[rows[j]] = diag_inv(j);
+          for (int j = 0; j < RPL; ++j) {
+            const double d = (P.kind == kJGamma) ? 1.0 - g * dv[j] : dv[j];
+            xb[rows[j]] = (rows[j] < n) ? 1.0 / d : 0.0;
+          }
           wave_sync();
           uint32_t ado[NW];
           opaque_copy<NW>(ad, ado);
@@ -156,23 +180,15 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
           for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr(ado, s));
           wave_sync();
         }
-        const double* bc = P.b + cell * n;
-#pragma unroll
-        for (int j = 0; j < RPL; ++j) {
-          const bool real = rows[j] < n;
-          const double bj = bc[real ? rows[j] : 0];
-          r[j] = real ? bj : 0.0;
-          xv[j] = 0;
-        }
         bn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
         it = 0;
         restarts_left = P.brs;
         restart();
         active = true;
         if (!finite(bn)) {
-          finish(BCS_NONFINITE, __builtin_nan(""));
+          finish(kNonfinite, __builtin_nan(""));
         } else if (bn == 0.0) {
-          finish(BCS_CONVERGED, 0.0);
+          finish(kConverged, 0.0);
         }
       }
     }
@@ -181,12 +197,12 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
 
     // ---- one BiCGStab iteration of this slot's cell ----
     ++it;
-    int ended = -1;  // -1 = continue, else BCS_CONVERGED / BCS_BREAKDOWN / BCS_NONFINITE
+    int ended = -1;  // -1 = continue, else kConverged / kBreakdown / kNonfinite
     const double rho = gsum<LANES>(ldot<RPL>(rh, r));
     if (!finite(rho)) {
-      ended = BCS_NONFINITE;
+      ended = kNonfinite;
     } else if (rho == 0.0) {
-      ended = BCS_BREAKDOWN;
+      ended = kBreakdown;
     } else {
       if (first) {
 #pragma unroll
@@ -197,31 +213,31 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       }
-      spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, p, v);
+      sch.spmv(a, ad, ldsb, xb, yb, gl, rows, p, v);
       const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
       if (!finite(sigma)) {
-        ended = BCS_NONFINITE;
+        ended = kNonfinite;
       } else if (sigma == 0.0) {
-        ended = BCS_BREAKDOWN;
+        ended = kBreakdown;
       } else {
         alpha = rho / sigma;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
         const double sn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
         if (!finite(sn)) {
-          ended = BCS_NONFINITE;
+          ended = kNonfinite;
         } else if (sn / bn <= P.rtol) {
 #pragma unroll
           for (int j = 0; j < RPL; ++j) xv[j] = xv[j] + alpha * p[j];
-          ended = BCS_CONVERGED;
+          ended = kConverged;
         } else {
-          spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, r, t);
+          sch.spmv(a, ad, ldsb, xb, yb, gl, rows, r, t);
           const double tt = gsum<LANES>(ldot<RPL>(t, t));
           const double ts = gsum<LANES>(ldot<RPL>(t, r));
           if (!finite(tt)) {
-            ended = BCS_NONFINITE;
+            ended = kNonfinite;
           } else if (tt == 0.0) {
-            ended = BCS_BREAKDOWN;
+            ended = kBreakdown;
           } else {
             omega = ts / tt;
 #pragma unroll
@@ -231,11 +247,11 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
             }
             const double rn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
             if (!finite(rn)) {
-              ended = BCS_NONFINITE;
+              ended = kNonfinite;
             } else if (rn / bn <= P.rtol) {
-              ended = BCS_CONVERGED;
+              ended = kConverged;
             } else if (omega == 0.0) {
-              ended = BCS_BREAKDOWN;
+              ended = kBreakdown;
             } else {
               rho_prev = rho;
             }
@@ -243,10 +259,10 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
         }
       }
     }
-    if (ended < 0 && it >= P.maxit) ended = BCS_MAXIT;
+    if (ended < 0 && it >= P.maxit) ended = kMaxit;
     if (ended >= 0) {
       // The true residual of the current iterate decides (t is free here).
-      spmv<LANES, RPL, KMAX>(a, ad, f0, f1, ldsb, xb, yb, gl, rows, xv, t);
+      sch.spmv(a, ad, ldsb, xb, yb, gl, rows, xv, t);
       {
         const double* bc = P.b + cell * n;
 #pragma unroll
@@ -257,17 +273,17 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
         }
       }
       const double res = __builtin_sqrt(gsum<LANES>(ldot<RPL>(t, t))) / bn;
-      if (ended == BCS_NONFINITE || !finite(res)) {
-        finish(BCS_NONFINITE, res);
+      if (ended == kNonfinite || !finite(res)) {
+        finish(kNonfinite, res);
       } else if (res <= P.rtol) {
-        finish(BCS_CONVERGED, res);
-      } else if (it < P.maxit && ((ended == BCS_CONVERGED && P.rr) || (ended == BCS_BREAKDOWN && restarts_left > 0))) {
-        if (ended == BCS_BREAKDOWN) --restarts_left;
+        finish(kConverged, res);
+      } else if (it < P.maxit && ((ended == kConverged && P.rr) || (ended == kBreakdown && restarts_left > 0))) {
+        if (ended == kBreakdown) --restarts_left;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = t[j];
         restart();
       } else {
-        finish(ended == BCS_BREAKDOWN ? BCS_BREAKDOWN : BCS_MAXIT, res);
+        finish(ended == kBreakdown ? kBreakdown : kMaxit, res);
       }
     }
   }
@@ -282,11 +298,19 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
   }
 }
 
+// Precompiled generic variant (segment boundaries read at run time).
+template <int LANES, int RPL, int KMAX>
+__global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
+  fp64_body<dev::DynSched<LANES, RPL, KMAX>>(P);
+}
+
+#ifndef __HIPCC_RTC__
 template <int LANES, int RPL, int KMAX>
 hipError_t launch_fp64(const KParams& P, int grid, hipStream_t stream) {
-  const size_t lds = (size_t)kWavesPerWg * (64 / LANES) * P.xs * sizeof(double);
+  const size_t lds = (size_t)kWavesPerWg * (64 / LANES) * P.xs * sizeof(double) + (size_t)KMAX * LANES * 4;
   hipLaunchKernelGGL((k_fp64<LANES, RPL, KMAX>), dim3(grid), dim3(kWgThreads), lds, stream, P);
   return hipGetLastError();
 }
+#endif
 
 }  // namespace bcs

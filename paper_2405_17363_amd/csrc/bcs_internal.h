@@ -1,76 +1,21 @@
-// Internal definitions shared by the host plan code and the gfx950 kernels.
+// Host-side internal definitions: the registry of precompiled kernel variants.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/bcs.h"
+#include "bcs_kdefs.h"
 
 namespace bcs {
 
-// Largest number of row slots per lane and schedule steps per lane that any
-// compiled kernel variant handles.
-constexpr int kMaxRpl = 8;
-constexpr int kMaxSteps = 128;
-// Waves per workgroup of every solve kernel.  Each wave works on its own
-// cells with its own LDS slice, so the waves never synchronise.
-constexpr int kWavesPerWg = 4;
-constexpr int kWgThreads = 64 * kWavesPerWg;
+static_assert(kConverged == BCS_CONVERGED && kMaxit == BCS_MAXIT && kBreakdown == BCS_BREAKDOWN &&
+                  kNonfinite == BCS_NONFINITE,
+              "status codes");
+static_assert(kJGamma == BCS_J_GAMMA && kADirect == BCS_A_DIRECT, "matrix kinds");
 
-// Schedule entry: value position in the cell's CSR array, plus flags.
-constexpr int32_t kEntDiag = 1 << 30;  // the entry is a diagonal position
-constexpr int32_t kEntPad = 1 << 29;   // padding step (value 0; reads position 0)
-constexpr int32_t kEntPosMask = kEntPad - 1;
-
-// Schedule of one matrix (A, or A^T for the adjoint) for one lanes-per-cell
-// choice.  Rows are dealt to (slot j, lane l) in the order of decreasing row
-// length (a sliced-ELL layout with slice height = lanes per cell), so every
-// slot j spans the same steps [seg_begin_j, seg_end_j) on every lane.
-struct DevSchedule {
-  const int32_t* ent = nullptr;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
-  const uint8_t* col = nullptr;   // [ksteps * lanes] gathered vector index (row of the other operand)
-  const int16_t* row = nullptr;   // [rpl * lanes] row owned by slot j of lane l, -1 = none
-  int32_t ksteps = 0;             // steps per lane (sum of slot segment lengths)
-  int32_t rpl = 0;                // row slots per lane
-  uint64_t flush[2] = {0, 0};     // bit s set: a slot's segment ends after step s
-};
-
-// Everything a solve kernel needs, passed by value.
-struct KParams {
-  int64_t ncells;
-  int32_t n, nnz;
-  const double* values;
-  const double* gamma;
-  int64_t gamma_stride;
-  const double* b;
-  const double* xin;   // adjoint: forward solution x
-  double rtol;
-  int32_t maxit;
-  int32_t precond;
-  int32_t kind;
-  int32_t rr;
-  int32_t brs;
-  double inner_rtol;
-  int32_t max_refine;
-  double* x;           // solution (adjoint: lambda)
-  double* grad_a;      // adjoint only: dL/dA on the pattern
-  int32_t* iters;
-  double* resid;
-  int32_t* status;
-  int32_t* refinements;
-  const int32_t* diag_pos;  // [n] CSR position of the diagonal, -1 if absent
-  DevSchedule sched;        // schedule of the solved matrix (A, or A^T for the adjoint)
-  const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
-  const int16_t* coo_col;   // [nnz] column of each CSR position
-  int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
-  unsigned long long* queue;  // [0] next cell, [1] finished waves
-  int32_t total_waves;
-  int32_t xs;               // LDS elements per cell slot (double or float)
-  int32_t xoff2;            // offset of a second n-vector within the slot (adjoint, mixed)
-  int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the slot
-};
-
-// Kernel variants: (lanes per cell, row slots per lane, max steps per lane).
+// Precompiled variants: (lanes per cell, row slots per lane, max steps per
+// lane), with the slot segment boundaries read at run time.
 using LaunchFn = hipError_t (*)(const KParams&, int grid, hipStream_t stream);
 
 struct Variant {
@@ -80,7 +25,21 @@ struct Variant {
   const void* fp64_kernel;  // for occupancy queries
 };
 
-// Registry of compiled variants (defined in the kernel translation units).
-const Variant* variants(int* count);
+const Variant* variants_l16(int* count);
+const Variant* variants_l32(int* count);
+const Variant* variants_l64(int* count);
+
+// Kernels specialised for one pattern's exact slot segments, compiled at
+// plan creation with hipRTC (bcs_jit.cpp).
+struct JitKernel {
+  hipFunction_t fn = nullptr;
+  int max_blocks = 0;  // resident workgroups per CU
+};
+
+// Compile (or fetch from the cache) the FP64 solve kernel for `lanes` lanes
+// per cell and slot segment lengths seg[0..rpl).  Returns BCS_OK or an error
+// code with the message in `err`.
+int jit_fp64_kernel(int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes, JitKernel* out,
+                    char* err, size_t errlen);
 
 }  // namespace bcs

@@ -1,0 +1,179 @@
+// Pattern-specialised solve kernels compiled at plan creation with hipRTC.
+//
+// The precompiled variants read a pattern's slot segment boundaries at run
+// time, which costs a scalar test and branch on every SpMV step and pads every
+// lane to the variant's step count.  A plan instead compiles the same kernel
+// body with its exact segment lengths as template constants, so that each SpMV
+// is straight-line code.  Compiled code objects are cached in memory for the
+// process and on disk (directory $BCS_JIT_CACHE, else $HOME/.cache/bcs_jit,
+// else /tmp/bcs_jit), keyed by a hash of the generated source, the compile
+// options and the device architecture.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "bcs_internal.h"
+#include "bcs_jit_sources.inc"  // kJitHeaderCount, kJitHeaderNames[], kJitHeaderSources[], kJitSourceHash
+
+namespace bcs {
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, JitKernel> g_cache;
+
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string cache_dir() {
+  if (const char* d = std::getenv("BCS_JIT_CACHE")) return d;
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/bcs_jit";
+  return "/tmp/bcs_jit";
+}
+
+void mkdirs(const std::string& path) {
+  std::string cur;
+  std::stringstream ss(path);
+  std::string part;
+  if (!path.empty() && path[0] == '/') cur = "/";
+  while (std::getline(ss, part, '/')) {
+    if (part.empty()) continue;
+    cur += part + "/";
+    mkdir(cur.c_str(), 0755);
+  }
+}
+
+bool read_file(const std::string& path, std::vector<char>* out) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return false;
+  out->assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+  return !out->empty();
+}
+
+void write_file_atomic(const std::string& path, const std::vector<char>& data) {
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(data.data(), (std::streamsize)data.size());
+    if (!f) return;
+  }
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+int compile(const std::string& src, const std::string& arch, std::vector<char>* code, std::string* log) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "bcs_jit.hip", kJitHeaderCount, kJitHeaderSources,
+                          kJitHeaderNames) != HIPRTC_SUCCESS) {
+    *log = "hiprtcCreateProgram failed";
+    return -1;
+  }
+  const std::string arch_opt = "--offload-arch=" + arch;
+  const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  size_t ls = 0;
+  hiprtcGetProgramLogSize(prog, &ls);
+  if (ls > 1) {
+    std::vector<char> buf(ls + 1, 0);
+    hiprtcGetProgramLog(prog, buf.data());
+    *log = buf.data();
+  }
+  if (r != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return -1;
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code->resize(cs);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return 0;
+}
+
+}  // namespace
+
+int jit_fp64_kernel(int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes, JitKernel* out,
+                    char* err, size_t errlen) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    snprintf(err, errlen, "no HIP device");
+    return BCS_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    snprintf(err, errlen, "cannot query device properties");
+    return BCS_ERR_HIP;
+  }
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  const std::string base_arch = arch.substr(0, colon);
+
+  std::ostringstream src;
+  src << "#include \"bcs_fp64.h\"\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
+  if (waves_per_eu > 0) src << ", " << waves_per_eu;
+  src << ") bcs_jit_kernel(bcs::KParams P) {\n"
+      << "  bcs::fp64_body<bcs::dev::StaticSched<" << lanes;
+  for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
+  src << ">>(P);\n}\n";
+  const std::string source = src.str();
+  const std::string key = std::string(kJitSourceHash) + "|" + arch + "|" + source;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  const std::string mkey = std::to_string(dev) + "|" + key;
+  auto it = g_cache.find(mkey);
+  if (it == g_cache.end()) {
+    char name[64];
+    snprintf(name, sizeof(name), "%016llx.co", (unsigned long long)fnv1a(key));
+    const std::string dir = cache_dir();
+    const std::string path = dir + "/" + name;
+    std::vector<char> code;
+    if (!read_file(path, &code)) {
+      std::string log;
+      if (compile(source, base_arch, &code, &log) != 0) {
+        snprintf(err, errlen, "hipRTC compile failed: %.400s", log.c_str());
+        return BCS_ERR_HIP;
+      }
+      mkdirs(dir);
+      write_file_atomic(path, code);
+    }
+    hipModule_t mod;
+    if (hipModuleLoadData(&mod, code.data()) != hipSuccess) {
+      snprintf(err, errlen, "hipModuleLoadData failed for the compiled kernel");
+      return BCS_ERR_HIP;
+    }
+    JitKernel k;
+    if (hipModuleGetFunction(&k.fn, mod, "bcs_jit_kernel") != hipSuccess) {
+      snprintf(err, errlen, "compiled kernel not found in module");
+      return BCS_ERR_HIP;
+    }
+    it = g_cache.emplace(mkey, k).first;
+  }
+  JitKernel k = it->second;
+  int nb = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.fn, kWgThreads, lds_bytes) != hipSuccess) {
+    snprintf(err, errlen, "occupancy query failed");
+    return BCS_ERR_HIP;
+  }
+  k.max_blocks = nb > 0 ? nb : 1;
+  *out = k;
+  return BCS_OK;
+}
+
+}  // namespace bcs

@@ -1,0 +1,87 @@
+// Definitions shared by the host code and the gfx950 kernels.  Safe to
+// compile both with hipcc and with the runtime compiler (hipRTC), which has
+// no standard headers.
+#pragma once
+
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#else
+using __hip_internal::int16_t;
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+using __hip_internal::uint8_t;
+#endif
+
+namespace bcs {
+
+// per-cell status (values of BCS_CONVERGED .. BCS_NONFINITE)
+constexpr int kConverged = 0;
+constexpr int kMaxit = 1;
+constexpr int kBreakdown = 2;
+constexpr int kNonfinite = 3;
+// matrix kinds (values of BCS_J_GAMMA, BCS_A_DIRECT)
+constexpr int kJGamma = 0;
+constexpr int kADirect = 1;
+
+// Waves per workgroup of every solve kernel.  Each wave works on its own
+// cells with its own LDS slice; the waves synchronise once, at kernel start.
+constexpr int kWavesPerWg = 4;
+constexpr int kWgThreads = 64 * kWavesPerWg;
+
+// Schedule entry: value position in the cell's CSR array, plus flags.
+constexpr int32_t kEntDiag = 1 << 30;  // the entry is a diagonal position
+constexpr int32_t kEntPad = 1 << 29;   // padding step (value 0; reads position 0)
+constexpr int32_t kEntPosMask = kEntPad - 1;
+
+// Schedule of one matrix (A, or A^T for the adjoint) for one lanes-per-cell
+// choice.  Rows are dealt to (slot j, lane l) in the order of decreasing row
+// length (a sliced-ELL layout with slice height = lanes per cell), so every
+// slot j spans the same steps [seg_begin_j, seg_end_j) on every lane.
+struct DevSchedule {
+  const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
+  const uint8_t* col;   // [ksteps * lanes] gathered vector index (row of the other operand)
+  const int16_t* row;   // [rpl * lanes] row owned by slot j of lane l, -1 = none
+  int32_t ksteps;       // steps per lane (sum of slot segment lengths)
+  int32_t rpl;          // row slots per lane
+  uint64_t flush[2];    // bit s set: a slot's segment ends after step s
+};
+
+// Everything a solve kernel needs, passed by value.
+struct KParams {
+  int64_t ncells;
+  int32_t n, nnz;
+  const double* values;
+  const double* gamma;
+  int64_t gamma_stride;
+  const double* b;
+  const double* xin;   // adjoint: forward solution x
+  double rtol;
+  int32_t maxit;
+  int32_t precond;
+  int32_t kind;
+  int32_t rr;
+  int32_t brs;
+  double inner_rtol;
+  int32_t max_refine;
+  double* x;           // solution (adjoint: lambda)
+  double* grad_a;      // adjoint only: dL/dA on the pattern
+  int32_t* iters;
+  double* resid;
+  int32_t* status;
+  int32_t* refinements;
+  const int32_t* diag_pos;  // [n] CSR position of the diagonal (0 if absent)
+  DevSchedule sched;        // schedule of the solved matrix (A, or A^T for the adjoint)
+  const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
+  const int16_t* coo_col;   // [nnz] column of each CSR position
+  int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
+  unsigned long long* queue;  // [0] next cell, [1] finished waves
+  int32_t total_waves;
+  int32_t xs;               // LDS elements per cell slot (doubles)
+  int32_t xoff2;            // offset of a second n-vector within the slot (adjoint)
+  int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the slot
+};
+
+}  // namespace bcs

@@ -3,6 +3,7 @@
 // every (rows per lane, max steps per lane) pair below and exports them.
 #pragma once
 
+#include "bcs_internal.h"
 #include "bcs_fp64.h"
 
 #ifndef BCS_LANES

@@ -1,0 +1,167 @@
+"""GPU adjoint: transposed batched BiCGStab and dL/dA, dL/db, dL/dJ, dL/dgamma.
+
+lambda = A^-T g is compared with the oracle's dense LU of A^T within the
+residual-implied bound; dL/dA_ij = -lambda_i x_j is checked exactly from the
+GPU's own lambda and x; duality g.x = lambda.b; central finite differences of
+L = w.x (dense-LU evaluations, relative steps 1e-6 |A_k|) on 16 sampled cells;
+and the autograd chain rule to J and gamma against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workload import config_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_17363_amd as bcs  # noqa: E402
+
+RTOL = 1e-10
+
+
+def gpu(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def cfg5():
+    mech, cells = config_inputs(5)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    V, G, B, W = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"]), gpu(cells["w"])
+    x, it, res, st, _ = bcs.solve_batch(plan, V, G, B, RTOL, 200)
+    gb, gA, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, W, RTOL, 200)
+    torch.cuda.synchronize()
+    out = dict(x=x.cpu().numpy(), st=st.cpu().numpy(), gb=gb.cpu().numpy(), gA=gA.cpu().numpy(),
+               ait=ait.cpu().numpy(), ares=ares.cpu().numpy(), ast=ast.cpu().numpy())
+    return mech, cells, plan, out
+
+
+def test_adjoint_lambda_matches_transposed_lu(cfg5):
+    mech, cells, plan, o = cfg5
+    rp, ci = mech.row_ptr, mech.col_idx
+    assert np.mean(o["ast"] == bcs.BCS_CONVERGED) >= 0.99
+    assert np.all(o["ares"][o["ast"] == 0] <= RTOL)
+    rng = np.random.default_rng(55)
+    sample = np.sort(rng.choice(len(o["st"]), 300, replace=False))
+    lam, info = oracle.lu_batch(rp, ci, cells["values"][sample], cells["gamma"][sample], cells["w"][sample],
+                                transpose=True)
+    for q, c in enumerate(sample):
+        if o["ast"][c] != 0:
+            continue
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        kappa = np.linalg.cond(A)
+        rlu = np.linalg.norm(cells["w"][c] - A.T @ lam[q]) / np.linalg.norm(cells["w"][c])
+        err = np.linalg.norm(o["gb"][c] - lam[q]) / np.linalg.norm(lam[q])
+        assert err <= max(1e-8, 4 * kappa * max(o["ares"][c], rlu)), (c, err, kappa)
+
+
+def test_adjoint_matches_oracle_adjoint_statuses(cfg5):
+    mech, cells, plan, o = cfg5
+    gb, gA, it, res, st = oracle.adjoint_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], o["x"],
+                                               cells["w"], precond=1)
+    assert np.mean(st == o["ast"]) >= 0.99
+    both = (st == 0) & (o["ast"] == 0)
+    close = np.abs(it[both] - o["ait"][both]) <= np.maximum(3, 0.15 * it[both])
+    assert np.mean(close) >= 0.95
+
+
+def test_pattern_gradient_is_minus_lambda_x(cfg5):
+    mech, cells, plan, o = cfg5
+    rows = np.repeat(np.arange(mech.n), np.diff(mech.row_ptr))
+    expect = -o["gb"][:, rows] * o["x"][:, mech.col_idx]
+    assert np.array_equal(o["gA"], expect)
+
+
+def test_duality(cfg5):
+    mech, cells, plan, o = cfg5
+    ok = (o["st"] == 0) & (o["ast"] == 0)
+    lhs = np.sum(cells["w"] * o["x"], axis=1)
+    rhs = np.sum(o["gb"] * cells["b"], axis=1)
+    scale = (np.linalg.norm(cells["w"], axis=1) * np.linalg.norm(o["x"], axis=1)
+             + np.linalg.norm(o["gb"], axis=1) * np.linalg.norm(cells["b"], axis=1))
+    assert np.all(np.abs(lhs - rhs)[ok] <= 1e-8 * scale[ok])
+
+
+def test_central_finite_differences_on_16_cells(cfg5):
+    mech, cells, plan, o = cfg5
+    rp, ci = mech.row_ptr, mech.col_idx
+    rng = np.random.Generator(np.random.PCG64(5))
+    cells_fd = rng.choice(len(o["st"]), 16, replace=False)
+    for c in cells_fd:
+        if o["ast"][c] != 0:
+            continue
+        A = oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c])
+        w, b = cells["w"][c], cells["b"][c]
+
+        def L(Av, bv):
+            xx, _ = oracle.lu_batch(rp, ci, Av[None], [0.0], bv[None], kind=oracle.A_DIRECT)
+            return float(w @ xx[0])
+
+        gA = o["gA"][c]
+        L0 = abs(L(A, b))
+        amax = np.abs(gA).max()
+        resolvable = np.nonzero(1e-6 * np.abs(A * gA) > 1e-8 * L0)[0]
+        for k in rng.choice(resolvable, size=min(8, resolvable.size), replace=False):
+            eps = 1e-6 * abs(A[k])
+            Ap, Am = A.copy(), A.copy()
+            Ap[k] += eps
+            Am[k] -= eps
+            fd = (L(Ap, b) - L(Am, b)) / (2 * eps)
+            assert abs(fd - gA[k]) <= 1e-5 * max(abs(gA[k]), 1e-3 * amax), (c, k, fd, gA[k])
+        gbc = o["gb"][c]
+        for i in rng.choice(mech.n, size=4, replace=False):
+            e = np.zeros(mech.n)
+            e[i] = 1e-6
+            fd = (L(A, b + e) - L(A, b - e)) / 2e-6
+            assert abs(fd - gbc[i]) <= 1e-5 * max(abs(gbc[i]), 1e-3 * np.abs(gbc).max())
+
+
+def test_autograd_chain_rule_to_J_gamma_b():
+    mech, cells = config_inputs(5, ncells=500)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    V = gpu(cells["values"]).requires_grad_(True)
+    G = gpu(cells["gamma"]).requires_grad_(True)
+    B = gpu(cells["b"]).requires_grad_(True)
+    W = gpu(cells["w"])
+    x = bcs.BatchedSolve.apply(V, G, B, plan)
+    loss = (W * x).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    xn = x.detach().cpu().numpy()
+    gb_o, gA_o, it, res, st = oracle.adjoint_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"],
+                                                   xn, cells["w"], precond=1)
+    ok = st == 0
+    gJ = V.grad.cpu().numpy()
+    gG = G.grad.cpu().numpy()
+    gB = B.grad.cpu().numpy()
+    # dL/dJ = gamma * lambda_i x_j, dL/dgamma = lambda^T J x, dL/db = lambda
+    expect_J = -cells["gamma"][:, None] * gA_o
+    expect_G = -np.sum(cells["values"] * gA_o, axis=1)
+    for c in np.nonzero(ok)[0][:200]:
+        scale = np.abs(expect_J[c]).max()
+        assert np.allclose(gJ[c], expect_J[c], rtol=1e-6, atol=1e-9 * scale)
+        assert np.allclose(gB[c], gb_o[c], rtol=1e-6, atol=1e-9 * np.abs(gb_o[c]).max())
+        gscale = np.sum(np.abs(cells["values"][c] * gA_o[c]))
+        assert abs(gG[c] - expect_G[c]) <= 1e-6 * gscale + 1e-12
+
+
+def test_data_autotune_keeps_results_valid():
+    mech, cells = config_inputs(2, ncells=6000)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
+    lanes = plan.autotune(V, G, B)
+    assert lanes in (16, 32, 64) and plan.info()["lanes_per_cell"] == lanes
+    x, it, res, st, _ = bcs.solve_batch(plan, V, G, B)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    xo, ito, reso, sto = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"],
+                                            cells["b"], precond=1)
+    assert np.mean(st == sto) >= 0.99
+    # the adjoint kernel follows the tuned layout and still works
+    gb, gA, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, B)
+    torch.cuda.synchronize()
+    assert np.mean(ast.cpu().numpy() == 0) >= 0.99
