@@ -200,7 +200,7 @@ void free_kernel(Kernel* K) {
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
-                int lanes, int adjoint, bool use_jit, int waves_per_eu, Kernel* out) {
+                int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out) {
   const int rpl = (n + lanes - 1) / lanes;
   Kernel K;
   K.lanes = lanes;
@@ -214,10 +214,14 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.lds = lds_bytes(n, lanes, rpl, S.ksteps, adjoint);
     if (K.lds > 65536) return BCS_ERR_UNSUPPORTED;  // gather addresses are 16-bit
     char err[512] = {0};
-    const int rc = bcs::jit_fp64_kernel(lanes, S.seg.data(), rpl, waves_per_eu, K.lds, &K.jit, err, sizeof(err));
+    if (waves_per_eu == 0)
+      if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
+    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", lanes, S.seg.data(), rpl, waves_per_eu,
+                                   K.lds, &K.jit, err, sizeof(err));
     if (rc != BCS_OK) return fail(rc, "%s", err);
     K.max_blocks = K.jit.max_blocks;
   } else {
+    if (mixed) return BCS_ERR_UNSUPPORTED;  // the mixed form exists only as specialised kernels
     int nv = 0;
     const bcs::Variant* vs = all_variants(&nv);
     const bcs::Variant* best = nullptr;
@@ -251,8 +255,9 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     return rc;
   }
   if (verbose())
-    std::fprintf(stderr, "[bcs] kernel %s lanes=%d rpl=%d steps=%d adjoint=%d lds=%zu blocks/CU=%d\n",
-                 use_jit ? "jit" : "precompiled", lanes, K.rpl, K.ksteps, adjoint, K.lds, K.max_blocks);
+    std::fprintf(stderr, "[bcs] kernel %s%s lanes=%d rpl=%d steps=%d adjoint=%d lds=%zu blocks/CU=%d\n",
+                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", lanes, K.rpl, K.ksteps, adjoint, K.lds,
+                 K.max_blocks);
   *out = K;
   return BCS_OK;
 }
@@ -497,7 +502,6 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     for (int i = 0; i < n; ++i)
       if (diag[i] < 0) return fail(BCS_ERR_PATTERN, "row %d has no diagonal entry", i);
   if (n > 256) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 256 rows per cell", n);
-  if (o.precision != BCS_FP64) return fail(BCS_ERR_UNSUPPORTED, "FP32_REFINE is not available yet");
 
   bcs_plan* p = new bcs_plan();
   p->n = n;
@@ -557,6 +561,11 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   // Lanes per cell.  Candidates that fit are either timed on a synthetic
   // batch (autotune) or ranked by wave-steps per cell (ksteps * lanes / 64).
   const bool jit = o.jit == 1;
+  const bool mixed = o.precision == BCS_FP32_REFINE;
+  if (mixed && !jit) {
+    release(p);
+    return fail(BCS_ERR_UNSUPPORTED, "FP32_REFINE needs jit = 1 (its kernels are compiled per pattern)");
+  }
   Kernel best;
   double best_cost = 1e300;
   int rc = BCS_OK;
@@ -565,7 +574,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     if (o.lanes_per_cell != 0 && o.lanes_per_cell != L) continue;
     Kernel K;
     g_err.clear();
-    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, &K);
+    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) {
       rc = r;
@@ -594,7 +603,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (rc == BCS_OK) {
     p->fwd = best;
     g_err.clear();
-    rc = make_kernel(n, trp, tci, tpos, best.lanes, 1, jit, 0, &p->adj);
+    rc = make_kernel(n, trp, tci, tpos, best.lanes, 1, jit, 0, false, &p->adj);
     if (rc == BCS_ERR_UNSUPPORTED && g_err.empty())
       rc = fail(BCS_ERR_UNSUPPORTED, "no kernel layout holds the transposed pattern");
   } else {
@@ -643,7 +652,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
     if (L == p->fwd.lanes) continue;
     Kernel K;
     g_err.clear();
-    int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, &K);
+    int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) return r;
     double t = 0;
@@ -675,7 +684,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
       }
     Kernel A;
     g_err.clear();
-    rc = make_kernel(p->n, trp, tci, tpos, best_lanes, 1, jit, 0, &A);
+    rc = make_kernel(p->n, trp, tci, tpos, best_lanes, 1, jit, 0, false, &A);
     if (rc != BCS_OK) return g_err.empty() ? fail(rc, "no kernel layout holds the transposed pattern") : rc;
     free_kernel(&p->adj);
     p->adj = A;

@@ -110,19 +110,21 @@ struct DynSched {
   uint64_t f0_, f1_;
   __device__ explicit DynSched(const DevSchedule& d) : f0_(d.flush[0]), f1_(d.flush[1]) {}
 
+  // T = double, or float stored in the low half of double-spaced slots
+  // (so both precisions share the slot layout and the gather addresses).
   template <typename T>
   __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
-                                       const char* lds, T* xb, T* yb, int gl, const int (&rows)[RPL],
+                                       const char* lds, double* xb, double* yb, int gl, const int (&rows)[RPL],
                                        const T (&in)[RPL], T (&out)[RPL]) const {
     constexpr int NW = addr_words<KMAX>();
     const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
     uint32_t ad[NW];
     opaque_copy<NW>(ad_, ad);
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
+    for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
     wave_sync();
     T acc = 0;
-    T* ydst = yb + gl;
+    double* ydst = yb + gl;
 #pragma unroll
     for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
       constexpr int C = kGatherChunk;
@@ -138,7 +140,7 @@ struct DynSched {
         if (s < KMAX) {
           acc = __builtin_fma(a[s], g[i], acc);
           if (flush_bit(f0, f1, s)) {
-            *ydst = acc;
+            *(T*)ydst = acc;
             ydst += LANES;
             acc = 0;
           }
@@ -147,7 +149,7 @@ struct DynSched {
     }
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) out[j] = yb[j * LANES + gl];
+    for (int j = 0; j < RPL; ++j) out[j] = *(const T*)(yb + j * LANES + gl);
     wave_sync();
   }
 };
@@ -172,6 +174,15 @@ struct StaticSched {
     }
     return RPL - 1;
   }
+  static constexpr int slot_start(int s) {
+    constexpr int seg[RPL] = {SEG...};
+    int b = 0;
+    for (int j = 0; j < RPL; ++j) {
+      if (s < b + seg[j]) return b;
+      b += seg[j];
+    }
+    return b;
+  }
   static constexpr bool ends_slot(int s) {
     constexpr int seg[RPL] = {SEG...};
     int e = 0;
@@ -184,15 +195,17 @@ struct StaticSched {
 
   template <typename T>
   __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
-                                       const char* lds, T* xb, T* /*yb*/, int /*gl*/, const int (&rows)[RPL],
-                                       const T (&in)[RPL], T (&out)[RPL]) const {
+                                       const char* lds, double* xb, double* /*yb*/, int /*gl*/,
+                                       const int (&rows)[RPL], const T (&in)[RPL], T (&out)[RPL]) const {
     constexpr int NW = addr_words<KMAX>();
     uint32_t ad[NW];
     opaque_copy<NW>(ad_, ad);
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) xb[rows[j]] = in[j];
+    for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
     wave_sync();
-    T acc = 0;
+    // two accumulators per slot (even / odd steps of the slot) halve the
+    // FMA dependency chain
+    T acc0 = 0, acc1 = 0;
 #pragma unroll
     for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
       constexpr int C = kGatherChunk;
@@ -206,10 +219,14 @@ struct StaticSched {
       for (int i = 0; i < C; ++i) {
         const int s = s0 + i;
         if (s < KMAX) {
-          acc = __builtin_fma(a[s], g[i], acc);
+          if (((s - slot_start(s)) & 1) == 0)
+            acc0 = __builtin_fma(a[s], g[i], acc0);
+          else
+            acc1 = __builtin_fma(a[s], g[i], acc1);
           if (ends_slot(s)) {
-            out[slot_of(s)] = acc;
-            acc = 0;
+            out[slot_of(s)] = acc0 + acc1;
+            acc0 = 0;
+            acc1 = 0;
           }
         }
       }

@@ -78,7 +78,7 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   // column-scaled (Ahat = A D^-1, right preconditioning), so xv holds
   // xhat = D x and x = D^-1 xhat is formed when the cell finishes.
   double xv[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];
-  double bn = 0, rho_prev = 1, alpha = 1, omega = 1;
+  double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
   int64_t cell = 0;
@@ -180,10 +180,13 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
           for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr(ado, s));
           wave_sync();
         }
-        bn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
+        const double bn2 = gsum<LANES>(ldot<RPL>(r, r));
+        bn = __builtin_sqrt(bn2);
+        tol2 = (P.rtol * bn) * (P.rtol * bn);
         it = 0;
         restarts_left = P.brs;
         restart();
+        rho = bn2;  // (rhat, r) with rhat = r = b
         active = true;
         if (!finite(bn)) {
           finish(kNonfinite, __builtin_nan(""));
@@ -196,9 +199,11 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
     if (!active) continue;
 
     // ---- one BiCGStab iteration of this slot's cell ----
+    // rho = (rhat, r) was reduced together with ||r||^2 at the end of the
+    // previous iteration (or at staging / restart, where rhat = r).
+    // Convergence tests compare squared norms with (rtol ||b||)^2.
     ++it;
     int ended = -1;  // -1 = continue, else kConverged / kBreakdown / kNonfinite
-    const double rho = gsum<LANES>(ldot<RPL>(rh, r));
     if (!finite(rho)) {
       ended = kNonfinite;
     } else if (rho == 0.0) {
@@ -209,7 +214,7 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
         for (int j = 0; j < RPL; ++j) p[j] = r[j];
         first = false;
       } else {
-        const double beta = (rho / rho_prev) * (alpha / omega);
+        const double beta = (rho * alpha) / (rho_prev * omega);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       }
@@ -223,10 +228,10 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
         alpha = rho / sigma;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
-        const double sn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
-        if (!finite(sn)) {
+        const double sn2 = gsum<LANES>(ldot<RPL>(r, r));
+        if (!finite(sn2)) {
           ended = kNonfinite;
-        } else if (sn / bn <= P.rtol) {
+        } else if (sn2 <= tol2) {
 #pragma unroll
           for (int j = 0; j < RPL; ++j) xv[j] = xv[j] + alpha * p[j];
           ended = kConverged;
@@ -245,15 +250,17 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
               xv[j] = xv[j] + alpha * p[j] + omega * r[j];
               r[j] = r[j] - omega * t[j];
             }
-            const double rn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r, r)));
-            if (!finite(rn)) {
+            const double rn2 = gsum<LANES>(ldot<RPL>(r, r));
+            const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+            if (!finite(rn2)) {
               ended = kNonfinite;
-            } else if (rn / bn <= P.rtol) {
+            } else if (rn2 <= tol2) {
               ended = kConverged;
             } else if (omega == 0.0) {
               ended = kBreakdown;
             } else {
               rho_prev = rho;
+              rho = rho_next;
             }
           }
         }
@@ -272,7 +279,8 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
           t[j] = (real ? bj : 0.0) - t[j];
         }
       }
-      const double res = __builtin_sqrt(gsum<LANES>(ldot<RPL>(t, t))) / bn;
+      const double tt2 = gsum<LANES>(ldot<RPL>(t, t));
+      const double res = __builtin_sqrt(tt2) / bn;
       if (ended == kNonfinite || !finite(res)) {
         finish(kNonfinite, res);
       } else if (res <= P.rtol) {
@@ -282,6 +290,7 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = t[j];
         restart();
+        rho = tt2;  // (rhat, r) with rhat = r = b - A x
       } else {
         finish(ended == kBreakdown ? kBreakdown : kMaxit, res);
       }

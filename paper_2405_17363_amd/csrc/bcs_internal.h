@@ -36,10 +36,10 @@ struct JitKernel {
   int max_blocks = 0;  // resident workgroups per CU
 };
 
-// Compile (or fetch from the cache) the FP64 solve kernel for `lanes` lanes
-// per cell and slot segment lengths seg[0..rpl).  Returns BCS_OK or an error
-// code with the message in `err`.
-int jit_fp64_kernel(int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes, JitKernel* out,
-                    char* err, size_t errlen);
+// Compile (or fetch from the cache) a solve kernel -- body "fp64_body" or
+// "mixed_body" -- for `lanes` lanes per cell and slot segment lengths
+// seg[0..rpl).  Returns BCS_OK or an error code with the message in `err`.
+int jit_kernel(const char* body, int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes,
+               JitKernel* out, char* err, size_t errlen);
 
 }  // namespace bcs

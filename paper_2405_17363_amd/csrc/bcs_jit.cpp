@@ -108,8 +108,8 @@ int compile(const std::string& src, const std::string& arch, std::vector<char>* 
 
 }  // namespace
 
-int jit_fp64_kernel(int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes, JitKernel* out,
-                    char* err, size_t errlen) {
+int jit_kernel(const char* body, int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes,
+               JitKernel* out, char* err, size_t errlen) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     snprintf(err, errlen, "no HIP device");
@@ -125,11 +125,11 @@ int jit_fp64_kernel(int lanes, const int* seg, int rpl, int waves_per_eu, size_t
   const std::string base_arch = arch.substr(0, colon);
 
   std::ostringstream src;
-  src << "#include \"bcs_fp64.h\"\n"
+  src << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
   if (waves_per_eu > 0) src << ", " << waves_per_eu;
   src << ") bcs_jit_kernel(bcs::KParams P) {\n"
-      << "  bcs::fp64_body<bcs::dev::StaticSched<" << lanes;
+      << "  bcs::" << body << "<bcs::dev::StaticSched<" << lanes;
   for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
   src << ">>(P);\n}\n";
   const std::string source = src.str();

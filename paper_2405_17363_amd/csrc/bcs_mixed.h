@@ -1,0 +1,327 @@
+// Mixed-precision batched solve: FP32 inner BiCGStab inside FP64 iterative
+// refinement, one cell per slot, same persistent work-queue structure as the
+// FP64 kernel.
+//
+// Per cell (D = diag(A)):
+//   Ahat = A D^-1 is formed in FP64 and held in VGPRs in FP32;
+//   x = 0, r = b (FP64);
+//   repeat while ||r||/||b|| > rtol and fewer than max_refine inner solves:
+//     solve Ahat d = float(r / ||r||) by FP32 BiCGStab to inner_rtol (x0 = 0;
+//     an exact breakdown restarts once from the FP32 true residual);
+//     x_new = x + ||r|| D^-1 d (FP64); r_new = b - A x_new (FP64, with A
+//     streamed again from memory, so the FP64 matrix never occupies VGPRs);
+//     stop without accepting x_new if ||r_new|| >= ||r|| (stagnation).
+// Outputs: x, iters = total inner iterations, refinements = inner solves,
+// resid = ||b - A x||/||b|| in FP64, status.
+#pragma once
+
+#include "bcs_device.h"
+
+namespace bcs {
+
+template <class S>
+__device__ __forceinline__ void mixed_body(const KParams& P) {
+  using namespace dev;
+  constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
+  constexpr int G = 64 / LANES;
+  constexpr int NW = addr_words<KMAX>();
+  const S sch(P.sched);
+  extern __shared__ double lds[];
+  const char* ldsb = (const char*)lds;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int gl = lane & (LANES - 1);
+  const int grp = lane / LANES;
+  const int slot_base = (wv * G + grp) * P.xs;  // in doubles
+  double* xb = lds + slot_base;
+  double* yb = xb + P.yoff;
+  const int n = P.n, nnz = P.nnz;
+
+  uint32_t ad[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int s = 2 * q + i;
+      if (s < KMAX) w |= (uint32_t)((slot_base + P.sched.col[s * LANES + gl]) * 8) << (16 * i);
+    }
+    ad[q] = w;
+  }
+  int rows[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    const int rj = P.sched.row[j * LANES + gl];
+    rows[j] = rj >= 0 ? rj : n;
+  }
+  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
+  for (int i = threadIdx.x; i < KMAX * LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
+  __syncthreads();
+  int dpos[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) dpos[j] = P.diag_pos[rows[j] < n ? rows[j] : 0] & kEntPosMask;
+
+  float a32[KMAX];                      // Ahat = A D^-1 rounded to FP32
+  double x64[RPL], r64[RPL], dg[RPL];   // FP64 iterate, residual, diag(A)
+  float d[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];  // FP32 inner state
+  double bn = 0, rn = 0, g = 0;
+  float itol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
+  int it_in = 0, tot = 0, nref = 0, restarts_left = 0;
+  bool first = true, active = false, dead = false;
+  int phase = 0;  // 0: check / start an inner solve, 1: inner iterating, 2: refinement update
+  int64_t cell = 0;
+
+  auto finish = [&](int st, double res) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+      if (rows[j] < n) P.x[cell * n + rows[j]] = x64[j];
+    if (gl == 0) {
+      P.iters[cell] = tot;
+      P.resid[cell] = res;
+      P.status[cell] = st;
+      if (P.refinements) P.refinements[cell] = nref;
+    }
+    active = false;
+  };
+
+  // out = b - A xin in FP64, with A's values streamed from memory (per step:
+  // value position from the LDS schedule copy, the value, A = I - gamma J).
+  auto residual64 = [&](const double (&xin)[RPL], double (&out)[RPL]) {
+    const double* vals = P.values + cell * nnz;
+    double av[KMAX];
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+      const int32_t e = ent_lds[s * LANES + gl];
+      const double jv = vals[e & kEntPosMask];
+      const double a = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
+      av[s] = (e & kEntPad) ? 0.0 : a;
+    }
+    double ax[RPL];
+    sch.spmv(av, ad, ldsb, xb, yb, gl, rows, xin, ax);
+    const double* bc = P.b + cell * n;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const bool real = rows[j] < n;
+      const double bj = bc[real ? rows[j] : 0];
+      out[j] = (real ? bj : 0.0) - ax[j];
+    }
+  };
+
+  // start the FP32 inner solve for the scaled residual r64 / rn
+  auto start_inner = [&]() {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      r[j] = (float)(r64[j] / rn);
+      d[j] = 0.f;
+      rh[j] = r[j];
+      p[j] = 0.f;
+      v[j] = 0.f;
+    }
+    const float ib2 = gsum<LANES>(ldot<RPL>(r, r));
+    const float ibn = __builtin_sqrtf(ib2);
+    const float tol = (float)P.inner_rtol * ibn;
+    itol2 = tol * tol;
+    rho = ib2;
+    rho_prev = alpha = omega = 1.f;
+    first = true;
+    it_in = 0;
+    restarts_left = 1;
+  };
+
+  for (;;) {
+    if (!active && !dead) {
+      unsigned long long c = 0;
+      if (gl == 0) c = atomicAdd(P.queue, 1ull);
+      c = __shfl(c, grp * LANES, 64);
+      if (c >= (unsigned long long)P.ncells) {
+        dead = true;
+      } else {
+        cell = (int64_t)c;
+        const double* vals = P.values + cell * nnz;
+        g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
+        const double* bc = P.b + cell * n;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const bool real = rows[j] < n;
+          const double bj = bc[real ? rows[j] : 0];
+          const double dvj = vals[dpos[j]];
+          dg[j] = (P.kind == kJGamma) ? 1.0 - g * dvj : dvj;
+          r64[j] = real ? bj : 0.0;
+          x64[j] = 0.0;
+          xb[rows[j]] = real ? 1.0 / dg[j] : 0.0;  // D^-1 for the column scaling
+        }
+        wave_sync();
+        uint32_t ado[NW];
+        opaque_copy<NW>(ad, ado);
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+          const int32_t e = ent_lds[s * LANES + gl];
+          const double jv = vals[e & kEntPosMask];
+          const double a = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
+          const double sc = *(const double*)(ldsb + step_addr(ado, s));
+          a32[s] = (e & kEntPad) ? 0.f : (float)(a * sc);
+        }
+        wave_sync();
+        bn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r64, r64)));
+        rn = bn;
+        tot = 0;
+        nref = 0;
+        phase = 0;
+        active = true;
+        if (!finite(bn)) {
+          finish(kNonfinite, __builtin_nan(""));
+        } else if (bn == 0.0) {
+          finish(kConverged, 0.0);
+        }
+      }
+    }
+    if (__ballot(!dead) == 0ull) break;
+    if (!active) continue;
+
+    if (phase == 0) {
+      if (!finite(rn)) {
+        finish(kNonfinite, __builtin_nan(""));
+        continue;
+      }
+      if (rn / bn <= P.rtol) {
+        finish(kConverged, rn / bn);
+        continue;
+      }
+      if (nref >= P.max_refine) {
+        finish(kMaxit, rn / bn);
+        continue;
+      }
+      start_inner();
+      phase = 1;
+    }
+
+    if (phase == 1) {
+      // one FP32 BiCGStab iteration on Ahat d = r64 / rn
+      ++it_in;
+      int ended = -1;
+      if (!finite(rho)) {
+        ended = kNonfinite;
+      } else if (rho == 0.f) {
+        ended = kBreakdown;
+      } else {
+        if (first) {
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) p[j] = r[j];
+          first = false;
+        } else {
+          const float beta = (rho * alpha) / (rho_prev * omega);
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
+        }
+        sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, p, v);
+        const float sigma = gsum<LANES>(ldot<RPL>(rh, v));
+        if (!finite(sigma)) {
+          ended = kNonfinite;
+        } else if (sigma == 0.f) {
+          ended = kBreakdown;
+        } else {
+          alpha = rho / sigma;
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];
+          const float sn2 = gsum<LANES>(ldot<RPL>(r, r));
+          if (!finite(sn2)) {
+            ended = kNonfinite;
+          } else if (sn2 <= itol2) {
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) d[j] = d[j] + alpha * p[j];
+            ended = kConverged;
+          } else {
+            sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, r, t);
+            const float tt = gsum<LANES>(ldot<RPL>(t, t));
+            const float ts = gsum<LANES>(ldot<RPL>(t, r));
+            if (!finite(tt)) {
+              ended = kNonfinite;
+            } else if (tt == 0.f) {
+              ended = kBreakdown;
+            } else {
+              omega = ts / tt;
+#pragma unroll
+              for (int j = 0; j < RPL; ++j) {
+                d[j] = d[j] + alpha * p[j] + omega * r[j];
+                r[j] = r[j] - omega * t[j];
+              }
+              const float rn2 = gsum<LANES>(ldot<RPL>(r, r));
+              const float rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+              if (!finite(rn2)) {
+                ended = kNonfinite;
+              } else if (rn2 <= itol2) {
+                ended = kConverged;
+              } else if (omega == 0.f) {
+                ended = kBreakdown;
+              } else {
+                rho_prev = rho;
+                rho = rho_next;
+              }
+            }
+          }
+        }
+      }
+      if (ended < 0 && it_in >= P.maxit) ended = kMaxit;
+      if (ended == kNonfinite) {
+        tot += it_in;
+        ++nref;
+        finish(kNonfinite, __builtin_nan(""));
+        continue;
+      }
+      if (ended == kBreakdown && restarts_left > 0 && it_in < P.maxit) {
+        // restart from the FP32 true residual of the scaled system
+        --restarts_left;
+        float ad32[RPL];
+        sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, d, ad32);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          r[j] = (float)(r64[j] / rn) - ad32[j];
+          rh[j] = r[j];
+          p[j] = 0.f;
+          v[j] = 0.f;
+        }
+        rho = gsum<LANES>(ldot<RPL>(r, r));
+        rho_prev = alpha = omega = 1.f;
+        first = true;
+      } else if (ended >= 0) {
+        tot += it_in;
+        ++nref;
+        phase = 2;
+      }
+    }
+
+    if (phase == 2) {
+      // FP64 refinement: x_new = x + ||r|| D^-1 d, accepted only if the
+      // FP64 true residual decreases
+      double xn[RPL], rnv[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) xn[j] = x64[j] + rn * ((double)d[j] / dg[j]);
+      residual64(xn, rnv);
+      const double rnn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(rnv, rnv)));
+      if (!(rnn < rn)) {
+        if (finite(rnn))
+          finish(kMaxit, rn / bn);
+        else
+          finish(kNonfinite, __builtin_nan(""));
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        x64[j] = xn[j];
+        r64[j] = rnv[j];
+      }
+      rn = rnn;
+      phase = 0;
+    }
+  }
+
+  if (lane == 0) {
+    const unsigned long long done = atomicAdd(P.queue + 1, 1ull);
+    if (done == (unsigned long long)(P.total_waves - 1)) {
+      atomicExch(P.queue, 0ull);
+      atomicExch(P.queue + 1, 0ull);
+    }
+  }
+}
+
+}  // namespace bcs
