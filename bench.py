@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB device buffer (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,6 +74,13 @@ def main():
     mech, cells = config_inputs(3, ncells=None if args.ncells == 100_000 else args.ncells)[0]
     C, n, nnz = cells["b"].shape[0], mech.n, mech.nnz
     print(f"# generated {C} cells n={n} nnz={nnz} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        # a plain device-to-device copy of known size: 2^30 bytes read, 2^30 written
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     values = torch.as_tensor(cells["values"], device=dev)
     gamma = torch.as_tensor(cells["gamma"], device=dev)
     b = torch.as_tensor(cells["b"], device=dev)
@@ -112,13 +121,17 @@ def main():
     valu_tfs = flops_launch / avg_launch_s / 1e12
     info = plan.info()
 
+    # HBM bytes per launch from the committed counter summary, used only while
+    # the kernel sources and the layout are those the counters were taken with
     traffic = None
-    tr_path = os.path.join(HERE, "profiles", "traffic_fp64_solve_100k.json")
+    tr_path = os.path.join(HERE, "profiles", "traffic_fp64_solve_100k_n80.txt")
     if os.path.exists(tr_path):
-        with open(tr_path) as f:
-            tr = json.load(f)
-        if tr.get("plan") == info and tr.get("ncells") == C:
-            traffic = tr.get("hbm_bytes_per_launch")
+        from paper_2405_17363_amd.profiling import load_traffic, source_hash
+
+        tr = load_traffic(tr_path)
+        if (tr.get("source_hash") == source_hash() and tr.get("ncells") == C
+                and tr.get("lanes_per_cell") == info["lanes_per_cell"]):
+            traffic = round(tr["hbm_bytes_per_launch"])
 
     fracs = {"hbm": hbm_gbs / HBM_PEAK_GBS, "alu": valu_tfs / FP64_VALU_PEAK}
     bound = max(fracs, key=fracs.get)
@@ -129,7 +142,8 @@ def main():
         "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
         "frac": round(fracs[bound], 4),
         "traffic": traffic,
-        "kernel": "k_fp64<%d,%d,%d>" % (info["lanes_per_cell"], info["rows_per_lane"], info["steps_per_lane"]),
+        "kernel": "bcs_jit_kernel (fp64, %d lanes/cell, %d rows/lane, %d steps/lane)" % (
+            info["lanes_per_cell"], info["rows_per_lane"], info["steps_per_lane"]),
         "avg_launch_ms": round(avg_launch_s * 1e3, 4),
         "hbm_gbs": round(hbm_gbs, 2),
         "hbm_frac": round(fracs["hbm"], 4),

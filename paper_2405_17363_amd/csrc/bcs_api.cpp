@@ -141,6 +141,7 @@ constexpr int kMaxJitSteps = 160;
 // One launchable solve kernel with its schedule on the device.
 struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
+  std::vector<int> seg;               // slot segment lengths (specialised kernels)
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -216,10 +217,11 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", lanes, S.seg.data(), rpl, waves_per_eu,
-                                   K.lds, &K.jit, err, sizeof(err));
+    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, lanes, S.seg.data(), rpl,
+                                   waves_per_eu, K.lds, &K.jit, err, sizeof(err));
     if (rc != BCS_OK) return fail(rc, "%s", err);
     K.max_blocks = K.jit.max_blocks;
+    K.seg = S.seg;
   } else {
     if (mixed) return BCS_ERR_UNSUPPORTED;  // the mixed form exists only as specialised kernels
     int nv = 0;
@@ -764,9 +766,90 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
                     const double* const* values, const double* const* gamma, const int64_t* gamma_stride,
                     const double* const* b, double rtol, int32_t maxit, double* const* x, int32_t* const* iters,
                     double* const* resid, int32_t* const* status, void* stream) {
-  (void)nmech; (void)plans; (void)ncells; (void)values; (void)gamma; (void)gamma_stride; (void)b; (void)rtol;
-  (void)maxit; (void)x; (void)iters; (void)resid; (void)status; (void)stream;
-  return fail(BCS_ERR_UNSUPPORTED, "bcs_solve_multi is not available yet");
+  g_err.clear();
+  if (nmech < 1 || nmech > bcs::kMaxMech) return fail(BCS_ERR_ARG, "nmech must be in [1, %d]", bcs::kMaxMech);
+  if (!plans || !ncells || !values || !gamma || !gamma_stride || !b || !x || !iters || !resid || !status)
+    return fail(BCS_ERR_ARG, "an array argument is NULL");
+  std::vector<int> order;
+  for (int m = 0; m < nmech; ++m) {
+    const bcs_plan* p = plans[m];
+    int rc = check_common(p, ncells[m], values[m], gamma[m], gamma_stride[m], rtol, maxit);
+    if (rc != BCS_OK) return rc;
+    for (int q = 0; q < m; ++q)
+      if (plans[q] == p) return fail(BCS_ERR_ARG, "a plan appears twice (mechanisms %d and %d)", q, m);
+    if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var)
+      return fail(BCS_ERR_UNSUPPORTED, "bcs_solve_multi needs FP64 plans created with jit = 1 (mechanism %d)", m);
+    if (ncells[m] == 0) continue;
+    if (!b[m] || !x[m] || !iters[m] || !resid[m] || !status[m])
+      return fail(BCS_ERR_ARG, "b/x/iters/resid/status of mechanism %d is NULL", m);
+    order.push_back(m);
+  }
+  if (order.empty()) return BCS_OK;
+  // heaviest cells first: their slots take longest, the light cells fill the tail
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+    return (int64_t)plans[u]->fwd.ksteps * plans[u]->fwd.lanes > (int64_t)plans[v]->fwd.ksteps * plans[v]->fwd.lanes;
+  });
+  const int nm = (int)order.size();
+  bcs::MultiParams M{};
+  M.nmech = nm;
+  int wave_stride = 0;
+  std::vector<SlotLayout> lay(nm);
+  for (int q = 0; q < nm; ++q) {
+    const Kernel& K = plans[order[q]]->fwd;
+    lay[q] = slot_layout(plans[order[q]]->n, K.lanes, K.rpl, 0);
+    wave_stride = std::max(wave_stride, (64 / K.lanes) * lay[q].stride);
+  }
+  M.wave_stride = wave_stride;
+  size_t off = (size_t)bcs::kWavesPerWg * wave_stride;  // doubles
+  for (int q = 0; q < nm; ++q) {
+    const Kernel& K = plans[order[q]]->fwd;
+    M.ent_off[q] = (int32_t)off;
+    off += ((size_t)K.ksteps * K.lanes * 4 + 7) / 8;
+  }
+  const size_t lds = off * 8;
+  if ((size_t)bcs::kWavesPerWg * wave_stride * 8 > 65536 || lds > 65536)
+    return fail(BCS_ERR_UNSUPPORTED, "the mechanisms need %zu bytes of LDS per workgroup (limit 64 KiB)", lds);
+  std::vector<int> lanes(nm), rpl(nm);
+  std::vector<const int*> segs(nm);
+  for (int q = 0; q < nm; ++q) {
+    const Kernel& K = plans[order[q]]->fwd;
+    lanes[q] = K.lanes;
+    rpl[q] = K.rpl;
+    segs[q] = K.seg.data();
+  }
+  bcs::JitKernel jk;
+  char err[512] = {0};
+  int rc = bcs::jit_multi_kernel(nm, lanes.data(), segs.data(), rpl.data(), lds, &jk, err, sizeof(err));
+  if (rc != BCS_OK) return fail(rc, "%s", err);
+  int64_t need = 0;
+  for (int q = 0; q < nm; ++q) {
+    const int m = order[q];
+    const bcs_plan* p = plans[m];
+    bcs::KParams P = base_params(p, ncells[m], values[m], gamma[m], gamma_stride[m], rtol, maxit);
+    P.b = b[m];
+    P.x = x[m];
+    P.iters = iters[m];
+    P.resid = resid[m];
+    P.status = status[m];
+    P.refinements = nullptr;
+    P.sched = p->fwd.d;
+    P.adjoint = 0;
+    P.xs = lay[q].stride;
+    P.xoff2 = lay[q].xoff2;
+    P.yoff = lay[q].yoff;
+    P.queue = p->queue;
+    M.m[q] = P;
+    const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
+    need += (ncells[m] + cpw - 1) / cpw;
+  }
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)jk.max_blocks * plans[order[0]]->num_cu));
+  M.total_waves = grid * bcs::kWavesPerWg;
+  for (int q = 0; q < nm; ++q) M.m[q].total_waves = M.total_waves;
+  void* args[] = {&M};
+  const hipError_t e = hipModuleLaunchKernel(jk.fn, grid, 1, 1, bcs::kWgThreads, 1, 1, (unsigned)lds,
+                                             (hipStream_t)stream, args, nullptr);
+  if (e != hipSuccess) return fail(BCS_ERR_HIP, "multi launch: %s", hipGetErrorString(e));
+  return BCS_OK;
 }
 
 }  // extern "C"

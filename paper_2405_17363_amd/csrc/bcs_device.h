@@ -44,14 +44,50 @@ __device__ __forceinline__ float dpp(float v) {
 // the same two partial sums (in either order, and IEEE addition commutes), so
 // all lanes of the cell end with bitwise the same value, and the result of a
 // cell never depends on which slot or wave it ran in.
+// Sum of a value over 16-lane row pairs (0,1), (2,3) with v_permlane16_swap
+// (SWAP32 = false), or over the two wave halves with v_permlane32_swap: both
+// results of the swap applied to (v, v) hold the pair in the same order, so
+// every lane adds the same two operands in the same order.
+template <bool SWAP32>
+__device__ __forceinline__ double pair_sum(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  uint32_t a_lo, b_lo, a_hi, b_hi;
+  if constexpr (SWAP32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a_lo = l[0], b_lo = l[1], a_hi = h[0], b_hi = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a_lo = l[0], b_lo = l[1], a_hi = h[0], b_hi = h[1];
+  }
+  return __builtin_bit_cast(double, ((uint64_t)a_hi << 32) | a_lo) +
+         __builtin_bit_cast(double, ((uint64_t)b_hi << 32) | b_lo);
+}
+
+template <bool SWAP32>
+__device__ __forceinline__ float pair_sum(float v) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, v);
+  uint32_t a, b;
+  if constexpr (SWAP32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    a = r[0], b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    a = r[0], b = r[1];
+  }
+  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
 template <int LANES, typename T>
 __device__ __forceinline__ T gsum(T v) {
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x141>(v);  // row_half_mirror: quads 0<->1 within each 8 lanes
   v += dpp<0x140>(v);  // row_mirror: halves 0<->1 within each 16-lane row
-  if constexpr (LANES >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (LANES >= 64) v += __shfl_xor(v, 32, 64);
+  if constexpr (LANES >= 32) v = pair_sum<false>(v);
+  if constexpr (LANES >= 64) v = pair_sum<true>(v);
   return v;
 }
 
@@ -67,6 +103,12 @@ __device__ __forceinline__ T opaque(T v) {
 // Copy a lane's packed words so that values unpacked from the copy are
 // recomputed at this use instead of being hoisted and kept live unpacked.
 template <int N>
+__device__ __forceinline__ void opaque_inplace(uint32_t (&w)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) asm volatile("" : "+v"(w[q]));
+}
+
+template <int N>
 __device__ __forceinline__ void opaque_copy(const uint32_t (&in)[N], uint32_t (&out)[N]) {
 #pragma unroll
   for (int q = 0; q < N; ++q) {
@@ -75,10 +117,28 @@ __device__ __forceinline__ void opaque_copy(const uint32_t (&in)[N], uint32_t (&
   }
 }
 
-// 16-bit LDS byte address of step s from packed words.
-template <int N>
+// LDS byte address of step s: PACK = 2 packs two 16-bit addresses per word
+// (saves VGPRs, costs one VALU op per step), PACK = 1 keeps one per word.
+template <int PACK, int N>
 __device__ __forceinline__ uint32_t step_addr(const uint32_t (&ad)[N], int s) {
+  if constexpr (PACK == 1) return ad[s];
   return (s & 1) ? (ad[s >> 1] >> 16) : (ad[s >> 1] & 0xffffu);
+}
+
+// Fill a lane's address words for schedule `col` (steps x lanes, step-major)
+// and a cell slot starting at slot_base doubles.
+template <int PACK, int KMAX, int LANES, int N>
+__device__ __forceinline__ void build_addr(uint32_t (&ad)[N], const uint8_t* col, int slot_base, int gl) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int i = 0; i < PACK; ++i) {
+      const int s = PACK * q + i;
+      if (s < KMAX) w |= (uint32_t)((slot_base + col[s * LANES + gl]) * 8) << (16 * i);
+    }
+    ad[q] = w;
+  }
 }
 
 __device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
@@ -87,10 +147,6 @@ __device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
 
 constexpr int kGatherChunk = 8;
 
-// Number of 32-bit words holding a lane's per-step LDS gather addresses
-// (16-bit byte addresses, two per word).
-template <int KMAX>
-constexpr int addr_words() { return (KMAX + 1) / 2; }
 
 // Schedule policies.  Both run out = M * in for the cell's matrix held as
 // schedule values a[] (this lane's KMAX steps) and packed LDS byte addresses
@@ -107,16 +163,16 @@ constexpr int addr_words() { return (KMAX + 1) / 2; }
 template <int LANES_, int RPL_, int KMAX_>
 struct DynSched {
   static constexpr int LANES = LANES_, RPL = RPL_, KMAX = KMAX_;
+  static constexpr int PACK = 2, NW = (KMAX + 1) / 2;
   uint64_t f0_, f1_;
   __device__ explicit DynSched(const DevSchedule& d) : f0_(d.flush[0]), f1_(d.flush[1]) {}
 
   // T = double, or float stored in the low half of double-spaced slots
   // (so both precisions share the slot layout and the gather addresses).
   template <typename T>
-  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
-                                       const char* lds, double* xb, double* yb, int gl, const int (&rows)[RPL],
-                                       const T (&in)[RPL], T (&out)[RPL]) const {
-    constexpr int NW = addr_words<KMAX>();
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[NW], const char* lds, double* xb,
+                                       double* yb, int gl, const int (&rows)[RPL], const T (&in)[RPL],
+                                       T (&out)[RPL]) const {
     const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
     uint32_t ad[NW];
     opaque_copy<NW>(ad_, ad);
@@ -132,7 +188,7 @@ struct DynSched {
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         const int s = s0 + i;
-        if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
+        if (s < KMAX) g[i] = *(const T*)(lds + step_addr<PACK>(ad, s));
       }
 #pragma unroll
       for (int i = 0; i < C; ++i) {
@@ -162,6 +218,8 @@ struct StaticSched {
   static constexpr int LANES = LANES_;
   static constexpr int RPL = sizeof...(SEG);
   static constexpr int KMAX = (SEG + ...);
+  // short schedules keep one address per word (no extraction on the hot path)
+  static constexpr int PACK = KMAX <= 48 ? 1 : 2, NW = (KMAX + PACK - 1) / PACK;
   __device__ explicit StaticSched(const DevSchedule&) {}
 
   // slot of step s, and whether s is the last step of its slot
@@ -194,12 +252,10 @@ struct StaticSched {
   }
 
   template <typename T>
-  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[addr_words<KMAX>()],
-                                       const char* lds, double* xb, double* /*yb*/, int /*gl*/,
-                                       const int (&rows)[RPL], const T (&in)[RPL], T (&out)[RPL]) const {
-    constexpr int NW = addr_words<KMAX>();
-    uint32_t ad[NW];
-    opaque_copy<NW>(ad_, ad);
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], const char* lds, double* xb,
+                                       double* /*yb*/, int /*gl*/, const int (&rows)[RPL], const T (&in)[RPL],
+                                       T (&out)[RPL]) const {
+    opaque_inplace<NW>(ad);
 #pragma unroll
     for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
     wave_sync();
@@ -213,7 +269,7 @@ struct StaticSched {
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         const int s = s0 + i;
-        if (s < KMAX) g[i] = *(const T*)(lds + step_addr(ad, s));
+        if (s < KMAX) g[i] = *(const T*)(lds + step_addr<PACK>(ad, s));
       }
 #pragma unroll
       for (int i = 0; i < C; ++i) {

@@ -24,20 +24,25 @@
 
 namespace bcs {
 
-template <class S>
-__device__ __forceinline__ void fp64_body(const KParams& P) {
+// One mechanism's persistent solve loop: this wave's cell slots claim cells
+// from P.queue[0] until it is exhausted.  `lds` is the workgroup's LDS base,
+// wave_base the start (in doubles) of this wave's slot region and ent_lds
+// the LDS copy of the schedule's value positions.
+// ADJ: -1 = forward or adjoint chosen by P.adjoint at run time (the
+// precompiled generic kernels), 0 = forward only, 1 = adjoint only (kernels
+// compiled per pattern, which then carry no code for the other mode).
+template <class S, int ADJ = -1>
+__device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave_base, const int32_t* ent_lds) {
   using namespace dev;
+  const bool adjoint = ADJ < 0 ? (P.adjoint != 0) : (ADJ == 1);
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
-  constexpr int G = 64 / LANES;
   const S sch(P.sched);
-  constexpr int NW = addr_words<KMAX>();
-  extern __shared__ double lds[];
+  constexpr int NW = S::NW, PACK = S::PACK;
   const char* ldsb = (const char*)lds;
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
   const int gl = lane & (LANES - 1);
   const int grp = lane / LANES;
-  const int slot_base = (wv * G + grp) * P.xs;  // in doubles
+  const int slot_base = wave_base + grp * P.xs;  // in doubles
   double* xb = lds + slot_base;          // SpMV operand (n + spare)
   double* yb = xb + P.yoff;               // SpMV result, slot-major RPL x LANES
 
@@ -46,16 +51,7 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   // This lane's LDS gather addresses (the schedule is shared by every cell
   // of the plan and padded to exactly KMAX steps).
   uint32_t ad[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int s = 2 * q + i;
-      if (s < KMAX) w |= (uint32_t)((slot_base + P.sched.col[s * LANES + gl]) * 8) << (16 * i);
-    }
-    ad[q] = w;
-  }
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, slot_base, gl);
   // Owned rows; a padding row (-1) stages into the spare LDS element n.
   int rows[RPL];
 #pragma unroll
@@ -64,11 +60,6 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
     rows[j] = rj >= 0 ? rj : n;
   }
 
-  // The schedule's value positions, shared by every cell slot of the
-  // workgroup, copied once into LDS after the cell slots.
-  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
-  for (int i = threadIdx.x; i < KMAX * LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
-  __syncthreads();
   int dpos[RPL];  // CSR position of the diagonal of each owned row
 #pragma unroll
   for (int j = 0; j < RPL; ++j) dpos[j] = P.diag_pos[rows[j] < n ? rows[j] : 0] & kEntPosMask;
@@ -78,26 +69,19 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   // column-scaled (Ahat = A D^-1, right preconditioning), so xv holds
   // xhat = D x and x = D^-1 xhat is formed when the cell finishes.
   double xv[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];
+  double bb[RPL], dinv[RPL];  // b and diag(A)^-1 of the owned rows
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
   int64_t cell = 0;
 
-  // diag(A)^-1 of this lane's rows (0 for padding rows).
-  auto diag_inv = [&](int j) -> double {
-    const double dvj = P.values[cell * nnz + dpos[j]];
-    const double g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
-    const double d = (P.kind == kJGamma) ? 1.0 - g * dvj : dvj;
-    return rows[j] < n ? 1.0 / d : 0.0;
-  };
-
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {
     if (P.precond) {
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) xv[j] = diag_inv(j) * xv[j];
+      for (int j = 0; j < RPL; ++j) xv[j] = dinv[j] * xv[j];
     }
-    if (P.adjoint) {
+    if (adjoint) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
         xb[rows[j]] = xv[j];
@@ -156,7 +140,8 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
           const bool real = rows[j] < n;
           const double bj = bc[real ? rows[j] : 0];
           dv[j] = vals[dpos[j]];
-          r[j] = real ? bj : 0.0;
+          bb[j] = real ? bj : 0.0;
+          r[j] = bb[j];
           xv[j] = 0;
         }
         asm volatile("" ::: "memory");  // re-read the flags below instead of keeping them live
@@ -171,13 +156,14 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
 #pragma unroll
           for (int j = 0; j < RPL; ++j) {
             const double d = (P.kind == kJGamma) ? 1.0 - g * dv[j] : dv[j];
-            xb[rows[j]] = (rows[j] < n) ? 1.0 / d : 0.0;
+            dinv[j] = (rows[j] < n) ? 1.0 / d : 0.0;
+            xb[rows[j]] = dinv[j];
           }
           wave_sync();
           uint32_t ado[NW];
           opaque_copy<NW>(ad, ado);
 #pragma unroll
-          for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr(ado, s));
+          for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr<PACK>(ado, s));
           wave_sync();
         }
         const double bn2 = gsum<LANES>(ldot<RPL>(r, r));
@@ -228,40 +214,41 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
         alpha = rho / sigma;
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
+        // t = A s is formed before the half-step test so that ||s||^2,
+        // (t, s) and (t, t) are reduced together (one reduction latency
+        // instead of two; t is discarded on a half-step exit)
+        sch.spmv(a, ad, ldsb, xb, yb, gl, rows, r, t);
         const double sn2 = gsum<LANES>(ldot<RPL>(r, r));
+        const double tt = gsum<LANES>(ldot<RPL>(t, t));
+        const double ts = gsum<LANES>(ldot<RPL>(t, r));
         if (!finite(sn2)) {
           ended = kNonfinite;
         } else if (sn2 <= tol2) {
 #pragma unroll
           for (int j = 0; j < RPL; ++j) xv[j] = xv[j] + alpha * p[j];
           ended = kConverged;
+        } else if (!finite(tt)) {
+          ended = kNonfinite;
+        } else if (tt == 0.0) {
+          ended = kBreakdown;
         } else {
-          sch.spmv(a, ad, ldsb, xb, yb, gl, rows, r, t);
-          const double tt = gsum<LANES>(ldot<RPL>(t, t));
-          const double ts = gsum<LANES>(ldot<RPL>(t, r));
-          if (!finite(tt)) {
+          omega = ts / tt;
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) {
+            xv[j] = xv[j] + alpha * p[j] + omega * r[j];
+            r[j] = r[j] - omega * t[j];
+          }
+          const double rn2 = gsum<LANES>(ldot<RPL>(r, r));
+          const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+          if (!finite(rn2)) {
             ended = kNonfinite;
-          } else if (tt == 0.0) {
+          } else if (rn2 <= tol2) {
+            ended = kConverged;
+          } else if (omega == 0.0) {
             ended = kBreakdown;
           } else {
-            omega = ts / tt;
-#pragma unroll
-            for (int j = 0; j < RPL; ++j) {
-              xv[j] = xv[j] + alpha * p[j] + omega * r[j];
-              r[j] = r[j] - omega * t[j];
-            }
-            const double rn2 = gsum<LANES>(ldot<RPL>(r, r));
-            const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
-            if (!finite(rn2)) {
-              ended = kNonfinite;
-            } else if (rn2 <= tol2) {
-              ended = kConverged;
-            } else if (omega == 0.0) {
-              ended = kBreakdown;
-            } else {
-              rho_prev = rho;
-              rho = rho_next;
-            }
+            rho_prev = rho;
+            rho = rho_next;
           }
         }
       }
@@ -270,15 +257,8 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
     if (ended >= 0) {
       // The true residual of the current iterate decides (t is free here).
       sch.spmv(a, ad, ldsb, xb, yb, gl, rows, xv, t);
-      {
-        const double* bc = P.b + cell * n;
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) {
-          const bool real = rows[j] < n;
-          const double bj = bc[real ? rows[j] : 0];
-          t[j] = (real ? bj : 0.0) - t[j];
-        }
-      }
+      for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
       const double tt2 = gsum<LANES>(ldot<RPL>(t, t));
       const double res = __builtin_sqrt(tt2) / bn;
       if (ended == kNonfinite || !finite(res)) {
@@ -297,12 +277,60 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
     }
   }
 
+}
+
+template <class S, int ADJ = -1>
+__device__ __forceinline__ void fp64_body(const KParams& P) {
+  constexpr int G = 64 / S::LANES;
+  extern __shared__ double lds[];
+  // The schedule's value positions, shared by every cell slot of the
+  // workgroup, copied once into LDS after the cell slots.
+  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
+  for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6;
+  fp64_run<S, ADJ>(P, lds, wv * G * P.xs, ent_lds);
   // The last wave to finish re-arms the work queue for the next launch.
-  if (lane == 0) {
+  if ((threadIdx.x & 63) == 0) {
     const unsigned long long done = atomicAdd(P.queue + 1, 1ull);
     if (done == (unsigned long long)(P.total_waves - 1)) {
       atomicExch(P.queue, 0ull);
       atomicExch(P.queue + 1, 0ull);
+    }
+  }
+}
+
+// Several mechanisms in one persistent launch.  Every wave drains the
+// mechanisms' work queues in the given order (the host orders them by cost
+// per cell, largest first), refilling its cell slots from the current queue;
+// a wave moves to the next mechanism once the current queue is empty and its
+// slots have finished.
+template <int I, class S, class... Rest>
+__device__ __forceinline__ void multi_run(const MultiParams& M, double* lds, int wave_base) {
+  fp64_run<S, 0>(M.m[I], lds, wave_base, (const int32_t*)(lds + M.ent_off[I]));
+  if constexpr (sizeof...(Rest) > 0) multi_run<I + 1, Rest...>(M, lds, wave_base);
+}
+
+template <class... Ss>
+__device__ __forceinline__ void multi_body(const MultiParams& M) {
+  extern __shared__ double lds[];
+  constexpr int NM = sizeof...(Ss);
+  constexpr int lanes[NM] = {Ss::LANES...};
+  constexpr int ksteps[NM] = {Ss::KMAX...};
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    int32_t* e = (int32_t*)(lds + M.ent_off[m]);
+    for (int i = threadIdx.x; i < ksteps[m] * lanes[m]; i += kWgThreads) e[i] = M.m[m].sched.ent[i];
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6;
+  multi_run<0, Ss...>(M, lds, wv * M.wave_stride);
+  if ((threadIdx.x & 63) == 0) {
+    const unsigned long long done = atomicAdd(M.m[0].queue + 1, 1ull);
+    if (done == (unsigned long long)(M.total_waves - 1)) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) atomicExch(M.m[m].queue, 0ull);
+      atomicExch(M.m[0].queue + 1, 0ull);
     }
   }
 }

@@ -108,8 +108,10 @@ int compile(const std::string& src, const std::string& arch, std::vector<char>* 
 
 }  // namespace
 
-int jit_kernel(const char* body, int lanes, const int* seg, int rpl, int waves_per_eu, size_t lds_bytes,
-               JitKernel* out, char* err, size_t errlen) {
+namespace {
+
+// Compile (or load from the caches) `source`, whose kernel is bcs_jit_kernel.
+int load_source(const std::string& source, size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     snprintf(err, errlen, "no HIP device");
@@ -121,18 +123,7 @@ int jit_kernel(const char* body, int lanes, const int* seg, int rpl, int waves_p
     return BCS_ERR_HIP;
   }
   std::string arch = prop.gcnArchName;
-  const size_t colon = arch.find(':');
-  const std::string base_arch = arch.substr(0, colon);
-
-  std::ostringstream src;
-  src << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
-      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
-  if (waves_per_eu > 0) src << ", " << waves_per_eu;
-  src << ") bcs_jit_kernel(bcs::KParams P) {\n"
-      << "  bcs::" << body << "<bcs::dev::StaticSched<" << lanes;
-  for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
-  src << ">>(P);\n}\n";
-  const std::string source = src.str();
+  const std::string base_arch = arch.substr(0, arch.find(':'));
   const std::string key = std::string(kJitSourceHash) + "|" + arch + "|" + source;
 
   std::lock_guard<std::mutex> lock(g_mu);
@@ -174,6 +165,43 @@ int jit_kernel(const char* body, int lanes, const int* seg, int rpl, int waves_p
   k.max_blocks = nb > 0 ? nb : 1;
   *out = k;
   return BCS_OK;
+}
+
+void sched_type(std::ostringstream& src, int lanes, const int* seg, int rpl) {
+  src << "bcs::dev::StaticSched<" << lanes;
+  for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
+  src << ">";
+}
+
+}  // namespace
+
+int jit_kernel(const char* body, int adjoint, int lanes, const int* seg, int rpl, int waves_per_eu,
+               size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
+  std::ostringstream src;
+  src << "// device sources " << kJitSourceHash << "\n"  // no compiler cache may reuse code across header versions
+      << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
+  if (waves_per_eu > 0) src << ", " << waves_per_eu;
+  src << ") bcs_jit_kernel(bcs::KParams P) {\n  bcs::" << body << "<";
+  sched_type(src, lanes, seg, rpl);
+  if (std::string(body) == "fp64_body") src << ", " << (adjoint ? 1 : 0);
+  src << ">(P);\n}\n";
+  return load_source(src.str(), lds_bytes, out, err, errlen);
+}
+
+int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const int* rpl, size_t lds_bytes,
+                     JitKernel* out, char* err, size_t errlen) {
+  std::ostringstream src;
+  src << "// device sources " << kJitSourceHash << "\n"
+      << "#include \"bcs_fp64.h\"\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_jit_kernel(bcs::MultiParams P) {\n"
+      << "  bcs::multi_body<";
+  for (int m = 0; m < nmech; ++m) {
+    if (m) src << ", ";
+    sched_type(src, lanes[m], seg[m], rpl[m]);
+  }
+  src << ">(P);\n}\n";
+  return load_source(src.str(), lds_bytes, out, err, errlen);
 }
 
 }  // namespace bcs

@@ -84,4 +84,14 @@ struct KParams {
   int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the slot
 };
 
+// Arguments of a multi-mechanism launch.
+constexpr int kMaxMech = 8;
+struct MultiParams {
+  int32_t nmech;
+  int32_t wave_stride;          // LDS doubles per wave (slot regions of every mechanism fit)
+  int32_t total_waves;
+  int32_t ent_off[kMaxMech];    // LDS offset (doubles) of each mechanism's schedule copy
+  KParams m[kMaxMech];          // per-mechanism solve arguments (queue[0] = its work queue)
+};
+
 }  // namespace bcs

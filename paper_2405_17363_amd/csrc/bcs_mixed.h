@@ -24,7 +24,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   using namespace dev;
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
   constexpr int G = 64 / LANES;
-  constexpr int NW = addr_words<KMAX>();
+  constexpr int NW = S::NW, PACK = S::PACK;
   const S sch(P.sched);
   extern __shared__ double lds[];
   const char* ldsb = (const char*)lds;
@@ -38,16 +38,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   const int n = P.n, nnz = P.nnz;
 
   uint32_t ad[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int s = 2 * q + i;
-      if (s < KMAX) w |= (uint32_t)((slot_base + P.sched.col[s * LANES + gl]) * 8) << (16 * i);
-    }
-    ad[q] = w;
-  }
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, slot_base, gl);
   int rows[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
@@ -158,7 +149,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           const int32_t e = ent_lds[s * LANES + gl];
           const double jv = vals[e & kEntPosMask];
           const double a = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
-          const double sc = *(const double*)(ldsb + step_addr(ado, s));
+          const double sc = *(const double*)(ldsb + step_addr<PACK>(ado, s));
           a32[s] = (e & kEntPad) ? 0.f : (float)(a * sc);
         }
         wave_sync();

@@ -1,0 +1,124 @@
+"""Summaries of rocprofv3 output for the solve kernels.
+
+    python -m paper_2405_17363_amd.profiling stats  --trace DIR [--kernel NAME]
+    python -m paper_2405_17363_amd.profiling traffic --fetch DIR --write DIR --ncells C --lanes L --out FILE
+
+The traffic summary is a text file: '#' lines describe how it was made, the
+rest is one JSON object (read back with ``load_traffic``).
+
+``traffic`` reads two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (CSV
+output) of ``bench.py --copy-calibration``.  That run first copies a 1 GiB
+device buffer; the counters' readings for that copy (2^30 bytes read and
+2^30 bytes written) give the factor that turns counter units into bytes, and
+the same factors scale the solve kernel's readings.  The result records a
+hash of the kernel sources, so that a later benchmark can tell whether the
+kernel has changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 1 << 30
+
+
+def source_hash() -> str:
+    """Hash of the kernel and host sources of the library."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _csv(dirname: str, suffix: str):
+    paths = glob.glob(os.path.join(dirname, "**", "*" + suffix), recursive=True)
+    if not paths:
+        raise FileNotFoundError(f"no *{suffix} under {dirname}")
+    with open(paths[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_stats(trace_dir: str, kernel: str = "bcs_jit_kernel") -> dict:
+    for r in _csv(trace_dir, "kernel_stats.csv"):
+        if r["Name"] == kernel:
+            return {"kernel": kernel, "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                    "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
+    raise KeyError(kernel)
+
+
+def per_dispatch(pmc_dir: str, counter: str) -> list:
+    """[(kernel name, grid size, summed counter value)] in dispatch order."""
+    acc = collections.OrderedDict()
+    for r in _csv(pmc_dir, "counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        key = (int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]))
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+    return [(k[1], k[2], v) for k, v in sorted(acc.items())]
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_jit_kernel") -> dict:
+    f = per_dispatch(fetch_dir, "FETCH_SIZE")
+    w = per_dispatch(write_dir, "WRITE_SIZE")
+    # the calibration copy is the copy kernel with the largest write
+    copy_w = max((v for name, g, v in w if "copyBuffer" in name), default=0.0)
+    copy_f = max((v for name, g, v in f if "copyBuffer" in name), default=0.0)
+    if copy_w <= 0 or copy_f <= 0:
+        raise RuntimeError("calibration copy not found in the counter runs")
+    kf = COPY_BYTES / copy_f
+    kw = COPY_BYTES / copy_w
+    fk = [v for name, g, v in f if name == kernel]
+    wk = [v for name, g, v in w if name == kernel]
+    if not fk or not wk:
+        raise RuntimeError(f"{kernel} not found in the counter runs")
+    fetch = kf * sum(fk) / len(fk)
+    write = kw * sum(wk) / len(wk)
+    return {"kernel": kernel, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+            "hbm_bytes_per_launch": fetch + write, "fetch_factor": kf, "write_factor": kw,
+            "launches": len(fk), "source_hash": source_hash()}
+
+
+def load_traffic(path: str) -> dict:
+    with open(path) as f:
+        return json.loads("".join(line for line in f if not line.lstrip().startswith("#")))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--kernel", default="bcs_jit_kernel")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", default="bcs_jit_kernel")
+    t.add_argument("--ncells", type=int, required=True)
+    t.add_argument("--lanes", type=int, required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--note", action="append", default=[], help="header line for the summary (repeatable)")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(json.dumps(kernel_stats(a.trace, a.kernel)))
+        return 0
+    res = traffic(a.fetch, a.write, a.kernel)
+    res.update({"ncells": a.ncells, "lanes_per_cell": a.lanes})
+    with open(a.out, "w") as f:
+        for line in a.note:
+            f.write("# " + line + "\n")
+        json.dump(res, f, indent=1)
+        f.write("\n")
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -294,3 +294,43 @@ def test_permutation_and_repetition_bitwise(jit):
     for u, v, w in zip(a, a2, p):
         assert np.array_equal(u, v)
         assert np.array_equal(u[perm], w)
+
+
+# ------------------------------------------- one launch, several mechanisms --
+
+def test_config4_single_persistent_launch():
+    mechs = config_inputs(4, ncells=12000)
+    plans = [bcs.Plan(m.row_ptr, m.col_idx) for m, _ in mechs]
+    V = [gpu(c["values"]) for _, c in mechs]
+    Gm = [gpu(c["gamma"]) for _, c in mechs]
+    Bv = [gpu(c["b"]) for _, c in mechs]
+    outs = bcs.solve_multi(plans, V, Gm, Bv, RTOL, 200)
+    torch.cuda.synchronize()
+    for (mech, cells), plan, (x, it, res, st), v, g, b in zip(mechs, plans, outs, V, Gm, Bv):
+        x, it, res, st = (t.cpu().numpy() for t in (x, it, res, st))
+        # the same per-cell arithmetic as the single-mechanism kernel
+        xs, its, ress, sts, _ = bcs.solve_batch(plan, v, g, b, RTOL, 200)
+        torch.cuda.synchronize()
+        assert np.array_equal(st, sts.cpu().numpy()) and np.array_equal(it, its.cpu().numpy())
+        assert np.array_equal(x, xs.cpu().numpy()) and np.array_equal(res, ress.cpu().numpy())
+        check_against_oracle(mech, cells, x, it, res, st, min_status_agree=0.98)
+        rng = np.random.default_rng(mech.n + 1)
+        check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st,
+                         rng.choice(len(st), 80, replace=False))
+
+
+def test_multi_rejects_bad_arguments_and_accepts_empty_mechanisms():
+    mechs = config_inputs(4, ncells=400)
+    plans = [bcs.Plan(m.row_ptr, m.col_idx) for m, _ in mechs]
+    V = [gpu(c["values"]) for _, c in mechs]
+    Gm = [gpu(c["gamma"]) for _, c in mechs]
+    Bv = [gpu(c["b"]) for _, c in mechs]
+    with pytest.raises(bcs.BcsError):
+        bcs.solve_multi([plans[0], plans[0]], V[:1] * 2, Gm[:1] * 2, Bv[:1] * 2)
+    empty = [gpu(np.zeros((0, plans[1].nnz))), gpu(np.zeros(1)), gpu(np.zeros((0, plans[1].n)))]
+    outs = bcs.solve_multi([plans[0], plans[1]], [V[0], empty[0]], [Gm[0], empty[1]], [Bv[0], empty[2]])
+    torch.cuda.synchronize()
+    assert outs[1][0].shape[0] == 0
+    xs, its, ress, sts, _ = bcs.solve_batch(plans[0], V[0], Gm[0], Bv[0])
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], xs) and torch.equal(outs[0][3], sts)
