@@ -24,20 +24,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane exchange within 16-lane rows.  Every control used here reads a valid
+// lane for every lane, so bound_ctrl never zeroes a lane; it only lets the
+// move write its destination without first copying the source into it.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)u, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF,
-                                             false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
-                                         false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 
 // All-reduce sum over the LANES lanes of a cell.  Butterfly: every lane adds
@@ -117,6 +117,20 @@ __device__ __forceinline__ void opaque_copy(const uint32_t (&in)[N], uint32_t (&
   }
 }
 
+// Loads through 32-bit LDS byte addresses.  The gather addresses are kept as
+// absolute LDS addresses so that a gather is one ds_read with no address
+// arithmetic.
+typedef __attribute__((address_space(3))) char lds_char_t;
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(__UINTPTR_TYPE__)(const lds_char_t*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_load(uint32_t addr) {
+  return *(const __attribute__((address_space(3))) T*)(__UINTPTR_TYPE__)addr;
+}
+
 // LDS byte address of step s: PACK = 2 packs two 16-bit addresses per word
 // (saves VGPRs, costs one VALU op per step), PACK = 1 keeps one per word.
 template <int PACK, int N>
@@ -126,16 +140,16 @@ __device__ __forceinline__ uint32_t step_addr(const uint32_t (&ad)[N], int s) {
 }
 
 // Fill a lane's address words for schedule `col` (steps x lanes, step-major)
-// and a cell slot starting at slot_base doubles.
+// and a cell slot whose operand starts at LDS byte address `base`.
 template <int PACK, int KMAX, int LANES, int N>
-__device__ __forceinline__ void build_addr(uint32_t (&ad)[N], const uint8_t* col, int slot_base, int gl) {
+__device__ __forceinline__ void build_addr(uint32_t (&ad)[N], const uint8_t* col, uint32_t base, int gl) {
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     uint32_t w = 0;
 #pragma unroll
     for (int i = 0; i < PACK; ++i) {
       const int s = PACK * q + i;
-      if (s < KMAX) w |= (uint32_t)((slot_base + col[s * LANES + gl]) * 8) << (16 * i);
+      if (s < KMAX) w |= (base + (uint32_t)col[s * LANES + gl] * 8u) << (16 * i);
     }
     ad[q] = w;
   }
@@ -150,10 +164,10 @@ constexpr int kGatherChunk = 8;
 
 // Schedule policies.  Both run out = M * in for the cell's matrix held as
 // schedule values a[] (this lane's KMAX steps) and packed LDS byte addresses
-// ad[] (two 16-bit addresses per word).  `in` and `out` are this lane's owned
-// rows (padding rows are staged into the spare element n of the slice); xb is
-// the cell's operand slice, yb its result slice (RPL x LANES, slot-major),
-// lds the workgroup's LDS base.  Gathers are issued a chunk at a time, ahead
+// ad[] (absolute LDS byte addresses, one or two 16-bit addresses per word).
+// `in` and `out` are this lane's owned rows (padding rows are staged into the
+// spare element n of the slice); xb is the cell's operand slice and yb its
+// result slice (RPL x LANES, slot-major).  Gathers are issued a chunk at a time, ahead
 // of the chunk's FMAs.
 
 // Slot boundaries known only at run time (precompiled generic variants): the
@@ -170,7 +184,7 @@ struct DynSched {
   // T = double, or float stored in the low half of double-spaced slots
   // (so both precisions share the slot layout and the gather addresses).
   template <typename T>
-  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[NW], const char* lds, double* xb,
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[NW], double* xb,
                                        double* yb, int gl, const int (&rows)[RPL], const T (&in)[RPL],
                                        T (&out)[RPL]) const {
     const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
@@ -188,7 +202,7 @@ struct DynSched {
 #pragma unroll
       for (int i = 0; i < C; ++i) {
         const int s = s0 + i;
-        if (s < KMAX) g[i] = *(const T*)(lds + step_addr<PACK>(ad, s));
+        if (s < KMAX) g[i] = lds_load<T>(step_addr<PACK>(ad, s));
       }
 #pragma unroll
       for (int i = 0; i < C; ++i) {
@@ -252,7 +266,7 @@ struct StaticSched {
   }
 
   template <typename T>
-  __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], const char* lds, double* xb,
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], double* xb,
                                        double* /*yb*/, int /*gl*/, const int (&rows)[RPL], const T (&in)[RPL],
                                        T (&out)[RPL]) const {
     opaque_inplace<NW>(ad);
@@ -260,31 +274,26 @@ struct StaticSched {
     for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
     wave_sync();
     // two accumulators per slot (even / odd steps of the slot) halve the
-    // FMA dependency chain
+    // FMA dependency chain; gathers run kGatherChunk steps ahead of the FMAs
+    // that consume them
+    constexpr int W = kGatherChunk;
     T acc0 = 0, acc1 = 0;
+    T g[W];
 #pragma unroll
-    for (int s0 = 0; s0 < KMAX; s0 += kGatherChunk) {
-      constexpr int C = kGatherChunk;
-      T g[C];
+    for (int s = 0; s < W; ++s)
+      if (s < KMAX) g[s] = lds_load<T>(step_addr<PACK>(ad, s));
 #pragma unroll
-      for (int i = 0; i < C; ++i) {
-        const int s = s0 + i;
-        if (s < KMAX) g[i] = *(const T*)(lds + step_addr<PACK>(ad, s));
-      }
-#pragma unroll
-      for (int i = 0; i < C; ++i) {
-        const int s = s0 + i;
-        if (s < KMAX) {
-          if (((s - slot_start(s)) & 1) == 0)
-            acc0 = __builtin_fma(a[s], g[i], acc0);
-          else
-            acc1 = __builtin_fma(a[s], g[i], acc1);
-          if (ends_slot(s)) {
-            out[slot_of(s)] = acc0 + acc1;
-            acc0 = 0;
-            acc1 = 0;
-          }
-        }
+    for (int s = 0; s < KMAX; ++s) {
+      const T gv = g[s % W];
+      if (s + W < KMAX) g[s % W] = lds_load<T>(step_addr<PACK>(ad, s + W));
+      if (((s - slot_start(s)) & 1) == 0)
+        acc0 = __builtin_fma(a[s], gv, acc0);
+      else
+        acc1 = __builtin_fma(a[s], gv, acc1);
+      if (ends_slot(s)) {
+        out[slot_of(s)] = acc0 + acc1;
+        acc0 = 0;
+        acc1 = 0;
       }
     }
     wave_sync();

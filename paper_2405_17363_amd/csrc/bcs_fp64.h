@@ -38,7 +38,6 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
   const S sch(P.sched);
   constexpr int NW = S::NW, PACK = S::PACK;
-  const char* ldsb = (const char*)lds;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (LANES - 1);
   const int grp = lane / LANES;
@@ -51,7 +50,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
   // This lane's LDS gather addresses (the schedule is shared by every cell
   // of the plan and padded to exactly KMAX steps).
   uint32_t ad[NW];
-  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, slot_base, gl);
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(lds + slot_base), gl);
   // Owned rows; a padding row (-1) stages into the spare LDS element n.
   int rows[RPL];
 #pragma unroll
@@ -163,7 +162,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
           uint32_t ado[NW];
           opaque_copy<NW>(ad, ado);
 #pragma unroll
-          for (int s = 0; s < KMAX; ++s) a[s] *= *(const double*)(ldsb + step_addr<PACK>(ado, s));
+          for (int s = 0; s < KMAX; ++s) a[s] *= lds_load<double>(step_addr<PACK>(ado, s));
           wave_sync();
         }
         const double bn2 = gsum<LANES>(ldot<RPL>(r, r));
@@ -204,7 +203,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
 #pragma unroll
         for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       }
-      sch.spmv(a, ad, ldsb, xb, yb, gl, rows, p, v);
+      sch.spmv(a, ad, xb, yb, gl, rows, p, v);
       const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
       if (!finite(sigma)) {
         ended = kNonfinite;
@@ -217,7 +216,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
         // t = A s is formed before the half-step test so that ||s||^2,
         // (t, s) and (t, t) are reduced together (one reduction latency
         // instead of two; t is discarded on a half-step exit)
-        sch.spmv(a, ad, ldsb, xb, yb, gl, rows, r, t);
+        sch.spmv(a, ad, xb, yb, gl, rows, r, t);
         const double sn2 = gsum<LANES>(ldot<RPL>(r, r));
         const double tt = gsum<LANES>(ldot<RPL>(t, t));
         const double ts = gsum<LANES>(ldot<RPL>(t, r));
@@ -256,7 +255,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
     if (ended < 0 && it >= P.maxit) ended = kMaxit;
     if (ended >= 0) {
       // The true residual of the current iterate decides (t is free here).
-      sch.spmv(a, ad, ldsb, xb, yb, gl, rows, xv, t);
+      sch.spmv(a, ad, xb, yb, gl, rows, xv, t);
 #pragma unroll
       for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
       const double tt2 = gsum<LANES>(ldot<RPL>(t, t));

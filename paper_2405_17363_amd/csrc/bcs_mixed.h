@@ -27,7 +27,6 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   constexpr int NW = S::NW, PACK = S::PACK;
   const S sch(P.sched);
   extern __shared__ double lds[];
-  const char* ldsb = (const char*)lds;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int gl = lane & (LANES - 1);
@@ -38,7 +37,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   const int n = P.n, nnz = P.nnz;
 
   uint32_t ad[NW];
-  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, slot_base, gl);
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(lds + slot_base), gl);
   int rows[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
@@ -88,7 +87,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
       av[s] = (e & kEntPad) ? 0.0 : a;
     }
     double ax[RPL];
-    sch.spmv(av, ad, ldsb, xb, yb, gl, rows, xin, ax);
+    sch.spmv(av, ad, xb, yb, gl, rows, xin, ax);
     const double* bc = P.b + cell * n;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
@@ -149,7 +148,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           const int32_t e = ent_lds[s * LANES + gl];
           const double jv = vals[e & kEntPosMask];
           const double a = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * jv) : jv;
-          const double sc = *(const double*)(ldsb + step_addr<PACK>(ado, s));
+          const double sc = lds_load<double>(step_addr<PACK>(ado, s));
           a32[s] = (e & kEntPad) ? 0.f : (float)(a * sc);
         }
         wave_sync();
@@ -204,7 +203,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 #pragma unroll
           for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
         }
-        sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, p, v);
+        sch.spmv(a32, ad, xb, yb, gl, rows, p, v);
         const float sigma = gsum<LANES>(ldot<RPL>(rh, v));
         if (!finite(sigma)) {
           ended = kNonfinite;
@@ -222,7 +221,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
             for (int j = 0; j < RPL; ++j) d[j] = d[j] + alpha * p[j];
             ended = kConverged;
           } else {
-            sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, r, t);
+            sch.spmv(a32, ad, xb, yb, gl, rows, r, t);
             const float tt = gsum<LANES>(ldot<RPL>(t, t));
             const float ts = gsum<LANES>(ldot<RPL>(t, r));
             if (!finite(tt)) {
@@ -263,7 +262,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         // restart from the FP32 true residual of the scaled system
         --restarts_left;
         float ad32[RPL];
-        sch.spmv(a32, ad, ldsb, xb, yb, gl, rows, d, ad32);
+        sch.spmv(a32, ad, xb, yb, gl, rows, d, ad32);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           r[j] = (float)(r64[j] / rn) - ad32[j];
