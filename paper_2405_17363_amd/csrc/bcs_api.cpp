@@ -110,33 +110,62 @@ HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector
   return S;
 }
 
-// LDS layout of one cell slot, in doubles: the SpMV operand (n values plus
-// a spare element that padding rows write to), for the adjoint a second
-// n-vector, then the SpMV result block (RPL x LANES).  The stride is padded so
-// that the slots of a wave start on different LDS banks.
-struct SlotLayout {
-  int stride, xoff2, yoff;
+// Workgroup LDS layout, in doubles (the fields of KParams).  First one
+// operand block per cell slot: the SpMV operand (n values plus a spare
+// element that padding rows write to; the adjoint also stages lambda there
+// for its gradient).  Gathers address only these blocks, through 16-bit byte
+// addresses, so they must end below 64 KiB; their stride is 8 mod 32 doubles
+// so that the slots of a wave start on different LDS banks.  Then one state
+// block per slot: the SpMV result block (RPL x LANES) of the precompiled
+// kernels.  Then the tables: the schedule's value
+// positions (ksteps x lanes) and the diagonal's position in every row (n),
+// 32-bit words.
+struct WgLayout {
+  int xs = 0, wxs = 0, bbase = 0, bs = 0, wbs = 0, yoff = 0, tbase = 0;
+  size_t operand_bytes = 0, bytes = 0;
 };
 
-SlotLayout slot_layout(int n, int lanes, int rpl, int adjoint) {
-  SlotLayout L;
+int slots_per_wg(int lanes) { return bcs::kWavesPerWg * (64 / lanes); }
+
+// operand block stride and state block size of one slot
+void slot_sizes(int n, int lanes, int rpl, int* xs, int* bs) {
   const int xn = ((n + 1 + 7) / 8) * 8;
-  L.xoff2 = xn;
-  L.yoff = adjoint ? 2 * xn : xn;
-  const int used = L.yoff + rpl * lanes;
-  L.stride = ((used + 31) / 32) * 32 + 8;
+  *xs = ((xn + 31) / 32) * 32 + 8;
+  *bs = rpl * lanes;
+}
+
+size_t table_doubles(int n, int lanes, int ksteps) { return ((size_t)ksteps * lanes + (size_t)n + 1) / 2; }
+
+WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint) {
+  WgLayout L;
+  (void)adjoint;
+  slot_sizes(n, lanes, rpl, &L.xs, &L.bs);
+  L.wxs = (64 / lanes) * L.xs;
+  L.wbs = (64 / lanes) * L.bs;
+  L.bbase = bcs::kWavesPerWg * L.wxs;
+  L.tbase = L.bbase + bcs::kWavesPerWg * L.wbs;
+  L.operand_bytes = (size_t)L.bbase * sizeof(double);
+  L.bytes = ((size_t)L.tbase + table_doubles(n, lanes, ksteps)) * sizeof(double);
   return L;
 }
 
-// Cell slots of the workgroup plus the LDS copy of the schedule entries.
-size_t lds_bytes(int n, int lanes, int rpl, int ksteps, int adjoint) {
-  return (size_t)bcs::kWavesPerWg * (64 / lanes) * slot_layout(n, lanes, rpl, adjoint).stride * sizeof(double) +
-         (size_t)ksteps * lanes * 4;
+// LDS a workgroup may allocate: the device's limit, and at most 64 KiB
+// (the layouts are tested up to that size).
+size_t device_max_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                                               hipSuccess || v <= 0)
+    return 65536;
+  return std::min<size_t>((size_t)v, 65536);
 }
 
-// Largest per-lane step count a specialised kernel is compiled for (the
-// matrix values of a lane's steps live in VGPRs).
-constexpr int kMaxJitSteps = 160;
+bool layout_fits(const WgLayout& L) { return L.operand_bytes <= 65536 && L.bytes <= device_max_lds(); }
+
+// Whether a specialised kernel of ksteps steps and rpl rows per lane is worth
+// compiling: the lane's matrix values (2 VGPRs a step), gather addresses
+// (half a VGPR a step) and register-resident vectors (8 VGPRs a row) must
+// leave room in the 256 VGPRs of a wave; larger layouts would spill.
+bool jit_feasible(int ksteps, int rpl) { return 2 * ksteps + (ksteps + 1) / 2 + 8 * rpl <= 240; }
 
 // One launchable solve kernel with its schedule on the device.
 struct Kernel {
@@ -146,6 +175,7 @@ struct Kernel {
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
   size_t lds = 0;
+  WgLayout layout;
   bcs::DevSchedule d{};
   void* buf = nullptr;  // device schedule arrays
 
@@ -198,6 +228,35 @@ void free_kernel(Kernel* K) {
   K->buf = nullptr;
 }
 
+// Transposed pattern of (rp, ci): trp/tci its CSR arrays, tpos[q] the CSR
+// position in the original matrix of transposed entry q.
+void transpose_pattern(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>& trp,
+                       std::vector<int>& tci, std::vector<int>& tpos) {
+  const int nnz = rp[n];
+  trp.assign(n + 1, 0);
+  tci.assign(nnz, 0);
+  tpos.assign(nnz, 0);
+  for (int k = 0; k < nnz; ++k) trp[ci[k] + 1]++;
+  for (int j = 0; j < n; ++j) trp[j + 1] += trp[j];
+  std::vector<int> fill(trp.begin(), trp.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int q = fill[ci[k]]++;
+      tci[q] = i;
+      tpos[q] = k;
+    }
+}
+
+// Whether the adjoint kernel of a lanes-per-cell choice fits the LDS (the
+// adjoint shares the forward solve's layout, so forward candidates whose
+// adjoint would not fit are skipped).
+bool adjoint_fits(int n, const std::vector<int>& trp, const std::vector<int>& tci, const std::vector<int>& tpos,
+                  int lanes) {
+  const int rpl = (n + lanes - 1) / lanes;
+  const HostSchedule T = build_schedule(n, trp, tci, tpos, lanes, rpl, 0);
+  return jit_feasible(T.ksteps, rpl) && layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1));
+}
+
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
@@ -209,17 +268,21 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   HostSchedule S;
   if (use_jit) {
     S = build_schedule(n, rp, ci, pos, lanes, rpl, 0);
-    if (S.ksteps > kMaxJitSteps) return BCS_ERR_UNSUPPORTED;
+    if (!jit_feasible(S.ksteps, rpl)) return BCS_ERR_UNSUPPORTED;
     K.rpl = rpl;
     K.ksteps = S.ksteps;
-    K.lds = lds_bytes(n, lanes, rpl, S.ksteps, adjoint);
-    if (K.lds > 65536) return BCS_ERR_UNSUPPORTED;  // gather addresses are 16-bit
+    K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint);
+    if (!layout_fits(K.layout)) return BCS_ERR_UNSUPPORTED;
+    K.lds = K.layout.bytes;
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
     const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, lanes, S.seg.data(), rpl,
                                    waves_per_eu, K.lds, &K.jit, err, sizeof(err));
     if (rc != BCS_OK) return fail(rc, "%s", err);
+    // a forward candidate that spills registers is dropped (another lane
+    // count serves the pattern); the adjoint and the mixed form keep theirs
+    if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
     K.max_blocks = K.jit.max_blocks;
     K.seg = S.seg;
   } else {
@@ -231,7 +294,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       const bcs::Variant& v = vs[q];
       if (v.lanes != lanes || v.rpl < rpl) continue;
       HostSchedule T = build_schedule(n, rp, ci, pos, lanes, v.rpl, v.kmax);
-      if (T.ksteps > v.kmax || lds_bytes(n, lanes, v.rpl, v.kmax, adjoint) > 65536) continue;
+      if (T.ksteps > v.kmax || !layout_fits(wg_layout(n, lanes, v.rpl, v.kmax, adjoint))) continue;
       if (!best || v.rpl < best->rpl || (v.rpl == best->rpl && v.kmax < best->kmax)) {
         best = &v;
         S = std::move(T);
@@ -241,7 +304,8 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.var = best;
     K.rpl = best->rpl;
     K.ksteps = best->kmax;
-    K.lds = lds_bytes(n, lanes, best->rpl, best->kmax, adjoint);
+    K.layout = wg_layout(n, lanes, best->rpl, best->kmax, adjoint);
+    K.lds = K.layout.bytes;
     int nb = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, best->fp64_kernel, bcs::kWgThreads, K.lds));
     K.max_blocks = std::max(nb, 1);
@@ -276,7 +340,7 @@ struct bcs_plan {
   int32_t* diag_pos = nullptr;
   int16_t* coo_row = nullptr;
   int16_t* coo_col = nullptr;
-  unsigned long long* queue = nullptr;  // [0..1] forward solves, [2..3] adjoint solves
+  unsigned long long* queue = nullptr;  // forward solves' work queue, then the adjoint's (kQueueWords each)
 };
 
 namespace {
@@ -328,10 +392,14 @@ int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
 int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, unsigned long long* queue, hipStream_t stream) {
   P.sched = K.d;
   P.adjoint = K.adjoint;
-  const SlotLayout L = slot_layout(p->n, K.lanes, K.rpl, K.adjoint);
-  P.xs = L.stride;
-  P.xoff2 = L.xoff2;
+  const WgLayout& L = K.layout;
+  P.xs = L.xs;
+  P.wxs = L.wxs;
+  P.bbase = L.bbase;
+  P.bs = L.bs;
+  P.wbs = L.wbs;
   P.yoff = L.yoff;
+  P.tbase = L.tbase;
   P.queue = queue;
   const int grid = grid_for(p, K, P.ncells);
   P.total_waves = grid * bcs::kWavesPerWg;
@@ -536,8 +604,8 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     e = hipMemcpy(p->coo_row, crow.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemcpy(p->coo_col, ccol.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->queue, 4 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMemset(p->queue, 0, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->queue, 2 * bcs::kQueueWords * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(p->queue, 0, 2 * bcs::kQueueWords * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     release(p);
@@ -547,18 +615,8 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   // A and A^T patterns with value positions
   std::vector<int> pos(nnz);
   for (int k = 0; k < nnz; ++k) pos[k] = k;
-  std::vector<int> trp(n + 1, 0), tci(nnz), tpos(nnz);
-  for (int k = 0; k < nnz; ++k) trp[p->ci[k] + 1]++;
-  for (int j = 0; j < n; ++j) trp[j + 1] += trp[j];
-  {
-    std::vector<int> fill(trp.begin(), trp.end() - 1);
-    for (int i = 0; i < n; ++i)
-      for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
-        const int q = fill[p->ci[k]]++;
-        tci[q] = i;
-        tpos[q] = k;
-      }
-  }
+  std::vector<int> trp, tci, tpos;
+  transpose_pattern(n, p->rp, p->ci, trp, tci, tpos);
 
   // Lanes per cell.  Candidates that fit are either timed on a synthetic
   // batch (autotune) or ranked by wave-steps per cell (ksteps * lanes / 64).
@@ -574,6 +632,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   const int cand[3] = {16, 32, 64};
   for (int L : cand) {
     if (o.lanes_per_cell != 0 && o.lanes_per_cell != L) continue;
+    if (!adjoint_fits(n, trp, tci, tpos, L)) continue;
     Kernel K;
     g_err.clear();
     int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K);
@@ -644,6 +703,8 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   std::vector<int> pos(p->nnz);
   for (int k = 0; k < p->nnz; ++k) pos[k] = k;
   const bool jit = p->opt.jit == 1;
+  std::vector<int> trp, tci, tpos;
+  transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);
   int best_lanes = p->fwd.lanes;
   double best = 1e300;
   int rc = time_launches(p, p->fwd, P, 2, &best);
@@ -651,7 +712,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
   const int cand[3] = {16, 32, 64};
   for (int L : cand) {
-    if (L == p->fwd.lanes) continue;
+    if (L == p->fwd.lanes || !adjoint_fits(p->n, trp, tci, tpos, L)) continue;
     Kernel K;
     g_err.clear();
     int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K);
@@ -674,16 +735,6 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
     }
   }
   if (p->adj.lanes != best_lanes) {
-    std::vector<int> trp(p->n + 1, 0), tci(p->nnz), tpos(p->nnz);
-    for (int k = 0; k < p->nnz; ++k) trp[p->ci[k] + 1]++;
-    for (int j = 0; j < p->n; ++j) trp[j + 1] += trp[j];
-    std::vector<int> fill(trp.begin(), trp.end() - 1);
-    for (int i = 0; i < p->n; ++i)
-      for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
-        const int q = fill[p->ci[k]]++;
-        tci[q] = i;
-        tpos[q] = k;
-      }
     Kernel A;
     g_err.clear();
     rc = make_kernel(p->n, trp, tci, tpos, best_lanes, 1, jit, 0, false, &A);
@@ -759,7 +810,7 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
-  return launch(p, p->adj, P, p->queue + 2, (hipStream_t)stream);
+  return launch(p, p->adj, P, p->queue + bcs::kQueueWords, (hipStream_t)stream);
 }
 
 int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells,
@@ -792,23 +843,31 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
   const int nm = (int)order.size();
   bcs::MultiParams M{};
   M.nmech = nm;
-  int wave_stride = 0;
-  std::vector<SlotLayout> lay(nm);
+  // The mechanisms run one after another in each workgroup, so their slot
+  // blocks share the operand and state regions (each sized for the largest
+  // mechanism); every mechanism keeps its own tables.
+  std::vector<WgLayout> lay(nm);
+  int wxs = 0, wbs = 0;
   for (int q = 0; q < nm; ++q) {
     const Kernel& K = plans[order[q]]->fwd;
-    lay[q] = slot_layout(plans[order[q]]->n, K.lanes, K.rpl, 0);
-    wave_stride = std::max(wave_stride, (64 / K.lanes) * lay[q].stride);
+    lay[q] = wg_layout(plans[order[q]]->n, K.lanes, K.rpl, K.ksteps, 0);
+    wxs = std::max(wxs, lay[q].wxs);
+    wbs = std::max(wbs, lay[q].wbs);
   }
-  M.wave_stride = wave_stride;
-  size_t off = (size_t)bcs::kWavesPerWg * wave_stride;  // doubles
+  const int operand = bcs::kWavesPerWg * wxs;
+  size_t off = (size_t)operand + (size_t)bcs::kWavesPerWg * wbs;  // doubles
   for (int q = 0; q < nm; ++q) {
     const Kernel& K = plans[order[q]]->fwd;
+    lay[q].wxs = wxs;
+    lay[q].wbs = wbs;
+    lay[q].bbase = operand;
     M.ent_off[q] = (int32_t)off;
-    off += ((size_t)K.ksteps * K.lanes * 4 + 7) / 8;
+    off += table_doubles(plans[order[q]]->n, K.lanes, K.ksteps);
   }
   const size_t lds = off * 8;
-  if ((size_t)bcs::kWavesPerWg * wave_stride * 8 > 65536 || lds > 65536)
-    return fail(BCS_ERR_UNSUPPORTED, "the mechanisms need %zu bytes of LDS per workgroup (limit 64 KiB)", lds);
+  if ((size_t)operand * 8 > 65536 || lds > device_max_lds())
+    return fail(BCS_ERR_UNSUPPORTED, "the mechanisms need %zu bytes of LDS per workgroup (device limit %zu)", lds,
+                device_max_lds());
   std::vector<int> lanes(nm), rpl(nm);
   std::vector<const int*> segs(nm);
   for (int q = 0; q < nm; ++q) {
@@ -834,9 +893,13 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.refinements = nullptr;
     P.sched = p->fwd.d;
     P.adjoint = 0;
-    P.xs = lay[q].stride;
-    P.xoff2 = lay[q].xoff2;
+    P.xs = lay[q].xs;
+    P.wxs = lay[q].wxs;
+    P.bbase = lay[q].bbase;
+    P.bs = lay[q].bs;
+    P.wbs = lay[q].wbs;
     P.yoff = lay[q].yoff;
+    P.tbase = M.ent_off[q];
     P.queue = p->queue;
     M.m[q] = P;
     const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);

@@ -159,7 +159,31 @@ __device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
   return s < 64 ? ((f0 >> s) & 1ull) != 0 : ((f1 >> (s - 64)) & 1ull) != 0;
 }
 
-constexpr int kGatherChunk = 8;
+constexpr int kGatherChunk = 16;
+
+// Claim the next cell for a slot (LANES lanes starting at lane `leader`):
+// one atomic on the queue's claim counter by the slot's first lane,
+// broadcast to the slot.  Returns false once every cell has been handed out.
+__device__ __forceinline__ bool claim_cell(unsigned long long* queue, int64_t ncells, int leader, bool is_leader,
+                                           int64_t& cell) {
+  unsigned long long c = 0;
+  if (is_leader) c = atomicAdd(queue, 1ull);
+  c = __shfl(c, leader, 64);
+  cell = (int64_t)c;
+  return c < (unsigned long long)ncells;
+}
+
+// Called once per wave when it leaves the solve: the last wave re-arms the
+// queue for the next launch.
+__device__ __forceinline__ void queue_wave_done(unsigned long long* queue, int total_waves) {
+  if ((threadIdx.x & 63) == 0) {
+    const unsigned long long done = atomicAdd(queue + kQueueDone, 1ull);
+    if (done == (unsigned long long)(total_waves - 1)) {
+      atomicExch(queue, 0ull);
+      atomicExch(queue + kQueueDone, 0ull);
+    }
+  }
+}
 
 
 // Schedule policies.  Both run out = M * in for the cell's matrix held as

@@ -25,14 +25,16 @@
 namespace bcs {
 
 // One mechanism's persistent solve loop: this wave's cell slots claim cells
-// from P.queue[0] until it is exhausted.  `lds` is the workgroup's LDS base,
-// wave_base the start (in doubles) of this wave's slot region and ent_lds
-// the LDS copy of the schedule's value positions.
+// from the work queue P.queue until it is exhausted.  `lds` is the
+// workgroup's LDS base, wv the wave's index in the workgroup, ent_lds and
+// diag_lds the LDS copies of the schedule's value positions and of the
+// diagonal's position in every row.
 // ADJ: -1 = forward or adjoint chosen by P.adjoint at run time (the
 // precompiled generic kernels), 0 = forward only, 1 = adjoint only (kernels
 // compiled per pattern, which then carry no code for the other mode).
 template <class S, int ADJ = -1>
-__device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave_base, const int32_t* ent_lds) {
+__device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, const int32_t* ent_lds,
+                                         const int32_t* diag_lds) {
   using namespace dev;
   const bool adjoint = ADJ < 0 ? (P.adjoint != 0) : (ADJ == 1);
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
@@ -41,16 +43,15 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
   const int lane = threadIdx.x & 63;
   const int gl = lane & (LANES - 1);
   const int grp = lane / LANES;
-  const int slot_base = wave_base + grp * P.xs;  // in doubles
-  double* xb = lds + slot_base;          // SpMV operand (n + spare)
-  double* yb = xb + P.yoff;               // SpMV result, slot-major RPL x LANES
+  double* xb = lds + wv * P.wxs + grp * P.xs;                    // SpMV operand (n + spare)
+  double* yb = lds + P.bbase + wv * P.wbs + grp * P.bs + P.yoff;  // SpMV result, slot-major RPL x LANES
 
   const int n = P.n, nnz = P.nnz;
 
   // This lane's LDS gather addresses (the schedule is shared by every cell
   // of the plan and padded to exactly KMAX steps).
   uint32_t ad[NW];
-  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(lds + slot_base), gl);
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(xb), gl);
   // Owned rows; a padding row (-1) stages into the spare LDS element n.
   int rows[RPL];
 #pragma unroll
@@ -58,10 +59,6 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
     const int rj = P.sched.row[j * LANES + gl];
     rows[j] = rj >= 0 ? rj : n;
   }
-
-  int dpos[RPL];  // CSR position of the diagonal of each owned row
-#pragma unroll
-  for (int j = 0; j < RPL; ++j) dpos[j] = P.diag_pos[rows[j] < n ? rows[j] : 0] & kEntPosMask;
 
   double a[KMAX];
   // Krylov state of this lane's rows.  With Jacobi the matrix is staged
@@ -84,11 +81,10 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
         xb[rows[j]] = xv[j];
-        xb[P.xoff2 + rows[j]] = (rows[j] < n) ? P.xin[cell * n + rows[j]] : 0.0;
       }
       wave_sync();
       for (int k = gl; k < nnz; k += LANES)
-        P.grad_a[cell * nnz + k] = -xb[P.coo_row[k]] * xb[P.xoff2 + P.coo_col[k]];
+        P.grad_a[cell * nnz + k] = -xb[P.coo_row[k]] * P.xin[cell * n + P.coo_col[k]];
       wave_sync();
     }
 #pragma unroll
@@ -117,13 +113,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
 
   for (;;) {
     if (!active && !dead) {
-      unsigned long long c = 0;
-      if (gl == 0) c = atomicAdd(P.queue, 1ull);
-      c = __shfl(c, grp * LANES, 64);
-      if (c >= (unsigned long long)P.ncells) {
+      if (!claim_cell(P.queue, P.ncells, grp * LANES, gl == 0, cell)) {
         dead = true;
       } else {
-        cell = (int64_t)c;
         // Stage the cell: A = I - gamma J (or A) into registers, b, and the
         // Jacobi column scaling.  Value positions come from the LDS copy of
         // the schedule, so every global load of the cell is independent and
@@ -138,7 +130,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
         for (int j = 0; j < RPL; ++j) {
           const bool real = rows[j] < n;
           const double bj = bc[real ? rows[j] : 0];
-          dv[j] = vals[dpos[j]];
+          dv[j] = vals[diag_lds[real ? rows[j] : 0]];
           bb[j] = real ? bj : 0.0;
           r[j] = bb[j];
           xv[j] = 0;
@@ -280,23 +272,17 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wave
 
 template <class S, int ADJ = -1>
 __device__ __forceinline__ void fp64_body(const KParams& P) {
-  constexpr int G = 64 / S::LANES;
   extern __shared__ double lds[];
-  // The schedule's value positions, shared by every cell slot of the
-  // workgroup, copied once into LDS after the cell slots.
-  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
+  // The schedule's value positions and the rows' diagonal positions, shared
+  // by every cell slot of the workgroup, copied once into LDS.
+  int32_t* ent_lds = (int32_t*)(lds + P.tbase);
+  int32_t* diag_lds = ent_lds + S::KMAX * S::LANES;
   for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
+  for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  fp64_run<S, ADJ>(P, lds, wv * G * P.xs, ent_lds);
-  // The last wave to finish re-arms the work queue for the next launch.
-  if ((threadIdx.x & 63) == 0) {
-    const unsigned long long done = atomicAdd(P.queue + 1, 1ull);
-    if (done == (unsigned long long)(P.total_waves - 1)) {
-      atomicExch(P.queue, 0ull);
-      atomicExch(P.queue + 1, 0ull);
-    }
-  }
+  fp64_run<S, ADJ>(P, lds, wv, ent_lds, diag_lds);
+  dev::queue_wave_done(P.queue, P.total_waves);
 }
 
 // Several mechanisms in one persistent launch.  Every wave drains the
@@ -305,9 +291,10 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
 // a wave moves to the next mechanism once the current queue is empty and its
 // slots have finished.
 template <int I, class S, class... Rest>
-__device__ __forceinline__ void multi_run(const MultiParams& M, double* lds, int wave_base) {
-  fp64_run<S, 0>(M.m[I], lds, wave_base, (const int32_t*)(lds + M.ent_off[I]));
-  if constexpr (sizeof...(Rest) > 0) multi_run<I + 1, Rest...>(M, lds, wave_base);
+__device__ __forceinline__ void multi_run(const MultiParams& M, double* lds, int wv) {
+  const int32_t* ent = (const int32_t*)(lds + M.ent_off[I]);
+  fp64_run<S, 0>(M.m[I], lds, wv, ent, ent + S::KMAX * S::LANES);
+  if constexpr (sizeof...(Rest) > 0) multi_run<I + 1, Rest...>(M, lds, wv);
 }
 
 template <class... Ss>
@@ -320,16 +307,20 @@ __device__ __forceinline__ void multi_body(const MultiParams& M) {
   for (int m = 0; m < NM; ++m) {
     int32_t* e = (int32_t*)(lds + M.ent_off[m]);
     for (int i = threadIdx.x; i < ksteps[m] * lanes[m]; i += kWgThreads) e[i] = M.m[m].sched.ent[i];
+    int32_t* dg = e + ksteps[m] * lanes[m];
+    for (int i = threadIdx.x; i < M.m[m].n; i += kWgThreads) dg[i] = M.m[m].diag_pos[i] & kEntPosMask;
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  multi_run<0, Ss...>(M, lds, wv * M.wave_stride);
+  multi_run<0, Ss...>(M, lds, wv);
+  // The last wave re-arms every mechanism's queue (mechanism 0's counts the
+  // finished waves).
   if ((threadIdx.x & 63) == 0) {
-    const unsigned long long done = atomicAdd(M.m[0].queue + 1, 1ull);
+    const unsigned long long done = atomicAdd(M.m[0].queue + kQueueDone, 1ull);
     if (done == (unsigned long long)(M.total_waves - 1)) {
 #pragma unroll
       for (int m = 0; m < NM; ++m) atomicExch(M.m[m].queue, 0ull);
-      atomicExch(M.m[0].queue + 1, 0ull);
+      atomicExch(M.m[0].queue + kQueueDone, 0ull);
     }
   }
 }
@@ -343,7 +334,7 @@ __global__ void __launch_bounds__(kWgThreads) k_fp64(KParams P) {
 #ifndef __HIPCC_RTC__
 template <int LANES, int RPL, int KMAX>
 hipError_t launch_fp64(const KParams& P, int grid, hipStream_t stream) {
-  const size_t lds = (size_t)kWavesPerWg * (64 / LANES) * P.xs * sizeof(double) + (size_t)KMAX * LANES * 4;
+  const size_t lds = ((size_t)P.tbase + ((size_t)KMAX * LANES + P.n + 1) / 2) * sizeof(double);
   hipLaunchKernelGGL((k_fp64<LANES, RPL, KMAX>), dim3(grid), dim3(kWgThreads), lds, stream, P);
   return hipGetLastError();
 }

@@ -33,7 +33,8 @@ const Variant* variants_l64(int* count);
 // plan creation with hipRTC (bcs_jit.cpp).
 struct JitKernel {
   hipFunction_t fn = nullptr;
-  int max_blocks = 0;  // resident workgroups per CU
+  int max_blocks = 0;   // resident workgroups per CU
+  int scratch = 0;      // private (spill) bytes per lane
 };
 
 // Compile (or fetch from the cache) a solve kernel -- body "fp64_body" or

@@ -163,6 +163,8 @@ int load_source(const std::string& source, size_t lds_bytes, JitKernel* out, cha
     return BCS_ERR_HIP;
   }
   k.max_blocks = nb > 0 ? nb : 1;
+  int local = 0;
+  if (hipFuncGetAttribute(&local, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, k.fn) == hipSuccess) k.scratch = local;
   *out = k;
   return BCS_OK;
 }

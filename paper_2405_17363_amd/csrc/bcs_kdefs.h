@@ -40,6 +40,11 @@ constexpr int32_t kEntPosMask = kEntPad - 1;
 // choice.  Rows are dealt to (slot j, lane l) in the order of decreasing row
 // length (a sliced-ELL layout with slice height = lanes per cell), so every
 // slot j spans the same steps [seg_begin_j, seg_end_j) on every lane.
+// Work queue of one solve: word 0 hands out cell indices, word 1 counts
+// finished waves; kQueueWords words are reserved per queue.
+constexpr int kQueueDone = 1;
+constexpr int kQueueWords = 16;
+
 struct DevSchedule {
   const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
   const uint8_t* col;   // [ksteps * lanes] gathered vector index (row of the other operand)
@@ -77,18 +82,24 @@ struct KParams {
   const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
   const int16_t* coo_col;   // [nnz] column of each CSR position
   int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
-  unsigned long long* queue;  // [0] next cell, [1] finished waves
+  unsigned long long* queue;  // kQueueWords words: claim counters, then finished waves
   int32_t total_waves;
-  int32_t xs;               // LDS elements per cell slot (doubles)
-  int32_t xoff2;            // offset of a second n-vector within the slot (adjoint)
-  int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the slot
+  // Workgroup LDS, in doubles: the operand block of slot g of wave w at
+  // w * wxs + g * xs (the only region gathers address, kept below 64 KiB
+  // for 16-bit addresses), its state block at bbase + w * wbs + g * bs, then
+  // the schedule tables at tbase.  Per-wave strides keep the waves of a
+  // multi-mechanism launch, which may be on different mechanisms at a time,
+  // in disjoint regions.
+  int32_t xs, wxs;          // operand block stride (n + spare, and a second n-vector for the adjoint), per wave
+  int32_t bbase, bs, wbs;   // state blocks: start, stride, stride per wave
+  int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the state block
+  int32_t tbase;            // start of the schedule tables
 };
 
 // Arguments of a multi-mechanism launch.
 constexpr int kMaxMech = 8;
 struct MultiParams {
   int32_t nmech;
-  int32_t wave_stride;          // LDS doubles per wave (slot regions of every mechanism fit)
   int32_t total_waves;
   int32_t ent_off[kMaxMech];    // LDS offset (doubles) of each mechanism's schedule copy
   KParams m[kMaxMech];          // per-mechanism solve arguments (queue[0] = its work queue)

@@ -31,20 +31,19 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   const int wv = threadIdx.x >> 6;
   const int gl = lane & (LANES - 1);
   const int grp = lane / LANES;
-  const int slot_base = (wv * G + grp) * P.xs;  // in doubles
-  double* xb = lds + slot_base;
-  double* yb = xb + P.yoff;
+  double* xb = lds + wv * P.wxs + grp * P.xs;
+  double* yb = lds + P.bbase + wv * P.wbs + grp * P.bs + P.yoff;
   const int n = P.n, nnz = P.nnz;
 
   uint32_t ad[NW];
-  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(lds + slot_base), gl);
+  build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(xb), gl);
   int rows[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
     const int rj = P.sched.row[j * LANES + gl];
     rows[j] = rj >= 0 ? rj : n;
   }
-  int32_t* ent_lds = (int32_t*)(lds + (size_t)kWavesPerWg * G * P.xs);
+  int32_t* ent_lds = (int32_t*)(lds + P.tbase);
   for (int i = threadIdx.x; i < KMAX * LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
   __syncthreads();
   int dpos[RPL];
@@ -120,13 +119,9 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 
   for (;;) {
     if (!active && !dead) {
-      unsigned long long c = 0;
-      if (gl == 0) c = atomicAdd(P.queue, 1ull);
-      c = __shfl(c, grp * LANES, 64);
-      if (c >= (unsigned long long)P.ncells) {
+      if (!claim_cell(P.queue, P.ncells, grp * LANES, gl == 0, cell)) {
         dead = true;
       } else {
-        cell = (int64_t)c;
         const double* vals = P.values + cell * nnz;
         g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
         const double* bc = P.b + cell * n;
@@ -305,13 +300,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
     }
   }
 
-  if (lane == 0) {
-    const unsigned long long done = atomicAdd(P.queue + 1, 1ull);
-    if (done == (unsigned long long)(P.total_waves - 1)) {
-      atomicExch(P.queue, 0ull);
-      atomicExch(P.queue + 1, 0ull);
-    }
-  }
+  dev::queue_wave_done(P.queue, P.total_waves);
 }
 
 }  // namespace bcs
