@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--ncells", type=int, default=100_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")
+    ap.add_argument("--no-forms", action="store_true", help="skip the adjoint and multi-mechanism timings")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer (reference for HBM byte counters)")
@@ -185,20 +186,79 @@ def main():
         except bcs.BcsError as e:
             mixed = {"error": str(e)}
 
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    adjoint = multi = None
+    if not args.no_forms:
+        # adjoint of the same batch: lambda = A^-T g (g ~ N(0,1)), dL/dA on the pattern
+        g = torch.as_tensor(np.random.default_rng(7).standard_normal((C, n)), device=dev)
+        xf = out[0].clone()
+        res_adj = {}
+
+        def astep():
+            res_adj["r"] = bcs.solve_batch_adjoint(plan, values, gamma, xf, g, RTOL, MAXIT)
+
+        ams = timed(astep, args.steps)
+        ast = res_adj["r"][4].cpu().numpy()
+        ares = res_adj["r"][3].cpu().numpy()
+        asolved = int(np.sum((ast == 0) & (ares <= RTOL)))
+        adjoint = {"value": round(asolved / (ams * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(ams, 4),
+                   "solved_fraction": round(asolved / C, 5),
+                   "iters_mean": round(float(res_adj["r"][2].float().mean().item()), 2),
+                   "algorithmic_bytes_per_cell": 16 * nnz + 24 * n + 32}
+        del g, xf, res_adj
+        # three mechanisms (n = 30 / 80 / 200, 12.5k / 25k / 12.5k cells) in one persistent launch,
+        # against the same cells solved by one launch per mechanism
+        mechs = config_inputs(4)
+        mplans = [bcs.Plan(m.row_ptr, m.col_idx, precond="jacobi") for m, _ in mechs]
+        MV = [torch.as_tensor(c["values"], device=dev) for _, c in mechs]
+        MG = [torch.as_tensor(c["gamma"], device=dev) for _, c in mechs]
+        MB = [torch.as_tensor(c["b"], device=dev) for _, c in mechs]
+        res_m = {}
+
+        def mstep_multi():
+            res_m["r"] = bcs.solve_multi(mplans, MV, MG, MB, RTOL, MAXIT)
+
+        def mstep_each():
+            for pl, v, gg, bb in zip(mplans, MV, MG, MB):
+                bcs.solve_batch(pl, v, gg, bb, RTOL, MAXIT)
+
+        mms = timed(mstep_multi, args.steps)
+        ems = timed(mstep_each, args.steps)
+        mc = sum(int(v.shape[0]) for v in MV)
+        msolved = sum(int(np.sum((r[3].cpu().numpy() == 0) & (r[2].cpu().numpy() <= RTOL))) for r in res_m["r"])
+        multi = {"value": round(msolved / (mms * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(mms, 4),
+                 "ncells": mc, "solved_fraction": round(msolved / mc, 5),
+                 "ms_one_launch_per_mechanism": round(ems, 4),
+                 "lanes_per_cell": [pl.info()["lanes_per_cell"] for pl in mplans]}
+        del MV, MG, MB, res_m
+
     cpu = None
     if not args.no_cpu:
         import oracle
 
         nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        # pilot on 2000 cells, then a sample sized for about 10 s of CPU work
+        # pilot on 2000 cells, then a sample sized for about 10 s of CPU work:
+        # a prefix of the batch, or the whole batch solved repeatedly
         S0 = min(2000, C)
         t1 = time.perf_counter()
         oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][:S0], cells["gamma"][:S0],
                            cells["b"][:S0], RTOL, MAXIT, precond=1, nthreads=nthreads)
         pilot = time.perf_counter() - t1
         S = int(min(C, max(S0, S0 * 10.0 / max(pilot, 1e-6))))
+        reps = max(1, min(20, int(10.0 / max(pilot * S / S0, 1e-6))))
         times = []
-        for _ in range(3 if S * pilot / S0 < 5 else 1):
+        for _ in range(reps):
             t1 = time.perf_counter()
             _, ci_it, ci_res, ci_st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][:S],
                                                          cells["gamma"][:S], cells["b"][:S], RTOL, MAXIT,
@@ -208,7 +268,7 @@ def main():
         csolved = int(np.sum((ci_st == 0) & (ci_res <= RTOL)))
         cpu = {"value": round(csolved / tcpu, 1), "unit": "cells/s", "cores": nthreads, "kind": "oracle",
                "sample": f"first {S} of the {C} cells, FP64 BiCGStab + Jacobi, OpenMP static over cells, "
-                         f"median of {len(times)} runs ({tcpu:.2f} s)"}
+                         f"median of {len(times)} runs of {tcpu:.2f} s"}
 
     line = {
         "metric": METRIC,
@@ -233,6 +293,8 @@ def main():
         "status_counts": np.bincount(status, minlength=4).tolist(),
         "roofline": roofline,
         "fp32_refine": mixed,
+        "adjoint": adjoint,
+        "multi_mechanism": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
