@@ -91,6 +91,30 @@ __device__ __forceinline__ T gsum(T v) {
   return v;
 }
 
+// All-reduce K values at once, level by level: every value goes through
+// exactly the steps of gsum (so each result is bitwise what gsum gives), and
+// the independent butterflies interleave, each one's moves and adds filling
+// the others' wait states.
+template <int LANES, int K, typename T>
+__device__ __forceinline__ void gsum_n(T (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp<0x141>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp<0x140>(v[k]);
+  if constexpr (LANES >= 32) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = pair_sum<false>(v[k]);
+  }
+  if constexpr (LANES >= 64) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = pair_sum<true>(v[k]);
+  }
+}
+
 // Hide a wave-uniform value from the optimiser so that conditions derived
 // from it are evaluated where they are used instead of being hoisted and kept
 // live across the whole kernel (which exhausts the scalar registers).

@@ -209,9 +209,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         // (t, s) and (t, t) are reduced together (one reduction latency
         // instead of two; t is discarded on a half-step exit)
         sch.spmv(a, ad, xb, yb, gl, rows, r, t);
-        const double sn2 = gsum<LANES>(ldot<RPL>(r, r));
-        const double tt = gsum<LANES>(ldot<RPL>(t, t));
-        const double ts = gsum<LANES>(ldot<RPL>(t, r));
+        double red3[3] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r)};
+        gsum_n<LANES>(red3);
+        const double sn2 = red3[0], tt = red3[1], ts = red3[2];
         if (!finite(sn2)) {
           ended = kNonfinite;
         } else if (sn2 <= tol2) {
@@ -229,8 +229,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
             xv[j] = xv[j] + alpha * p[j] + omega * r[j];
             r[j] = r[j] - omega * t[j];
           }
-          const double rn2 = gsum<LANES>(ldot<RPL>(r, r));
-          const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+          double red2[2] = {ldot<RPL>(r, r), ldot<RPL>(rh, r)};
+          gsum_n<LANES>(red2);
+          const double rn2 = red2[0], rho_next = red2[1];
           if (!finite(rn2)) {
             ended = kNonfinite;
           } else if (rn2 <= tol2) {

@@ -217,8 +217,9 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
             ended = kConverged;
           } else {
             sch.spmv(a32, ad, xb, yb, gl, rows, r, t);
-            const float tt = gsum<LANES>(ldot<RPL>(t, t));
-            const float ts = gsum<LANES>(ldot<RPL>(t, r));
+            float red2[2] = {ldot<RPL>(t, t), ldot<RPL>(t, r)};
+            gsum_n<LANES>(red2);
+            const float tt = red2[0], ts = red2[1];
             if (!finite(tt)) {
               ended = kNonfinite;
             } else if (tt == 0.f) {
@@ -230,8 +231,9 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
                 d[j] = d[j] + alpha * p[j] + omega * r[j];
                 r[j] = r[j] - omega * t[j];
               }
-              const float rn2 = gsum<LANES>(ldot<RPL>(r, r));
-              const float rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+              float red2b[2] = {ldot<RPL>(r, r), ldot<RPL>(rh, r)};
+              gsum_n<LANES>(red2b);
+              const float rn2 = red2b[0], rho_next = red2b[1];
               if (!finite(rn2)) {
                 ended = kNonfinite;
               } else if (rn2 <= itol2) {
