@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")
     ap.add_argument("--no-forms", action="store_true", help="skip the adjoint and multi-mechanism timings")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--cell-order", type=int, default=1, choices=(0, 1),
+                    help="1: cells handed out in the cost order (sorted by gamma on the device each step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer (reference for HBM byte counters)")
     return ap.parse_args()
@@ -85,7 +87,8 @@ def main():
     values = torch.as_tensor(cells["values"], device=dev)
     gamma = torch.as_tensor(cells["gamma"], device=dev)
     b = torch.as_tensor(cells["b"], device=dev)
-    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", lanes_per_cell=args.lanes)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", lanes_per_cell=args.lanes,
+                    cell_order=bool(args.cell_order))
     if args.lanes == 0:
         # the library's autotuner on this batch (outside the timed region)
         plan.autotune(values, gamma, b, RTOL, MAXIT)
@@ -158,7 +161,7 @@ def main():
     if not args.no_mixed:
         try:
             mplan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", precision="fp32_refine",
-                             lanes_per_cell=args.lanes)
+                             lanes_per_cell=args.lanes, cell_order=bool(args.cell_order))
             if args.lanes == 0:
                 mplan.autotune(values, gamma, b, RTOL, MAXIT)
             mout = [torch.empty_like(o) for o in out]

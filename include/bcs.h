@@ -26,8 +26,10 @@
  *     `status`.
  *   - ncells == 0 is a no-op that returns BCS_OK.
  *   - Solves that share a plan and overlap in time (different streams, or
- *     several host threads) race on the plan's work-queue counters: serialise
- *     them, or create one plan per stream.
+ *     several host threads) race on the plan's work-queue counters and cell
+ *     order scratch: serialise them, or create one plan per stream.
+ *   - With cell_order on, a solve may allocate (once, then whenever ncells
+ *     grows) a device array of 4 * ncells bytes that the plan keeps.
  */
 #ifndef BCS_H
 #define BCS_H
@@ -79,15 +81,23 @@ typedef struct bcs_options {
                                    spread of diagonally dominant cells) and keep the
                                    fastest; 0: choose by a cost model; see also
                                    bcs_plan_autotune for tuning on real data        */
-  int32_t reserved[5];          /* must be zero                                       */
+  int32_t cell_order;           /* 1: in a BCS_J_GAMMA solve with one gamma per cell,
+                                   hand the cells to the solver in a cost order:
+                                   cells sorted by gamma on the device (two small
+                                   kernels per call), handed out alternately from
+                                   the large-gamma and the small-gamma end, so that
+                                   expensive cells start early.  Results are
+                                   identical to index order.  0: index order       */
+  int32_t reserved[4];          /* must be zero                                       */
 } bcs_options;
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
-                                     work-queue counters (see the note above) */
+                                     work-queue counters and cell-order scratch
+                                     (see the note above) */
 
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
- * max_refine 10, jit 1, autotune 1. */
+ * max_refine 10, jit 1, autotune 1, cell_order 1. */
 void bcs_options_default(bcs_options* opt);
 
 /* Create a plan for an n x n pattern with nnz entries in CSR form

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -341,6 +342,11 @@ struct bcs_plan {
   int16_t* coo_row = nullptr;
   int16_t* coo_col = nullptr;
   unsigned long long* queue = nullptr;  // forward solves' work queue, then the adjoint's (kQueueWords each)
+  // cost order of the cells (forward, adjoint): sort state and order arrays
+  // of `order_cap` cells, grown on demand
+  uint32_t* order_state[2] = {nullptr, nullptr};
+  int32_t* order[2] = {nullptr, nullptr};
+  int64_t order_cap[2] = {0, 0};
 };
 
 namespace {
@@ -354,6 +360,10 @@ void release(bcs_plan* p) {
   if (p->diag_pos) (void)hipFree(p->diag_pos);
   if (p->coo_row) (void)hipFree(p->coo_row);
   if (p->queue) (void)hipFree(p->queue);
+  for (int k = 0; k < 2; ++k) {
+    if (p->order_state[k]) (void)hipFree(p->order_state[k]);
+    if (p->order[k]) (void)hipFree(p->order[k]);
+  }
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
 }
@@ -379,6 +389,30 @@ bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values
   P.coo_row = p->coo_row;
   P.coo_col = p->coo_col;
   return P;
+}
+
+// Cost order for a solve (kind 0 forward, 1 adjoint): with cell_order on,
+// per-cell gamma and at least two cells, sort the cells by gamma on the
+// stream and point the solve at the order.  The order array grows on demand
+// (the only allocation a solve call can make).
+int cell_order(bcs_plan* p, int kind, bcs::KParams* P, hipStream_t stream) {
+  P->order = nullptr;
+  if (p->opt.cell_order != 1 || p->opt.matrix_kind != BCS_J_GAMMA || P->gamma_stride == 0 || P->ncells < 2 ||
+      P->ncells > INT32_MAX)
+    return BCS_OK;
+  if (!p->order_state[kind]) HIP_TRY(hipMalloc((void**)&p->order_state[kind], bcs::kOrderStateWords * sizeof(uint32_t)));
+  if (P->ncells > p->order_cap[kind]) {
+    if (p->order[kind]) HIP_TRY(hipFree(p->order[kind]));
+    p->order[kind] = nullptr;
+    p->order_cap[kind] = 0;
+    HIP_TRY(hipMalloc((void**)&p->order[kind], (size_t)P->ncells * sizeof(int32_t)));
+    p->order_cap[kind] = P->ncells;
+  }
+  const hipError_t e =
+      bcs::launch_cell_order(P->gamma, P->gamma_stride, P->ncells, p->order_state[kind], p->order[kind], stream);
+  if (e != hipSuccess) return fail(BCS_ERR_HIP, "cell order launch: %s", hipGetErrorString(e));
+  P->order = p->order[kind];
+  return BCS_OK;
 }
 
 int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
@@ -519,6 +553,7 @@ void bcs_options_default(bcs_options* o) {
   o->max_refine = 10;
   o->jit = 1;
   o->autotune = 1;
+  o->cell_order = 1;
 }
 
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -548,7 +583,8 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     return fail(BCS_ERR_ARG, "FP32_REFINE needs 0 < inner_rtol < 1 and max_refine >= 1");
   if (o.jit != 0 && o.jit != 1) return fail(BCS_ERR_ARG, "jit must be 0 or 1");
   if (o.autotune != 0 && o.autotune != 1) return fail(BCS_ERR_ARG, "autotune must be 0 or 1");
-  for (int i = 0; i < 5; ++i)
+  if (o.cell_order != 0 && o.cell_order != 1) return fail(BCS_ERR_ARG, "cell_order must be 0 or 1");
+  for (int i = 0; i < 4; ++i)
     if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
   // pattern
@@ -788,6 +824,8 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   P.resid = resid;
   P.status = status;
   P.refinements = refinements;
+  rc = cell_order(const_cast<bcs_plan*>(p), 0, &P, (hipStream_t)stream);
+  if (rc != BCS_OK) return rc;
   return launch(p, p->fwd, P, p->queue, (hipStream_t)stream);
 }
 
@@ -810,6 +848,8 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
+  rc = cell_order(const_cast<bcs_plan*>(p), 1, &P, (hipStream_t)stream);
+  if (rc != BCS_OK) return rc;
   return launch(p, p->adj, P, p->queue + bcs::kQueueWords, (hipStream_t)stream);
 }
 

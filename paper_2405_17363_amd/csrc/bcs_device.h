@@ -187,14 +187,25 @@ constexpr int kGatherChunk = 16;
 
 // Claim the next cell for a slot (LANES lanes starting at lane `leader`):
 // one atomic on the queue's claim counter by the slot's first lane,
-// broadcast to the slot.  Returns false once every cell has been handed out.
-__device__ __forceinline__ bool claim_cell(unsigned long long* queue, int64_t ncells, int leader, bool is_leader,
-                                           int64_t& cell) {
+// broadcast to the slot.  With a cost order, queue position k maps to the
+// cell of rank k/2 from the expensive end (even k) or from the cheap end
+// (odd k).  Returns false once every cell has been handed out.
+__device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int32_t* order, int64_t ncells,
+                                           int leader, bool is_leader, int64_t& cell) {
   unsigned long long c = 0;
   if (is_leader) c = atomicAdd(queue, 1ull);
   c = __shfl(c, leader, 64);
-  cell = (int64_t)c;
-  return c < (unsigned long long)ncells;
+  if (c >= (unsigned long long)ncells) return false;
+  if (order) {
+    const int64_t k = (int64_t)c;
+    const int64_t rank = (k & 1) ? ncells - 1 - (k >> 1) : (k >> 1);
+    int32_t v = 0;
+    if (is_leader) v = order[rank];
+    cell = (int64_t)__shfl(v, leader, 64);
+  } else {
+    cell = (int64_t)c;
+  }
+  return true;
 }
 
 // Called once per wave when it leaves the solve: the last wave re-arms the

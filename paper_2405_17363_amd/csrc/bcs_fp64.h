@@ -113,7 +113,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.ncells, grp * LANES, gl == 0, cell)) {
+      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell)) {
         dead = true;
       } else {
         // Stage the cell: A = I - gamma J (or A) into registers, b, and the

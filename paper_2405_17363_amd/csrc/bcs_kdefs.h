@@ -45,6 +45,15 @@ constexpr int32_t kEntPosMask = kEntPad - 1;
 constexpr int kQueueDone = 1;
 constexpr int kQueueWords = 16;
 
+// Cost order of the cells: a counting sort of the cells by a bucket of
+// gamma (kOrderBuckets buckets of a quarter octave each, from 2^-16 up;
+// larger gamma = stiffer cell = more iterations).  Queue position k then
+// takes the cell of rank k/2 from the top for even k and from the bottom for
+// odd k, so expensive cells start early while cheap ones keep the refill rate
+// even.  The sort state is the bucket counts, then the bucket cursors.
+constexpr int kOrderBuckets = 128;
+constexpr int kOrderStateWords = 2 * kOrderBuckets;
+
 struct DevSchedule {
   const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
   const uint8_t* col;   // [ksteps * lanes] gathered vector index (row of the other operand)
@@ -82,7 +91,8 @@ struct KParams {
   const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
   const int16_t* coo_col;   // [nnz] column of each CSR position
   int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
-  unsigned long long* queue;  // kQueueWords words: claim counters, then finished waves
+  unsigned long long* queue;  // kQueueWords words: claim counter, then finished waves
+  const int32_t* order;       // cells in decreasing cost order, or null for index order
   int32_t total_waves;
   // Workgroup LDS, in doubles: the operand block of slot g of wave w at
   // w * wxs + g * xs (the only region gathers address, kept below 64 KiB

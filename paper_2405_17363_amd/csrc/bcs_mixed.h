@@ -119,7 +119,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.ncells, grp * LANES, gl == 0, cell)) {
+      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell)) {
         dead = true;
       } else {
         const double* vals = P.values + cell * nnz;

@@ -25,7 +25,7 @@ def test_options_struct_layout_and_defaults():
     assert o.precision == bcs.BCS_FP64 and o.precond == 1 and o.matrix_kind == bcs.BCS_J_GAMMA
     assert o.residual_replacement == 1 and o.breakdown_restarts == 1
     assert o.inner_rtol == 1e-4 and o.max_refine == 10
-    assert o.jit == 1 and o.autotune == 1
+    assert o.jit == 1 and o.autotune == 1 and o.cell_order == 1
     assert ctypes.sizeof(_Options) == 64
 
 
@@ -60,7 +60,7 @@ def test_invalid_patterns_are_rejected(rp, ci, what):
 
 @pytest.mark.parametrize("field,value", [("precision", 7), ("precond", 5), ("matrix_kind", 3),
                                           ("lanes_per_cell", 8), ("residual_replacement", 2),
-                                          ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3)])
+                                          ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3), ("cell_order", 2)])
 def test_invalid_options_are_rejected(field, value):
     rc, msg, h = _create([0, 1, 2], [0, 1], **{field: value})
     assert rc == -1, msg

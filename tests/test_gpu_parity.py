@@ -334,3 +334,32 @@ def test_multi_rejects_bad_arguments_and_accepts_empty_mechanisms():
     xs, its, ress, sts, _ = bcs.solve_batch(plans[0], V[0], Gm[0], Bv[0])
     torch.cuda.synchronize()
     assert torch.equal(outs[0][0], xs) and torch.equal(outs[0][3], sts)
+
+
+def test_cost_order_gives_index_order_results():
+    """Handing cells out sorted by gamma changes only where and when a cell is
+    solved: every output is bitwise the index-order output, every cell is
+    written (outputs start as NaN), also for a second, smaller batch that
+    reuses the plan's order array, and for the adjoint."""
+    mech, cells = config_inputs(2)[0]
+    V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
+    p0 = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, cell_order=False)
+    p1 = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, cell_order=True)
+    for C in (V.shape[0], 3001):
+        ref = bcs.solve_batch(p0, V[:C], G[:C], B[:C], RTOL, 200)
+        out = [torch.full((C, mech.n), float("nan"), dtype=torch.float64, device="cuda"),
+               torch.full((C,), -1, dtype=torch.int32, device="cuda"),
+               torch.full((C,), float("nan"), dtype=torch.float64, device="cuda"),
+               torch.full((C,), -1, dtype=torch.int32, device="cuda"),
+               torch.full((C,), -1, dtype=torch.int32, device="cuda")]
+        got = bcs.solve_batch(p1, V[:C], G[:C], B[:C], RTOL, 200, out=out)
+        torch.cuda.synchronize()
+        for a, b in zip(ref[:4], got[:4]):
+            assert torch.equal(a, b)
+    W = gpu(np.random.default_rng(3).standard_normal((V.shape[0], mech.n)))
+    x = bcs.solve_batch(p0, V, G, B, RTOL, 200)[0]
+    a0 = bcs.solve_batch_adjoint(p0, V, G, x, W, RTOL, 200)
+    a1 = bcs.solve_batch_adjoint(p1, V, G, x, W, RTOL, 200)
+    torch.cuda.synchronize()
+    for a, b in zip(a0, a1):
+        assert torch.equal(a, b)
