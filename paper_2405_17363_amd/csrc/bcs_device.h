@@ -187,21 +187,33 @@ constexpr int kGatherChunk = 16;
 
 // Claim the next cell for a slot (LANES lanes starting at lane `leader`):
 // one atomic on the queue's claim counter by the slot's first lane,
-// broadcast to the slot.  With a cost order, queue position k maps to the
-// cell of rank k/2 from the expensive end (even k) or from the cheap end
-// (odd k).  Returns false once every cell has been handed out.
+// broadcast to the slot.  Returns false once every cell has been handed out.
+// In index order a claim takes one queue position, the cell of that index.
+// With a cost order a claim takes the pair of positions (2i, 2i+1): the cell
+// of rank i from the expensive end, solved now, and the cell of rank i from
+// the cheap end, kept in `held` (-1 when none) and solved next without
+// another claim; both order entries are read with one memory round trip.
 __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int32_t* order, int64_t ncells,
-                                           int leader, bool is_leader, int64_t& cell) {
+                                           int leader, bool is_leader, int64_t& cell, int64_t& held) {
+  if (held >= 0) {
+    cell = held;
+    held = -1;
+    return true;
+  }
   unsigned long long c = 0;
-  if (is_leader) c = atomicAdd(queue, 1ull);
+  if (is_leader) c = atomicAdd(queue, order ? 2ull : 1ull);
   c = __shfl(c, leader, 64);
   if (c >= (unsigned long long)ncells) return false;
   if (order) {
-    const int64_t k = (int64_t)c;
-    const int64_t rank = (k & 1) ? ncells - 1 - (k >> 1) : (k >> 1);
-    int32_t v = 0;
-    if (is_leader) v = order[rank];
-    cell = (int64_t)__shfl(v, leader, 64);
+    const int64_t i = (int64_t)(c >> 1);
+    const bool pair = (int64_t)c + 1 < ncells;
+    int32_t v0 = 0, v1 = -1;
+    if (is_leader) {
+      v0 = order[i];
+      if (pair) v1 = order[ncells - 1 - i];
+    }
+    cell = (int64_t)__shfl(v0, leader, 64);
+    held = (int64_t)__shfl(v1, leader, 64);
   } else {
     cell = (int64_t)c;
   }

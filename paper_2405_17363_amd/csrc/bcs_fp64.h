@@ -69,7 +69,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
-  int64_t cell = 0;
+  int64_t cell = 0, held = -1;  // held: the second cell of a claimed pair
 
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {
@@ -113,7 +113,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell)) {
+      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held)) {
         dead = true;
       } else {
         // Stage the cell: A = I - gamma J (or A) into registers, b, and the

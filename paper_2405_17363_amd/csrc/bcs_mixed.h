@@ -58,7 +58,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   int it_in = 0, tot = 0, nref = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
   int phase = 0;  // 0: check / start an inner solve, 1: inner iterating, 2: refinement update
-  int64_t cell = 0;
+  int64_t cell = 0, held = -1;  // held: the second cell of a claimed pair
 
   auto finish = [&](int st, double res) {
 #pragma unroll
@@ -119,7 +119,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell)) {
+      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held)) {
         dead = true;
       } else {
         const double* vals = P.values + cell * nnz;
