@@ -185,35 +185,44 @@ __device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
 
 constexpr int kGatherChunk = 16;
 
+// Cells a slot takes per claim when the cells come in a cost order.
+constexpr int kClaimGroup = 2;
+
 // Claim the next cell for a slot (LANES lanes starting at lane `leader`):
 // one atomic on the queue's claim counter by the slot's first lane,
 // broadcast to the slot.  Returns false once every cell has been handed out.
 // In index order a claim takes one queue position, the cell of that index.
-// With a cost order a claim takes the pair of positions (2i, 2i+1): the cell
-// of rank i from the expensive end, solved now, and the cell of rank i from
-// the cheap end, kept in `held` (-1 when none) and solved next without
-// another claim; both order entries are read with one memory round trip.
+// With a cost order a claim takes kClaimGroup consecutive positions, whose
+// cells (queue position k is the cell of rank k/2 from the expensive end for
+// even k, from the cheap end for odd k) are read from the order in one
+// memory round trip; the first is solved now, the others are kept in
+// held[] (-1 when none) and solved next without another claim.
 __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int32_t* order, int64_t ncells,
-                                           int leader, bool is_leader, int64_t& cell, int64_t& held) {
-  if (held >= 0) {
-    cell = held;
-    held = -1;
+                                           int leader, bool is_leader, int64_t& cell,
+                                           int32_t (&held)[kClaimGroup - 1]) {
+  if (held[0] >= 0) {
+    cell = held[0];
+#pragma unroll
+    for (int q = 0; q + 1 < kClaimGroup - 1; ++q) held[q] = held[q + 1];
+    held[kClaimGroup - 2] = -1;
     return true;
   }
   unsigned long long c = 0;
-  if (is_leader) c = atomicAdd(queue, order ? 2ull : 1ull);
+  if (is_leader) c = atomicAdd(queue, order ? (unsigned long long)kClaimGroup : 1ull);
   c = __shfl(c, leader, 64);
   if (c >= (unsigned long long)ncells) return false;
   if (order) {
-    const int64_t i = (int64_t)(c >> 1);
-    const bool pair = (int64_t)c + 1 < ncells;
-    int32_t v0 = 0, v1 = -1;
-    if (is_leader) {
-      v0 = order[i];
-      if (pair) v1 = order[ncells - 1 - i];
+    int32_t v[kClaimGroup];
+#pragma unroll
+    for (int q = 0; q < kClaimGroup; ++q) {
+      const int64_t k = (int64_t)c + q;
+      const int64_t rank = (k & 1) ? ncells - 1 - (k >> 1) : (k >> 1);
+      v[q] = -1;
+      if (is_leader && k < ncells) v[q] = order[rank];
     }
-    cell = (int64_t)__shfl(v0, leader, 64);
-    held = (int64_t)__shfl(v1, leader, 64);
+    cell = (int64_t)__shfl(v[0], leader, 64);
+#pragma unroll
+    for (int q = 1; q < kClaimGroup; ++q) held[q - 1] = __shfl(v[q], leader, 64);
   } else {
     cell = (int64_t)c;
   }

@@ -69,7 +69,10 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
-  int64_t cell = 0, held = -1;  // held: the second cell of a claimed pair
+  int64_t cell = 0;
+  int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
+#pragma unroll
+  for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
 
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {

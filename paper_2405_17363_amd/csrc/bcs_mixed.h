@@ -58,7 +58,10 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   int it_in = 0, tot = 0, nref = 0, restarts_left = 0;
   bool first = true, active = false, dead = false;
   int phase = 0;  // 0: check / start an inner solve, 1: inner iterating, 2: refinement update
-  int64_t cell = 0, held = -1;  // held: the second cell of a claimed pair
+  int64_t cell = 0;
+  int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
+#pragma unroll
+  for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
 
   auto finish = [&](int st, double res) {
 #pragma unroll
