@@ -146,7 +146,7 @@ def main():
         "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
         "frac": round(fracs[bound], 4),
         "traffic": traffic,
-        "kernel": "bcs_jit_kernel (fp64, %d lanes/cell, %d rows/lane, %d steps/lane)" % (
+        "kernel": "bcs_solve_fp64 (%d lanes/cell, %d rows/lane, %d steps/lane)" % (
             info["lanes_per_cell"], info["rows_per_lane"], info["steps_per_lane"]),
         "avg_launch_ms": round(avg_launch_s * 1e3, 4),
         "hbm_gbs": round(hbm_gbs, 2),

@@ -110,8 +110,9 @@ int compile(const std::string& src, const std::string& arch, std::vector<char>* 
 
 namespace {
 
-// Compile (or load from the caches) `source`, whose kernel is bcs_jit_kernel.
-int load_source(const std::string& source, size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
+// Compile (or load from the caches) `source`, whose kernel is `name`.
+int load_source(const std::string& source, const char* name, size_t lds_bytes, JitKernel* out, char* err,
+                size_t errlen) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     snprintf(err, errlen, "no HIP device");
@@ -130,10 +131,10 @@ int load_source(const std::string& source, size_t lds_bytes, JitKernel* out, cha
   const std::string mkey = std::to_string(dev) + "|" + key;
   auto it = g_cache.find(mkey);
   if (it == g_cache.end()) {
-    char name[64];
-    snprintf(name, sizeof(name), "%016llx.co", (unsigned long long)fnv1a(key));
+    char fname[64];
+    snprintf(fname, sizeof(fname), "%016llx.co", (unsigned long long)fnv1a(key));
     const std::string dir = cache_dir();
-    const std::string path = dir + "/" + name;
+    const std::string path = dir + "/" + fname;
     std::vector<char> code;
     if (!read_file(path, &code)) {
       std::string log;
@@ -150,7 +151,7 @@ int load_source(const std::string& source, size_t lds_bytes, JitKernel* out, cha
       return BCS_ERR_HIP;
     }
     JitKernel k;
-    if (hipModuleGetFunction(&k.fn, mod, "bcs_jit_kernel") != hipSuccess) {
+    if (hipModuleGetFunction(&k.fn, mod, name) != hipSuccess) {
       snprintf(err, errlen, "compiled kernel not found in module");
       return BCS_ERR_HIP;
     }
@@ -184,11 +185,14 @@ int jit_kernel(const char* body, int adjoint, int lanes, const int* seg, int rpl
       << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
   if (waves_per_eu > 0) src << ", " << waves_per_eu;
-  src << ") bcs_jit_kernel(bcs::KParams P) {\n  bcs::" << body << "<";
+  // kernel names tell the forms apart in profiles
+  const bool fp64 = std::string(body) == "fp64_body";
+  const char* name = fp64 ? (adjoint ? "bcs_solve_adjoint" : "bcs_solve_fp64") : "bcs_solve_mixed";
+  src << ") " << name << "(bcs::KParams P) {\n  bcs::" << body << "<";
   sched_type(src, lanes, seg, rpl);
-  if (std::string(body) == "fp64_body") src << ", " << (adjoint ? 1 : 0);
+  if (fp64) src << ", " << (adjoint ? 1 : 0);
   src << ">(P);\n}\n";
-  return load_source(src.str(), lds_bytes, out, err, errlen);
+  return load_source(src.str(), name, lds_bytes, out, err, errlen);
 }
 
 int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const int* rpl, size_t lds_bytes,
@@ -196,14 +200,14 @@ int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const i
   std::ostringstream src;
   src << "// device sources " << kJitSourceHash << "\n"
       << "#include \"bcs_fp64.h\"\n"
-      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_jit_kernel(bcs::MultiParams P) {\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_solve_multi(bcs::MultiParams P) {\n"
       << "  bcs::multi_body<";
   for (int m = 0; m < nmech; ++m) {
     if (m) src << ", ";
     sched_type(src, lanes[m], seg[m], rpl[m]);
   }
   src << ">(P);\n}\n";
-  return load_source(src.str(), lds_bytes, out, err, errlen);
+  return load_source(src.str(), "bcs_solve_multi", lds_bytes, out, err, errlen);
 }
 
 }  // namespace bcs

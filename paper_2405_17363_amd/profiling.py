@@ -46,7 +46,7 @@ def _csv(dirname: str, suffix: str):
         return list(csv.DictReader(f))
 
 
-def kernel_stats(trace_dir: str, kernel: str = "bcs_jit_kernel") -> dict:
+def kernel_stats(trace_dir: str, kernel: str = "bcs_solve_fp64") -> dict:
     for r in _csv(trace_dir, "kernel_stats.csv"):
         if r["Name"] == kernel:
             return {"kernel": kernel, "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
@@ -65,7 +65,7 @@ def per_dispatch(pmc_dir: str, counter: str) -> list:
     return [(k[1], k[2], v) for k, v in sorted(acc.items())]
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_jit_kernel") -> dict:
+def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> dict:
     f = per_dispatch(fetch_dir, "FETCH_SIZE")
     w = per_dispatch(write_dir, "WRITE_SIZE")
     # the calibration copy is the copy kernel with the largest write
@@ -96,11 +96,11 @@ def main(argv=None) -> int:
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
-    s.add_argument("--kernel", default="bcs_jit_kernel")
+    s.add_argument("--kernel", default="bcs_solve_fp64")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--kernel", default="bcs_jit_kernel")
+    t.add_argument("--kernel", default="bcs_solve_fp64")
     t.add_argument("--ncells", type=int, required=True)
     t.add_argument("--lanes", type=int, required=True)
     t.add_argument("--out", required=True)
