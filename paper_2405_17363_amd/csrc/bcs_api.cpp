@@ -941,6 +941,8 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.yoff = lay[q].yoff;
     P.tbase = M.ent_off[q];
     P.queue = p->queue;
+    rc = cell_order(const_cast<bcs_plan*>(p), 0, &P, (hipStream_t)stream);  // each mechanism in its cost order
+    if (rc != BCS_OK) return rc;
     M.m[q] = P;
     const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
     need += (ncells[m] + cpw - 1) / cpw;
