@@ -68,7 +68,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   double bb[RPL], dinv[RPL];  // b and diag(A)^-1 of the owned rows
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
-  bool first = true, active = false, dead = false;
+  bool active = false, dead = false;
   int64_t cell = 0;
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
@@ -111,7 +111,6 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       v[j] = 0;
     }
     rho_prev = alpha = omega = 1;
-    first = true;
   };
 
   for (;;) {
@@ -189,15 +188,11 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
     } else if (rho == 0.0) {
       ended = kBreakdown;
     } else {
-      if (first) {
+      // After a start or restart p = v = 0 and rho_prev = alpha = omega = 1,
+      // so this gives p = r on the first iteration without a separate branch.
+      const double beta = (rho * alpha) / (rho_prev * omega);
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) p[j] = r[j];
-        first = false;
-      } else {
-        const double beta = (rho * alpha) / (rho_prev * omega);
-#pragma unroll
-        for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
-      }
+      for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       sch.spmv(a, ad, xb, yb, gl, rows, p, v);
       const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
       if (!finite(sigma)) {
