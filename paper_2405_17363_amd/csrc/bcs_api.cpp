@@ -43,6 +43,7 @@ bool verbose() { return std::getenv("BCS_VERBOSE") != nullptr; }
 struct HostSchedule {
   int lanes = 0, rpl = 0, ksteps = 0;
   std::vector<int> seg;  // slot segment lengths
+  int flags = 0;         // kSchedSpan / kSchedDiag (specialised kernels)
   std::vector<int32_t> ent;
   std::vector<uint8_t> col;
   std::vector<int16_t> row;
@@ -111,6 +112,129 @@ HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector
   return S;
 }
 
+// Schedule of a specialised kernel.  As build_schedule with kmax = 0, with
+// two optional shapes (allowed: mask of kSchedDiag / kSchedSpan):
+// - kSchedDiag (every row holds its diagonal): the diagonal entries are left
+//   out; the kernel starts each row's sum with the diagonal term instead.
+// - kSchedSpan: the nx longest rows each take slots 0 and 1 of one lane
+//   (lanes 0 .. nx-1, slot-1 row kRowSpan), the other rows fill slots 0 and 1
+//   of the remaining lanes and the later slots of every lane, longest first.
+//   A few long rows then no longer set the length of slot 0 for every lane;
+//   nx is chosen for the fewest steps (nx = 0, the plain deal, if none is
+//   shorter).
+// Returns ksteps = -1 if the result fails its own consistency check.
+HostSchedule build_schedule_jit(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+                                const std::vector<int>& pos, int lanes, int rpl, int allowed) {
+  bool diag_all = true;
+  for (int i = 0; i < n && diag_all; ++i) {
+    bool has = false;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) has |= ci[k] == i;
+    diag_all = has;
+  }
+  const bool split = (allowed & bcs::kSchedDiag) && diag_all;
+  auto kept = [&](int k, int i) { return !(split && ci[k] == i); };
+  std::vector<int> len(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) len[i] += kept(k, i);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return len[u] > len[v]; });
+
+  // slot lengths with nx spanning lanes; 0 if the rows do not fit
+  auto deal = [&](int nx, std::vector<int>& seg) -> int {
+    seg.assign(rpl, 1);
+    int q = nx;
+    for (int j = 0; j < rpl; ++j) {
+      const int cap = j < 2 ? lanes - nx : lanes;
+      for (int c = 0; c < cap && q < n; ++c, ++q) seg[j] = std::max(seg[j], len[order[q]]);
+    }
+    if (q < n) return 0;
+    if (nx > 0 && len[order[0]] > seg[0] + seg[1]) seg[1] = len[order[0]] - seg[0];
+    int total = 0;
+    for (int v : seg) total += v;
+    return total;
+  };
+  std::vector<int> seg;
+  int ks = deal(0, seg), nx = 0;
+  if ((allowed & bcs::kSchedSpan) && rpl >= 2)
+    for (int c = 1; c < lanes && c < n; ++c) {
+      std::vector<int> sc;
+      const int t = deal(c, sc);
+      if (t > 0 && t < ks) {
+        ks = t;
+        seg = sc;
+        nx = c;
+      }
+    }
+
+  HostSchedule S;
+  S.lanes = lanes;
+  S.rpl = rpl;
+  S.seg = seg;
+  S.ksteps = ks;
+  S.flags = (split ? bcs::kSchedDiag : 0) | (nx > 0 ? bcs::kSchedSpan : 0);
+  S.row.assign((size_t)rpl * lanes, -1);
+  int q = 0;
+  for (int l = 0; l < nx; ++l, ++q) {
+    S.row[l] = (int16_t)order[q];
+    S.row[lanes + l] = bcs::kRowSpan;
+  }
+  for (int j = 0; j < rpl; ++j)
+    for (int l = j < 2 ? nx : 0; l < lanes && q < n; ++l, ++q) S.row[(size_t)j * lanes + l] = (int16_t)order[q];
+  S.ent.assign((size_t)ks * lanes, bcs::kEntPad);
+  S.col.assign((size_t)ks * lanes, 0);
+  int s0 = 0;
+  for (int j = 0; j < rpl; ++j) {
+    for (int l = 0; l < lanes; ++l) {
+      const int i = S.row[(size_t)j * lanes + l];
+      if (i < 0) continue;
+      int t = 0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        if (!kept(k, i)) continue;
+        const size_t at = (size_t)(s0 + t) * lanes + l;
+        S.ent[at] = pos[k] | (ci[k] == i ? bcs::kEntDiag : 0);
+        S.col[at] = (uint8_t)ci[k];
+        ++t;
+      }
+    }
+    const int last = s0 + seg[j] - 1;
+    if (last < 64)
+      S.flush[0] |= 1ull << last;
+    else if (last < 128)
+      S.flush[1] |= 1ull << (last - 64);
+    s0 += seg[j];
+  }
+
+  // Check: every entry placed is a kept entry of the row that owns its lane
+  // and step (a spanning row owns slots 0 and 1), with its own column, and
+  // every kept entry is placed exactly once.
+  const int nnz = rp[n];
+  std::vector<int> inv(nnz, -1), seen(nnz, 0);
+  for (int k = 0; k < nnz; ++k)
+    if (pos[k] >= 0 && pos[k] < nnz) inv[pos[k]] = k;
+  int placed = 0;
+  for (int l = 0; l < lanes; ++l)
+    for (int j = 0, b = 0; j < rpl; b += seg[j], ++j) {
+      const int i = S.row[(size_t)j * lanes + l];
+      for (int st = b; st < b + seg[j]; ++st) {
+        const int32_t e = S.ent[(size_t)st * lanes + l];
+        if (e & bcs::kEntPad) continue;
+        const int owner = (i == bcs::kRowSpan) ? S.row[l] : i;
+        const int k = inv[e & bcs::kEntPosMask];
+        if (owner < 0 || k < rp[owner] || k >= rp[owner + 1] || !kept(k, owner) || S.col[(size_t)st * lanes + l] != ci[k] ||
+            seen[k]++) {
+          S.ksteps = -1;
+          return S;
+        }
+        ++placed;
+      }
+    }
+  int want = 0;
+  for (int i = 0; i < n; ++i) want += len[i];
+  if (placed != want) S.ksteps = -1;
+  return S;
+}
+
 // Workgroup LDS layout, in doubles (the fields of KParams).  First one
 // operand block per cell slot: the SpMV operand (n values plus a spare
 // element that padding rows write to; the adjoint also stages lambda there
@@ -172,6 +296,7 @@ bool jit_feasible(int ksteps, int rpl) { return 2 * ksteps + (ksteps + 1) / 2 + 
 struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
   std::vector<int> seg;               // slot segment lengths (specialised kernels)
+  int flags = 0;                      // schedule shape (specialised kernels)
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -248,14 +373,22 @@ void transpose_pattern(int n, const std::vector<int>& rp, const std::vector<int>
     }
 }
 
+// Schedule shapes the specialised FP64 kernels may use (the mixed form's
+// kernels take plain schedules).  BCS_SCHED overrides the mask (tuning).
+int sched_allowed(bool mixed) {
+  if (mixed) return 0;
+  if (const char* e = std::getenv("BCS_SCHED")) return std::atoi(e) & (bcs::kSchedDiag | bcs::kSchedSpan);
+  return bcs::kSchedDiag | bcs::kSchedSpan;
+}
+
 // Whether the adjoint kernel of a lanes-per-cell choice fits the LDS (the
 // adjoint shares the forward solve's layout, so forward candidates whose
 // adjoint would not fit are skipped).
 bool adjoint_fits(int n, const std::vector<int>& trp, const std::vector<int>& tci, const std::vector<int>& tpos,
                   int lanes) {
   const int rpl = (n + lanes - 1) / lanes;
-  const HostSchedule T = build_schedule(n, trp, tci, tpos, lanes, rpl, 0);
-  return jit_feasible(T.ksteps, rpl) && layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1));
+  const HostSchedule T = build_schedule_jit(n, trp, tci, tpos, lanes, rpl, sched_allowed(false));
+  return T.ksteps > 0 && jit_feasible(T.ksteps, rpl) && layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1));
 }
 
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
@@ -268,7 +401,8 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   K.adjoint = adjoint;
   HostSchedule S;
   if (use_jit) {
-    S = build_schedule(n, rp, ci, pos, lanes, rpl, 0);
+    S = build_schedule_jit(n, rp, ci, pos, lanes, rpl, sched_allowed(mixed));
+    if (S.ksteps < 0) return fail(BCS_ERR_UNSUPPORTED, "internal error: schedule check failed (lanes = %d)", lanes);
     if (!jit_feasible(S.ksteps, rpl)) return BCS_ERR_UNSUPPORTED;
     K.rpl = rpl;
     K.ksteps = S.ksteps;
@@ -278,7 +412,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, lanes, S.seg.data(), rpl,
+    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, lanes, S.flags, S.seg.data(), rpl,
                                    waves_per_eu, K.lds, &K.jit, err, sizeof(err));
     if (rc != BCS_OK) return fail(rc, "%s", err);
     // a forward candidate that spills registers is dropped (another lane
@@ -286,6 +420,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
     K.max_blocks = K.jit.max_blocks;
     K.seg = S.seg;
+    K.flags = S.flags;
   } else {
     if (mixed) return BCS_ERR_UNSUPPORTED;  // the mixed form exists only as specialised kernels
     int nv = 0;
@@ -322,9 +457,9 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     return rc;
   }
   if (verbose())
-    std::fprintf(stderr, "[bcs] kernel %s%s lanes=%d rpl=%d steps=%d adjoint=%d lds=%zu blocks/CU=%d\n",
-                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", lanes, K.rpl, K.ksteps, adjoint, K.lds,
-                 K.max_blocks);
+    std::fprintf(stderr, "[bcs] kernel %s%s lanes=%d rpl=%d steps=%d shape=%d adjoint=%d lds=%zu blocks/CU=%d\n",
+                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", lanes, K.rpl, K.ksteps, K.flags, adjoint,
+                 K.lds, K.max_blocks);
   *out = K;
   return BCS_OK;
 }
@@ -908,17 +1043,19 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
   if ((size_t)operand * 8 > 65536 || lds > device_max_lds())
     return fail(BCS_ERR_UNSUPPORTED, "the mechanisms need %zu bytes of LDS per workgroup (device limit %zu)", lds,
                 device_max_lds());
-  std::vector<int> lanes(nm), rpl(nm);
+  std::vector<int> lanes(nm), rpl(nm), flags(nm);
   std::vector<const int*> segs(nm);
   for (int q = 0; q < nm; ++q) {
     const Kernel& K = plans[order[q]]->fwd;
     lanes[q] = K.lanes;
     rpl[q] = K.rpl;
+    flags[q] = K.flags;
     segs[q] = K.seg.data();
   }
   bcs::JitKernel jk;
   char err[512] = {0};
-  int rc = bcs::jit_multi_kernel(nm, lanes.data(), segs.data(), rpl.data(), lds, &jk, err, sizeof(err));
+  int rc = bcs::jit_multi_kernel(nm, lanes.data(), flags.data(), segs.data(), rpl.data(), lds, &jk, err,
+                                 sizeof(err));
   if (rc != BCS_OK) return fail(rc, "%s", err);
   int64_t need = 0;
   for (int q = 0; q < nm; ++q) {

@@ -258,6 +258,7 @@ template <int LANES_, int RPL_, int KMAX_>
 struct DynSched {
   static constexpr int LANES = LANES_, RPL = RPL_, KMAX = KMAX_;
   static constexpr int PACK = 2, NW = (KMAX + 1) / 2;
+  static constexpr int FLAGS = 0;  // plain sliced-ELL schedules only
   uint64_t f0_, f1_;
   __device__ explicit DynSched(const DevSchedule& d) : f0_(d.flush[0]), f1_(d.flush[1]) {}
 
@@ -266,7 +267,7 @@ struct DynSched {
   template <typename T>
   __device__ __forceinline__ void spmv(const T (&a)[KMAX], const uint32_t (&ad_)[NW], double* xb,
                                        double* yb, int gl, const int (&rows)[RPL], const T (&in)[RPL],
-                                       T (&out)[RPL]) const {
+                                       T (&out)[RPL], const T (&)[RPL] = {}, T = T(0)) const {
     const uint64_t f0 = opaque(f0_), f1 = opaque(f1_);
     uint32_t ad[NW];
     opaque_copy<NW>(ad_, ad);
@@ -307,10 +308,13 @@ struct DynSched {
 // Slot segment lengths known at compile time (kernels compiled for one
 // pattern at plan creation): straight-line code, row sums land directly in
 // out[j].
-template <int LANES_, int... SEG>
+template <int LANES_, int FLAGS_, int... SEG>
 struct StaticSched {
   static constexpr int LANES = LANES_;
+  static constexpr int FLAGS = FLAGS_;
+  static constexpr bool SPAN = (FLAGS & kSchedSpan) != 0, DIAG = (FLAGS & kSchedDiag) != 0;
   static constexpr int RPL = sizeof...(SEG);
+  static_assert(!SPAN || RPL >= 2, "a spanning row needs two slots");
   static constexpr int KMAX = (SEG + ...);
   // short schedules keep one address per word (no extraction on the hot path)
   static constexpr int PACK = KMAX <= 48 ? 1 : 2, NW = (KMAX + PACK - 1) / PACK;
@@ -345,10 +349,14 @@ struct StaticSched {
     return false;
   }
 
+  // out = A in over the schedule.  dg (DIAG): each owned row's diagonal
+  // value, whose term starts the row's sum.  sm (SPAN): 1 on a lane whose
+  // slots 0 and 1 hold one row (slot 1's sum is added into slot 0 and slot
+  // 1, a padding row, ends 0), else 0.
   template <typename T>
   __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], double* xb,
                                        double* /*yb*/, int /*gl*/, const int (&rows)[RPL], const T (&in)[RPL],
-                                       T (&out)[RPL]) const {
+                                       T (&out)[RPL], const T (&dg)[RPL], T sm) const {
     opaque_inplace<NW>(ad);
 #pragma unroll
     for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
@@ -357,7 +365,7 @@ struct StaticSched {
     // FMA dependency chain; gathers run kGatherChunk steps ahead of the FMAs
     // that consume them
     constexpr int W = kGatherChunk;
-    T acc0 = 0, acc1 = 0;
+    T acc0 = DIAG ? dg[0] * in[0] : T(0), acc1 = 0;
     T g[W];
 #pragma unroll
     for (int s = 0; s < W; ++s)
@@ -371,12 +379,28 @@ struct StaticSched {
       else
         acc1 = __builtin_fma(a[s], gv, acc1);
       if (ends_slot(s)) {
-        out[slot_of(s)] = acc0 + acc1;
-        acc0 = 0;
+        constexpr int last = RPL - 1;
+        const int j = slot_of(s);
+        const int jn = j < last ? j + 1 : last;
+        out[j] = acc0 + acc1;
+        acc0 = (DIAG && j < last) ? dg[jn] * in[jn] : T(0);
         acc1 = 0;
       }
     }
+    if constexpr (SPAN) {
+      out[0] = __builtin_fma(sm, out[1], out[0]);
+      out[1] = (T(1) - sm) * out[1];
+    }
     wave_sync();
+  }
+
+  // Plain schedules (the mixed form's kernels): no diagonal or span terms.
+  template <typename T>
+  __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], double* xb, double* yb, int gl,
+                                       const int (&rows)[RPL], const T (&in)[RPL], T (&out)[RPL]) const {
+    static_assert(FLAGS == 0, "this schedule needs the diagonal and span terms");
+    const T none[RPL] = {};
+    spmv(a, ad, xb, yb, gl, rows, in, out, none, T(0));
   }
 };
 

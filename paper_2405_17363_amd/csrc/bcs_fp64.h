@@ -66,6 +66,14 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   // xhat = D x and x = D^-1 xhat is formed when the cell finishes.
   double xv[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];
   double bb[RPL], dinv[RPL];  // b and diag(A)^-1 of the owned rows
+  // Schedules without diagonal entries: the staged (column-scaled) diagonal
+  // value of each owned row, 0 for padding rows.
+  double dgv[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) dgv[j] = 0;
+  // 1 on a lane whose slots 0 and 1 hold one long row
+  double span = 0;
+  if constexpr (S::FLAGS & kSchedSpan) span = (P.sched.row[LANES + gl] == kRowSpan) ? 1.0 : 0.0;
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it = 0, restarts_left = 0;
   bool active = false, dead = false;
@@ -144,6 +152,13 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           const double av = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * a[s]) : a[s];
           a[s] = (e & kEntPad) ? 0.0 : av;
         }
+        if constexpr ((S::FLAGS & kSchedDiag) != 0) {
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) {
+            const double d = (P.kind == kJGamma) ? 1.0 - g * dv[j] : dv[j];
+            dgv[j] = (rows[j] < n) ? d : 0.0;
+          }
+        }
         if (P.precond) {
           // column scaling by diag(A)^-1, gathered through the LDS slice
 #pragma unroll
@@ -151,6 +166,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
             const double d = (P.kind == kJGamma) ? 1.0 - g * dv[j] : dv[j];
             dinv[j] = (rows[j] < n) ? 1.0 / d : 0.0;
             xb[rows[j]] = dinv[j];
+            if constexpr ((S::FLAGS & kSchedDiag) != 0) dgv[j] *= dinv[j];
           }
           wave_sync();
           uint32_t ado[NW];
@@ -193,7 +209,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       const double beta = (rho * alpha) / (rho_prev * omega);
 #pragma unroll
       for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
-      sch.spmv(a, ad, xb, yb, gl, rows, p, v);
+      sch.spmv(a, ad, xb, yb, gl, rows, p, v, dgv, span);
       const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
       if (!finite(sigma)) {
         ended = kNonfinite;
@@ -206,7 +222,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         // t = A s is formed before the half-step test so that ||s||^2,
         // (t, s) and (t, t) are reduced together (one reduction latency
         // instead of two; t is discarded on a half-step exit)
-        sch.spmv(a, ad, xb, yb, gl, rows, r, t);
+        sch.spmv(a, ad, xb, yb, gl, rows, r, t, dgv, span);
         double red3[3] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r)};
         gsum_n<LANES>(red3);
         const double sn2 = red3[0], tt = red3[1], ts = red3[2];
@@ -246,7 +262,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
     if (ended < 0 && it >= P.maxit) ended = kMaxit;
     if (ended >= 0) {
       // The true residual of the current iterate decides (t is free here).
-      sch.spmv(a, ad, xb, yb, gl, rows, xv, t);
+      sch.spmv(a, ad, xb, yb, gl, rows, xv, t, dgv, span);
 #pragma unroll
       for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
       const double tt2 = gsum<LANES>(ldot<RPL>(t, t));

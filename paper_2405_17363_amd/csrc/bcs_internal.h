@@ -38,9 +38,10 @@ struct JitKernel {
 };
 
 // Compile (or fetch from the cache) a solve kernel -- body "fp64_body" or
-// "mixed_body" -- for `lanes` lanes per cell and slot segment lengths
-// seg[0..rpl).  Returns BCS_OK or an error code with the message in `err`.
-int jit_kernel(const char* body, int adjoint, int lanes, const int* seg, int rpl, int waves_per_eu,
+// "mixed_body" -- for `lanes` lanes per cell, schedule shape `flags`
+// (kSchedSpan / kSchedDiag) and slot segment lengths seg[0..rpl).  Returns
+// BCS_OK or an error code with the message in `err`.
+int jit_kernel(const char* body, int adjoint, int lanes, int flags, const int* seg, int rpl, int waves_per_eu,
                size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
 
 // Cost order of the cells (bcs_order.hip): fills order[0, ncells) with the
@@ -50,7 +51,7 @@ hipError_t launch_cell_order(const double* gamma, int64_t stride, int64_t ncells
                              hipStream_t stream);
 
 // The multi-mechanism kernel for mechanisms with the given layouts, in order.
-int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const int* rpl, size_t lds_bytes,
-                     JitKernel* out, char* err, size_t errlen);
+int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,
+                     size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
 
 }  // namespace bcs

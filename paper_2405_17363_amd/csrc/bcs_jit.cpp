@@ -170,15 +170,15 @@ int load_source(const std::string& source, const char* name, size_t lds_bytes, J
   return BCS_OK;
 }
 
-void sched_type(std::ostringstream& src, int lanes, const int* seg, int rpl) {
-  src << "bcs::dev::StaticSched<" << lanes;
+void sched_type(std::ostringstream& src, int lanes, int flags, const int* seg, int rpl) {
+  src << "bcs::dev::StaticSched<" << lanes << ", " << flags;
   for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
   src << ">";
 }
 
 }  // namespace
 
-int jit_kernel(const char* body, int adjoint, int lanes, const int* seg, int rpl, int waves_per_eu,
+int jit_kernel(const char* body, int adjoint, int lanes, int flags, const int* seg, int rpl, int waves_per_eu,
                size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
   std::ostringstream src;
   src << "// device sources " << kJitSourceHash << "\n"  // no compiler cache may reuse code across header versions
@@ -189,13 +189,14 @@ int jit_kernel(const char* body, int adjoint, int lanes, const int* seg, int rpl
   const bool fp64 = std::string(body) == "fp64_body";
   const char* name = fp64 ? (adjoint ? "bcs_solve_adjoint" : "bcs_solve_fp64") : "bcs_solve_mixed";
   src << ") " << name << "(bcs::KParams P) {\n  bcs::" << body << "<";
-  sched_type(src, lanes, seg, rpl);
+  sched_type(src, lanes, flags, seg, rpl);
   if (fp64) src << ", " << (adjoint ? 1 : 0);
   src << ">(P);\n}\n";
   return load_source(src.str(), name, lds_bytes, out, err, errlen);
 }
 
-int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const int* rpl, size_t lds_bytes,
+int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,
+                     size_t lds_bytes,
                      JitKernel* out, char* err, size_t errlen) {
   std::ostringstream src;
   src << "// device sources " << kJitSourceHash << "\n"
@@ -204,7 +205,7 @@ int jit_multi_kernel(int nmech, const int* lanes, const int* const* seg, const i
       << "  bcs::multi_body<";
   for (int m = 0; m < nmech; ++m) {
     if (m) src << ", ";
-    sched_type(src, lanes[m], seg[m], rpl[m]);
+    sched_type(src, lanes[m], flags[m], seg[m], rpl[m]);
   }
   src << ">(P);\n}\n";
   return load_source(src.str(), "bcs_solve_multi", lds_bytes, out, err, errlen);

@@ -54,10 +54,20 @@ constexpr int kQueueWords = 16;
 constexpr int kOrderBuckets = 128;
 constexpr int kOrderStateWords = 2 * kOrderBuckets;
 
+// Shapes of the specialised kernels' schedules (bits of their FLAGS).
+// kSchedSpan: a lane whose slot-1 row is kRowSpan holds one long row over
+// the steps of slots 0 and 1 together; slot 0 then yields a partial sum and
+// slot 1 the rest, which the SpMV adds into slot 0.  kSchedDiag: the diagonal
+// entries are not in the schedule; the SpMV starts each row's sum with the
+// diagonal term, taken from the row's own operand value in registers.
+constexpr int kSchedSpan = 1;
+constexpr int kSchedDiag = 2;
+constexpr int16_t kRowSpan = -2;
+
 struct DevSchedule {
   const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
   const uint8_t* col;   // [ksteps * lanes] gathered vector index (row of the other operand)
-  const int16_t* row;   // [rpl * lanes] row owned by slot j of lane l, -1 = none
+  const int16_t* row;   // [rpl * lanes] row owned by slot j of lane l, -1 = none, kRowSpan = slot 0's row
   int32_t ksteps;       // steps per lane (sum of slot segment lengths)
   int32_t rpl;          // row slots per lane
   uint64_t flush[2];    // bit s set: a slot's segment ends after step s
