@@ -139,7 +139,8 @@ int bcs_plan_info(const bcs_plan* plan, int32_t* lanes_per_cell, int32_t* rows_p
  *   gamma                 device, FP64: gamma of cell c is gamma[c*gamma_stride]
  *                         (gamma_stride 0 = one shared value); unused for A_DIRECT
  *   b [ncells, n]         device, FP64
- *   rtol > 0, 1 <= maxit <= 1000000
+ *   rtol > 0, 1 <= maxit <= 1000000: the iteration budget of a cell
+ *                         (FP32_REFINE: over all its inner solves)
  *   x [ncells, n]         device, FP64 out: last iterate (also when not converged)
  *   iters [ncells]        device, int32 out: BiCGStab iterations (half-step exit
  *                         counts 1; FP32_REFINE: total inner iterations)

@@ -225,7 +225,10 @@ void oracle_adjoint_batch(int64_t ncells, int n, int nnz, const int* rp, const i
 /* Mixed precision: FP32 inner BiCGStab inside FP64 iterative refinement.
  *   D = diag(A) (FP64); Ahat = A D^-1 (FP64 division, then rounded to float);
  *   x = 0, r = b;
- *   repeat up to max_refine times while ||r||/||b|| > rtol:
+ *   repeat up to max_refine times while ||r||/||b|| > rtol and fewer than
+ *   maxit inner iterations were spent (maxit is the cell's iteration budget
+ *   over all inner solves, as it bounds the FP64 solve's iterations over its
+ *   restarts):
  *     rhat32 = float(r / ||r||);
  *     solve Ahat d = rhat32 in FP32 to inner_rtol (no residual replacement);
  *     x_new = x + ||r|| * D^-1 * d (FP64); r_new = b - A x_new (FP64);
@@ -280,11 +283,11 @@ void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int
         while (1) {
           if (!isfinite(rn)) { st = OR_NONFINITE; break; }
           if (rn / bn <= rtol) { st = OR_CONVERGED; break; }
-          if (nref >= max_refine) { st = OR_MAXIT; break; }
+          if (nref >= max_refine || tot >= maxit) { st = OR_MAXIT; break; }
           for (int i = 0; i < n; ++i) r32[i] = (float)(r[i] / rn);
           double ires;
           int ist;
-          tot += bicgstab_f(n, rp, ci, A32, r32, inner_rtol, maxit, 0, 0, 1, d32, &ires, &ist, w32);
+          tot += bicgstab_f(n, rp, ci, A32, r32, inner_rtol, maxit - tot, 0, 0, 1, d32, &ires, &ist, w32);
           ++nref;
           if (ist == OR_NONFINITE) { st = OR_NONFINITE; break; }
           for (int i = 0; i < n; ++i) xn[i] = xc[i] + rn * ((double)d32[i] / dg[i]);

@@ -5,7 +5,8 @@
 // Per cell (D = diag(A)):
 //   Ahat = A D^-1 is formed in FP64 and held in VGPRs in FP32;
 //   x = 0, r = b (FP64);
-//   repeat while ||r||/||b|| > rtol and fewer than max_refine inner solves:
+//   repeat while ||r||/||b|| > rtol, fewer than max_refine inner solves ran
+//   and fewer than maxit inner iterations (over all inner solves) were spent:
 //     solve Ahat d = float(r / ||r||) by FP32 BiCGStab to inner_rtol (x0 = 0;
 //     an exact breakdown restarts once from the FP32 true residual);
 //     x_new = x + ||r|| D^-1 d (FP64); r_new = b - A x_new (FP64, with A
@@ -175,7 +176,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         finish(kConverged, rn / bn);
         continue;
       }
-      if (nref >= P.max_refine) {
+      if (nref >= P.max_refine || tot >= P.maxit) {
         finish(kMaxit, rn / bn);
         continue;
       }
@@ -251,14 +252,15 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           }
         }
       }
-      if (ended < 0 && it_in >= P.maxit) ended = kMaxit;
+      // maxit bounds the cell's inner iterations over all its refinements
+      if (ended < 0 && tot + it_in >= P.maxit) ended = kMaxit;
       if (ended == kNonfinite) {
         tot += it_in;
         ++nref;
         finish(kNonfinite, __builtin_nan(""));
         continue;
       }
-      if (ended == kBreakdown && restarts_left > 0 && it_in < P.maxit) {
+      if (ended == kBreakdown && restarts_left > 0 && tot + it_in < P.maxit) {
         // restart from the FP32 true residual of the scaled system
         --restarts_left;
         float ad32[RPL];

@@ -336,6 +336,25 @@ def test_multi_rejects_bad_arguments_and_accepts_empty_mechanisms():
     assert torch.equal(outs[0][0], xs) and torch.equal(outs[0][3], sts)
 
 
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+def test_schedule_shapes_against_plain_schedule(lanes, monkeypatch):
+    """The specialised kernels' schedules leave the diagonal out (its term
+    starts each row sum) and let the longest rows span two slots.  Both the
+    shaped and the plain schedule (BCS_SCHED=0) must meet the oracle and LU
+    bar on config 2, and the shaped one must be shorter."""
+    mech, cells = config_inputs(2, ncells=4000)[0]
+    monkeypatch.setenv("BCS_SCHED", "0")
+    plain = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=lanes)
+    monkeypatch.delenv("BCS_SCHED")
+    shaped = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=lanes)
+    assert shaped.info()["steps_per_lane"] < plain.info()["steps_per_lane"]
+    sample = np.random.default_rng(lanes).choice(4000, 60, replace=False)
+    for plan in (plain, shaped):
+        x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+        check_against_oracle(mech, cells, x, it, res, st)
+        check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st, sample)
+
+
 def test_cost_order_gives_index_order_results():
     """Handing cells out sorted by gamma changes only where and when a cell is
     solved: every output is bitwise the index-order output, every cell is
