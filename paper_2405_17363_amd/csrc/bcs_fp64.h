@@ -12,9 +12,8 @@
 //   alpha = rho / sigma;  s = r - alpha v;  stop if ||s|| <= rtol ||b||
 //   t = A M^-1 s;  omega = (t, s) / (t, t);  x += alpha M^-1 p + omega M^-1 s
 //   r = s - omega t;  stop if ||r|| <= rtol ||b||
-// with two all-reductions per iteration: sigma, then (s, s), (t, t), (t, s)
-// and (rhat, t) together, from which ||r||^2 and the next rho follow by
-// exact identities (the same quantities up to rounding); then the true residual ||b - A x|| confirms convergence; a cell whose true
+// (||r||^2 = ||s||^2 - omega (t, s), an identity, so that the last
+// reduction of the iteration carries only (rhat, r)); then the true residual ||b - A x|| confirms convergence; a cell whose true
 // residual misses rtol restarts from it (residual replacement) while
 // iterations remain, and an exact breakdown restarts a bounded number of
 // times.  The adjoint mode runs the same loop on A^T (a transposed schedule
@@ -222,16 +221,12 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
         // t = A s is formed before the half-step test so that ||s||^2,
-        // (t, s), (t, t) and (rhat, t) are reduced together (one reduction
-        // latency instead of two; t is discarded on a half-step exit).  The
-        // iteration's last two inner products then follow without a third
-        // reduction: with r' = s - omega t and omega = (t, s) / (t, t),
-        //   ||r'||^2 = ||s||^2 - omega (t, s),
-        //   (rhat, r') = (rhat, s) - omega (rhat, t) = rho - alpha sigma - omega (rhat, t).
+        // (t, s) and (t, t) are reduced together (one reduction latency
+        // instead of two; t is discarded on a half-step exit)
         sch.spmv(a, ad, xb, yb, gl, rows, r, t, dgv, span);
-        double red4[4] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r), ldot<RPL>(rh, t)};
-        gsum_n<LANES>(red4);
-        const double sn2 = red4[0], tt = red4[1], ts = red4[2], rht = red4[3];
+        double red3[3] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r)};
+        gsum_n<LANES>(red3);
+        const double sn2 = red3[0], tt = red3[1], ts = red3[2];
         if (!finite(sn2)) {
           ended = kNonfinite;
         } else if (sn2 <= tol2) {
@@ -249,10 +244,12 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
             xv[j] = xv[j] + alpha * p[j] + omega * r[j];
             r[j] = r[j] - omega * t[j];
           }
-          // a negative rn2 (cancellation) passes the test below; the true
-          // residual then decides
+          // ||r||^2 of r = s - omega t with omega = (t, s) / (t, t) is
+          // ||s||^2 - omega (t, s): only (rhat, r) needs a reduction.  (A
+          // negative value from cancellation passes the test below; the true
+          // residual then decides.)
           const double rn2 = sn2 - omega * ts;
-          const double rho_next = (rho - alpha * sigma) - omega * rht;
+          const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
           if (!finite(rn2)) {
             ended = kNonfinite;
           } else if (rn2 <= tol2) {
