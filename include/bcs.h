@@ -125,6 +125,34 @@ int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, cons
                       int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
                       int32_t* iters, double* resid, int32_t* status, int32_t* lanes_out);
 
+/* Shapes of the gather schedules of the specialised kernels (bit mask). */
+#define BCS_SCHED_SPAN 1 /* the longest rows may span row slots 0 and 1 of one lane */
+#define BCS_SCHED_DIAG 2 /* diagonal entries left out; the row sum starts from the diagonal term */
+
+/* Describe, on the host (no device needed), the gather schedule the
+ * specialised solve kernels use for a pattern: its rows dealt to row slots of
+ * `lanes` lanes (16, 32 or 64) by decreasing length, each lane's entries step
+ * after step (the sliced-ELL layout of Section 3.1's per-cell SpMV), for A
+ * (transpose = 0) or for A^T as the adjoint solves it (transpose = 1), with
+ * the schedule shapes allowed by `shapes` (BCS_SCHED_* mask; the diagonal is
+ * left out only if every row holds it).  For tests and tuning.
+ *   *steps          gather steps per lane
+ *   *rows_per_lane  row slots per lane, ceil(n / lanes)
+ *   *shape          the BCS_SCHED_* shapes used
+ *   seg [rows_per_lane]             steps of each row slot, in order
+ *   row [rows_per_lane * lanes]     row of slot j on lane l at j * lanes + l;
+ *                                   -1 = none; -2 = slot 1 of a lane whose
+ *                                   slot-0 row continues over slot 1's steps
+ *   pos [steps * lanes]             CSR position (in the pattern as given) of
+ *                                   the value at step s on lane l, at
+ *                                   s * lanes + l; -1 = padding step
+ *   col [steps * lanes]             column (row, for A^T) gathered at that step
+ * Each output may be NULL; the arrays must hold the sizes above (call once
+ * with NULL arrays to learn steps).  Returns BCS_OK or an error code. */
+int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,
+                          int32_t transpose, int32_t shapes, int32_t* steps, int32_t* rows_per_lane,
+                          int32_t* shape, int32_t* seg, int16_t* row, int32_t* pos, uint8_t* col);
+
 /* Describe the plan's launch configuration (for logs and tests):
  * lanes per cell, rows per lane, schedule steps per lane, cells per
  * workgroup.  Any output pointer may be NULL. */

@@ -21,12 +21,15 @@ from ._binding import (  # noqa: F401
     BCS_J_GAMMA,
     BCS_MAXIT,
     BCS_NONFINITE,
+    BCS_SCHED_DIAG,
+    BCS_SCHED_SPAN,
     BcsError,
     BatchedSolve,
     Plan,
     exported_symbols,
     lib,
     library_path,
+    schedule_describe,
     solve_batch,
     solve_batch_adjoint,
     solve_multi,

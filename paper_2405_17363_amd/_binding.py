@@ -18,6 +18,7 @@ BCS_CONVERGED, BCS_MAXIT, BCS_BREAKDOWN, BCS_NONFINITE = 0, 1, 2, 3
 BCS_FP64, BCS_FP32_REFINE = 0, 1
 BCS_PRECOND_NONE, BCS_PRECOND_JACOBI = 0, 1
 BCS_J_GAMMA, BCS_A_DIRECT = 0, 1
+BCS_SCHED_SPAN, BCS_SCHED_DIAG = 1, 2
 
 _PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI}
 _PRECISION = {"fp64": BCS_FP64, "fp32_refine": BCS_FP32_REFINE}
@@ -83,6 +84,8 @@ def lib():
         L.bcs_solve_batch_adjoint.restype = ctypes.c_int
         L.bcs_solve_multi.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, VP]
         L.bcs_solve_multi.restype = ctypes.c_int
+        L.bcs_schedule_describe.argtypes = [I32, I32, P, P, I32, I32, I32, P, P, P, P, P, P, P]
+        L.bcs_schedule_describe.restype = ctypes.c_int
         L.bcs_last_error.argtypes = []
         L.bcs_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -94,6 +97,27 @@ def exported_symbols() -> list:
     with open(_HEADER) as f:
         text = f.read()
     return sorted(set(re.findall(r"\b(bcs_[a-z_]+)\s*\(", text)))
+
+
+def schedule_describe(row_ptr, col_idx, lanes: int, transpose: bool = False,
+                      shapes: int = BCS_SCHED_SPAN | BCS_SCHED_DIAG) -> dict:
+    """The specialised kernels' gather schedule for a pattern (host only; see
+    bcs_schedule_describe in include/bcs.h): steps, rows_per_lane, shape, and
+    the arrays seg [rpl], row [rpl, lanes], pos [steps, lanes], col [steps, lanes]."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n, nnz = rp.size - 1, ci.size
+    v = [ctypes.c_int32() for _ in range(3)]
+    args = (n, nnz, rp.ctypes.data, ci.ctypes.data, int(lanes), int(transpose), int(shapes))
+    _check(lib().bcs_schedule_describe(*args, *[ctypes.byref(x) for x in v], None, None, None, None))
+    steps, rpl, shape = (x.value for x in v)
+    seg = np.zeros(rpl, np.int32)
+    row = np.zeros((rpl, lanes), np.int16)
+    pos = np.zeros((steps, lanes), np.int32)
+    col = np.zeros((steps, lanes), np.uint8)
+    _check(lib().bcs_schedule_describe(*args, None, None, None, seg.ctypes.data, row.ctypes.data, pos.ctypes.data,
+                                       col.ctypes.data))
+    return dict(steps=steps, rows_per_lane=rpl, shape=shape, seg=seg, row=row, pos=pos, col=col)
 
 
 def _check(rc: int) -> None:

@@ -466,6 +466,35 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
 
 }  // namespace
 
+namespace {
+
+// Validate a CSR pattern: row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
+// row_ptr, strictly increasing columns in [0, n) per row, the diagonal in
+// every row if need_diag, and n within the kernels' 256 rows.
+int check_pattern(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, bool need_diag) {
+  if (row_ptr[0] != 0) return fail(BCS_ERR_PATTERN, "row_ptr[0] must be 0");
+  if (row_ptr[n] != nnz) return fail(BCS_ERR_PATTERN, "row_ptr[n] = %d but nnz = %d", row_ptr[n], nnz);
+  std::vector<int> diag(n, -1);
+  for (int i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return fail(BCS_ERR_PATTERN, "row_ptr decreases at row %d", i);
+  for (int i = 0; i < n; ++i) {
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int c = col_idx[k];
+      if (c < 0 || c >= n) return fail(BCS_ERR_PATTERN, "column %d out of range in row %d", c, i);
+      if (k > row_ptr[i] && c <= col_idx[k - 1])
+        return fail(BCS_ERR_PATTERN, "columns of row %d are not strictly increasing", i);
+      if (c == i) diag[i] = k;
+    }
+  }
+  if (need_diag)
+    for (int i = 0; i < n; ++i)
+      if (diag[i] < 0) return fail(BCS_ERR_PATTERN, "row %d has no diagonal entry", i);
+  if (n > 256) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 256 rows per cell", n);
+  return BCS_OK;
+}
+
+}  // namespace
+
 struct bcs_plan {
   int n = 0, nnz = 0;
   int device = 0;
@@ -722,27 +751,10 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   for (int i = 0; i < 4; ++i)
     if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
-  // pattern
-  if (row_ptr[0] != 0) return fail(BCS_ERR_PATTERN, "row_ptr[0] must be 0");
-  if (row_ptr[n] != nnz) return fail(BCS_ERR_PATTERN, "row_ptr[n] = %d but nnz = %d", row_ptr[n], nnz);
-  std::vector<int> diag(n, -1);
-  for (int i = 0; i < n; ++i)
-    if (row_ptr[i + 1] < row_ptr[i]) return fail(BCS_ERR_PATTERN, "row_ptr decreases at row %d", i);
-  for (int i = 0; i < n; ++i) {
-    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-      const int c = col_idx[k];
-      if (c < 0 || c >= n) return fail(BCS_ERR_PATTERN, "column %d out of range in row %d", c, i);
-      if (k > row_ptr[i] && c <= col_idx[k - 1])
-        return fail(BCS_ERR_PATTERN, "columns of row %d are not strictly increasing", i);
-      if (c == i) diag[i] = k;
-    }
-  }
   const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI ||
                          o.precision == BCS_FP32_REFINE;
-  if (need_diag)
-    for (int i = 0; i < n; ++i)
-      if (diag[i] < 0) return fail(BCS_ERR_PATTERN, "row %d has no diagonal entry", i);
-  if (n > 256) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 256 rows per cell", n);
+  const int prc = check_pattern(n, nnz, row_ptr, col_idx, need_diag);
+  if (prc != BCS_OK) return prc;
 
   bcs_plan* p = new bcs_plan();
   p->n = n;
@@ -761,12 +773,13 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
 
   // device tables shared by every kernel of the plan
   std::vector<int16_t> crow(nnz), ccol(nnz);
+  std::vector<int> diag(n, 0);  // an absent diagonal (allowed without Jacobi) is never read: 0 keeps it in bounds
   for (int i = 0; i < n; ++i)
     for (int k = p->rp[i]; k < p->rp[i + 1]; ++k) {
       crow[k] = (int16_t)i;
       ccol[k] = (int16_t)p->ci[k];
+      if (p->ci[k] == i) diag[i] = k;
     }
-  for (int i = 0; i < n; ++i) diag[i] = std::max(diag[i], 0);  // absent diagonal: never read, keep in bounds
   hipError_t e = hipMalloc((void**)&p->diag_pos, sizeof(int32_t) * n);
   if (e == hipSuccess) e = hipMemcpy(p->diag_pos, diag.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&p->coo_row, sizeof(int16_t) * 2 * nnz);
@@ -923,6 +936,41 @@ int bcs_plan_info(const bcs_plan* p, int32_t* lanes, int32_t* rpl, int32_t* step
   if (rpl) *rpl = p->fwd.rpl;
   if (steps) *steps = p->fwd.ksteps;
   if (cells_per_wg) *cells_per_wg = bcs::kWavesPerWg * (64 / p->fwd.lanes);
+  return BCS_OK;
+}
+
+static_assert(BCS_SCHED_SPAN == bcs::kSchedSpan && BCS_SCHED_DIAG == bcs::kSchedDiag, "schedule shape bits");
+
+int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,
+                          int32_t transpose, int32_t shapes, int32_t* steps, int32_t* rows_per_lane, int32_t* shape,
+                          int32_t* seg, int16_t* row, int32_t* pos, uint8_t* col) {
+  g_err.clear();
+  if (n <= 0 || nnz < 1 || !row_ptr || !col_idx) return fail(BCS_ERR_ARG, "bad pattern arguments");
+  if (lanes != 16 && lanes != 32 && lanes != 64) return fail(BCS_ERR_ARG, "lanes must be 16, 32 or 64");
+  if (transpose != 0 && transpose != 1) return fail(BCS_ERR_ARG, "transpose must be 0 or 1");
+  if (shapes < 0 || shapes > (BCS_SCHED_SPAN | BCS_SCHED_DIAG)) return fail(BCS_ERR_ARG, "unknown shapes %d", shapes);
+  const int prc = check_pattern(n, nnz, row_ptr, col_idx, false);
+  if (prc != BCS_OK) return prc;
+  std::vector<int> rp(row_ptr, row_ptr + n + 1), ci(col_idx, col_idx + nnz), pos0(nnz);
+  for (int k = 0; k < nnz; ++k) pos0[k] = k;
+  std::vector<int> trp, tci, tpos;
+  if (transpose) transpose_pattern(n, rp, ci, trp, tci, tpos);
+  const int rpl = (n + lanes - 1) / lanes;
+  const HostSchedule S = transpose ? build_schedule_jit(n, trp, tci, tpos, lanes, rpl, shapes)
+                                   : build_schedule_jit(n, rp, ci, pos0, lanes, rpl, shapes);
+  if (S.ksteps < 0) return fail(BCS_ERR_UNSUPPORTED, "internal error: schedule check failed (lanes = %d)", lanes);
+  if (steps) *steps = S.ksteps;
+  if (rows_per_lane) *rows_per_lane = rpl;
+  if (shape) *shape = S.flags;
+  if (seg)
+    for (int j = 0; j < rpl; ++j) seg[j] = S.seg[j];
+  if (row)
+    for (size_t q = 0; q < S.row.size(); ++q) row[q] = S.row[q];
+  for (size_t q = 0; q < S.ent.size(); ++q) {
+    const bool pad = (S.ent[q] & bcs::kEntPad) != 0;
+    if (pos) pos[q] = pad ? -1 : (S.ent[q] & bcs::kEntPosMask);
+    if (col) col[q] = S.col[q];
+  }
   return BCS_OK;
 }
 
