@@ -412,6 +412,18 @@ __device__ __forceinline__ T ldot(const T (&u)[RPL], const T (&v)[RPL]) {
   return s;
 }
 
+// a / b for finite, nonzero b of normal magnitude (the iteration's scalars,
+// checked before they divide): the hardware reciprocal estimate refined by one
+// Newton step, then one correction of the quotient from its residual
+// a - b q.  Within about an ulp of the rounded quotient, in six dependent
+// operations instead of the scaled IEEE division sequence.
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 

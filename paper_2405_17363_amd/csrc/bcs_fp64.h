@@ -207,7 +207,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
     } else {
       // After a start or restart p = v = 0 and rho_prev = alpha = omega = 1,
       // so this gives p = r on the first iteration without a separate branch.
-      const double beta = (rho * alpha) / (rho_prev * omega);
+      const double beta = qdiv(rho * alpha, rho_prev * omega);
 #pragma unroll
       for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       sch.spmv(a, ad, xb, yb, gl, rows, p, v, dgv, span);
@@ -217,7 +217,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       } else if (sigma == 0.0) {
         ended = kBreakdown;
       } else {
-        alpha = rho / sigma;
+        alpha = qdiv(rho, sigma);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
         // t = A s is formed before the half-step test so that ||s||^2,
@@ -238,7 +238,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         } else if (tt == 0.0) {
           ended = kBreakdown;
         } else {
-          omega = ts / tt;
+          omega = qdiv(ts, tt);
 #pragma unroll
           for (int j = 0; j < RPL; ++j) {
             xv[j] = xv[j] + alpha * p[j] + omega * r[j];
