@@ -10,6 +10,7 @@ Functions (all take/return numpy arrays):
   lu_batch      dense LU with partial pivoting per cell   -> x (ground truth)
   adjoint_batch lambda = A^-T g and dL/dA on the pattern   -> grad_b, grad_A, iters, resid, status
   mixed_batch   FP32 inner BiCGStab + FP64 refinement      -> x, iters, refinements, resid, status
+  solve_groups  Block-cells (N): runs of cells solved as one block-diagonal system -> x, iters, resid, status
   form_a        A = I - gamma*J on the pattern
 """
 from __future__ import annotations
@@ -108,6 +109,60 @@ def solve_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, preco
     _load().oracle_solve_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, float(rtol), int(maxit), int(precond),
                                int(residual_replacement), int(breakdown_restarts), x, iters, resid, status,
                                int(nthreads))
+    return x, iters, resid, status
+
+
+def block_pattern(row_ptr, col_idx, copies):
+    """CSR pattern of the block-diagonal matrix of `copies` matrices with one pattern."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    ci = np.asarray(col_idx, dtype=np.int64)
+    n, nnz = rp.size - 1, ci.size
+    rpg = np.concatenate([rp[:-1] + k * nnz for k in range(copies)] + [[copies * nnz]])
+    cig = np.concatenate([ci + k * n for k in range(copies)])
+    return rpg.astype(np.int32), cig.astype(np.int32)
+
+
+def solve_groups(row_ptr, col_idx, values, gamma, b, group, rtol=1e-10, maxit=200, precond=0, kind=J_GAMMA,
+                 residual_replacement=1, breakdown_restarts=1, nthreads=0):
+    """Block-cells (N), Section 3: each run of `group` consecutive cells (the last run may be shorter) is one
+    system, the block-diagonal matrix of its cells, solved by the same BiCGStab (solve_batch on the assembled
+    system), so the cells of a run share every inner product, scalar and the stopping test.
+
+    Per cell: x; the run's iteration count; the cell's own true relative residual ||b_c - A_c x_c|| / ||b_c||
+    (0 when b_c = 0); status = the run's BREAKDOWN or NONFINITE, else CONVERGED if the cell's own residual is
+    <= rtol, else MAXIT."""
+    rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
+    if group < 1:
+        raise ValueError("group must be >= 1")
+    if kind == J_GAMMA:
+        A = np.stack([form_a(rp, ci, vals[c], g[c * gs]) for c in range(C)]) if C else vals.copy()
+    else:
+        A = vals
+    x = np.zeros((C, n))
+    iters = np.zeros(C, dtype=np.int32)
+    run_status = np.zeros(C, dtype=np.int32)
+    full = C // group
+    for c0, runs, size in ((0, full, group), (full * group, 1 if C % group else 0, C % group)):
+        if runs == 0:
+            continue
+        rpg, cig = block_pattern(rp, ci, size)
+        m = runs * size
+        xg, itg, _, stg = solve_batch(rpg, cig, A[c0:c0 + m].reshape(runs, size * nnz), [0.0],
+                                      bb[c0:c0 + m].reshape(runs, size * n), rtol, maxit, precond, A_DIRECT,
+                                      residual_replacement, breakdown_restarts, nthreads)
+        x[c0:c0 + m] = xg.reshape(m, n)
+        iters[c0:c0 + m] = np.repeat(itg, size)
+        run_status[c0:c0 + m] = np.repeat(stg, size)
+    ax = np.zeros((C, n))
+    for i in range(n):
+        ks = slice(rp[i], rp[i + 1])
+        ax[:, i] = np.sum(A[:, ks] * x[:, ci[ks]], axis=1)
+    bnorm = np.linalg.norm(bb, axis=1)
+    rnorm = np.linalg.norm(bb - ax, axis=1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        resid = np.where(bnorm > 0, rnorm / np.where(bnorm > 0, bnorm, 1.0), 0.0)
+    status = np.where((run_status == 2) | (run_status == 3), run_status,
+                      np.where(resid <= rtol, 0, 1)).astype(np.int32)
     return x, iters, resid, status
 
 

@@ -14,6 +14,7 @@
 * adjoint: LU of A^T, duality g^T x = lambda^T b, central finite differences.
 """
 import numpy as np
+import scipy.linalg
 import pytest
 
 import oracle
@@ -311,6 +312,71 @@ def test_permuting_cells_permutes_results_bitwise():
                            cells["b"][perm], precond=1)
     for u, v in zip(a, b):
         assert np.array_equal(u[perm], v)
+
+
+# ------------------------------------------------------- Block-cells (N) ----
+
+def test_block_pattern_is_the_block_diagonal_matrix():
+    mech, cells = config_inputs(1, ncells=3)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    rpg, cig = oracle.block_pattern(rp, ci, 3)
+    dense = oracle.to_dense(rpg, cig, cells["values"].reshape(-1))
+    want = scipy.linalg.block_diag(*[oracle.to_dense(rp, ci, v) for v in cells["values"]])
+    assert np.array_equal(dense, want)
+
+
+def test_groups_of_one_are_the_per_cell_solves():
+    mech, cells = config_inputs(1, ncells=30)[0]
+    args = (mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"])
+    x, it, res, st = oracle.solve_batch(*args, precond=1)
+    xg, itg, resg, stg = oracle.solve_groups(*args, group=1, precond=1)
+    assert np.array_equal(x, xg) and np.array_equal(it, itg) and np.array_equal(st, stg)
+    # the same residual, summed in another order: equal within its rounding
+    for c in range(30):
+        A = oracle.to_dense(mech.row_ptr, mech.col_idx,
+                            oracle.form_a(mech.row_ptr, mech.col_idx, cells["values"][c], cells["gamma"][c]))
+        slack = 64 * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(x[c])) / np.linalg.norm(cells["b"][c])
+        assert abs(res[c] - resg[c]) <= slack
+
+
+@pytest.mark.parametrize("group", [2, 4])
+def test_identical_cells_in_a_run_iterate_like_one_cell(group):
+    """A run of identical cells has every inner product `group` times the one
+    cell's (up to rounding), so alpha, omega, beta and the iterates are the
+    one cell's: same iteration count (within one) and the same x."""
+    mech, cells = config_inputs(1, ncells=8, mode="ideal")[0]
+    args = (mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"])
+    x, it, res, st = oracle.solve_batch(*args, precond=1)
+    xg, itg, resg, stg = oracle.solve_groups(*args, group=group, precond=1)
+    assert np.all(np.abs(itg - it) <= 1)
+    assert np.all(np.linalg.norm(xg - x, axis=1) <= 1e-8 * np.linalg.norm(x, axis=1))
+
+
+def test_runs_are_independent_and_the_last_run_may_be_short():
+    """Cells 0..5 in runs of 4 are runs {0..3} and {4, 5}: solving {4, 5} alone
+    as one run of 2 gives the same results bitwise."""
+    mech, cells = config_inputs(1, ncells=6)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    full = oracle.solve_groups(rp, ci, cells["values"], cells["gamma"], cells["b"], group=4, precond=1)
+    tail = oracle.solve_groups(rp, ci, cells["values"][4:], cells["gamma"][4:], cells["b"][4:], group=2, precond=1)
+    for u, v in zip(full, tail):
+        assert np.array_equal(u[4:], v)
+
+
+def test_grouped_cells_meet_the_lu_bound():
+    mech, cells = config_inputs(1, ncells=40)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    x, it, res, st = oracle.solve_groups(rp, ci, cells["values"], cells["gamma"], cells["b"], group=4, precond=1)
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    assert np.mean(st == 0) >= 0.9
+    for c in np.nonzero(st == 0)[0]:
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        kappa = np.linalg.cond(A)
+        rlu = np.linalg.norm(cells["b"][c] - A @ xl[c]) / np.linalg.norm(cells["b"][c])
+        assert res[c] <= 1e-10
+        assert np.linalg.norm(x[c] - xl[c]) / np.linalg.norm(xl[c]) <= max(1e-8, 4 * kappa * max(res[c], rlu))
+    # the cells of a run report the run's iteration count
+    assert np.all(it.reshape(10, 4) == it.reshape(10, 4)[:, :1])
 
 
 # ------------------------------------------------------------------ adjoint --
