@@ -201,7 +201,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
-    adjoint = multi = None
+    adjoint = multi = block_cells = None
     if not args.no_forms:
         # adjoint of the same batch: lambda = A^-T g (g ~ N(0,1)), dL/dA on the pattern
         g = torch.as_tensor(np.random.default_rng(7).standard_normal((C, n)), device=dev)
@@ -245,6 +245,37 @@ def main():
                  "ms_one_launch_per_mechanism": round(ems, 4),
                  "lanes_per_cell": [pl.info()["lanes_per_cell"] for pl in mplans]}
         del MV, MG, MB, res_m
+        # Block-cells (N) of Section 3 against Block-cells (1) on the same batch: the cells of a wave
+        # (64 / lanes consecutive cells) solved as one block-diagonal system with shared scalars
+        block_cells = []
+        for L in (32, 16):
+            row = {"lanes_per_cell": L, "cells_per_run": 64 // L}
+            for key, shared in (("bc1", False), ("bcN", True)):
+                bplan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", lanes_per_cell=L,
+                                 shared_scalars=shared, cell_order=not shared)
+                bout = [torch.empty_like(o) for o in out]
+
+                def bstep(bplan=bplan, bout=bout):
+                    bcs.solve_batch(bplan, values, gamma, b, RTOL, MAXIT, out=bout)
+
+                bms = timed(bstep, args.steps)
+                bit, bres, bst = bout[1].cpu().numpy(), bout[2].cpu().numpy(), bout[3].cpu().numpy()
+                bsolved = int(np.sum((bst == 0) & (bres <= RTOL)))
+                G = 64 // L if shared else 1
+                runs = bit[: (C // G) * G].reshape(-1, G)
+                row[key] = {"value": round(bsolved / (bms * 1e-3), 1), "ms_per_step": round(bms, 4),
+                            "solved_fraction": round(bsolved / C, 5),
+                            "iters_mean_per_run": round(float(runs[:, 0].mean()), 2),
+                            "iters_max": int(bit.max()),
+                            "run_iters_over_slowest_cell": None}
+                if shared:
+                    one = row["bc1"]["_iters"][: (C // G) * G].reshape(-1, G).max(axis=1)
+                    row[key]["run_iters_over_slowest_cell"] = round(float(np.mean(runs[:, 0] / one)), 3)
+                else:
+                    row[key]["_iters"] = bit
+                del bplan, bout
+            row["bc1"].pop("_iters")
+            block_cells.append(row)
 
     cpu = None
     if not args.no_cpu:
@@ -298,6 +329,7 @@ def main():
         "fp32_refine": mixed,
         "adjoint": adjoint,
         "multi_mechanism": multi,
+        "block_cells_n": block_cells,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -88,7 +88,20 @@ typedef struct bcs_options {
                                    the large-gamma and the small-gamma end, so that
                                    expensive cells start early.  Results are
                                    identical to index order.  0: index order       */
-  int32_t reserved[4];          /* must be zero                                       */
+  int32_t shared_scalars;       /* 1: Block-cells (N) of Section 3, an experiment
+                                   mode: each run of 64 / lanes_per_cell consecutive
+                                   cells (one wave's cells; the last run may be
+                                   shorter) is solved as one system, the block-
+                                   diagonal matrix of its cells, so the run shares
+                                   every inner product, scalar and stopping test.
+                                   Each cell reports the run's iteration count, its
+                                   own true relative residual, and BCS_CONVERGED
+                                   only if that residual is <= rtol (else
+                                   BCS_MAXIT, or the run's BREAKDOWN / NONFINITE).
+                                   Needs FP64, jit = 1 and lanes_per_cell 16, 32 or
+                                   64 (1 cell per run); forward solves only, cells
+                                   in index order.  0: every cell on its own      */
+  int32_t reserved[3];          /* must be zero                                       */
 } bcs_options;
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
@@ -97,7 +110,7 @@ typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for
 
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
- * max_refine 10, jit 1, autotune 1, cell_order 1. */
+ * max_refine 10, jit 1, autotune 1, cell_order 1, shared_scalars 0. */
 void bcs_options_default(bcs_options* opt);
 
 /* Create a plan for an n x n pattern with nnz entries in CSR form

@@ -44,7 +44,8 @@ class _Options(ctypes.Structure):
         ("jit", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("cell_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("shared_scalars", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -157,7 +158,8 @@ class Plan:
     def __init__(self, row_ptr, col_idx, precond: str = "jacobi", precision: str = "fp64",
                  matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
                  breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10,
-                 jit: bool = True, autotune: bool = True, cell_order: bool = True):
+                 jit: bool = True, autotune: bool = True, cell_order: bool = True,
+                 shared_scalars: bool = False):
         L = lib()
         rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
         ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
@@ -177,6 +179,7 @@ class Plan:
         opt.jit = int(bool(jit))
         opt.autotune = int(bool(autotune))
         opt.cell_order = int(bool(cell_order))
+        opt.shared_scalars = int(bool(shared_scalars))
         self.options = opt
         self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
         h = ctypes.c_void_p()

@@ -394,7 +394,8 @@ bool adjoint_fits(int n, const std::vector<int>& trp, const std::vector<int>& tc
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
-                int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out) {
+                int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out,
+                bool grouped = false) {
   const int rpl = (n + lanes - 1) / lanes;
   Kernel K;
   K.lanes = lanes;
@@ -412,8 +413,8 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, lanes, S.flags, S.seg.data(), rpl,
-                                   waves_per_eu, K.lds, &K.jit, err, sizeof(err));
+    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes, S.flags,
+                                   S.seg.data(), rpl, waves_per_eu, K.lds, &K.jit, err, sizeof(err));
     if (rc != BCS_OK) return fail(rc, "%s", err);
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
@@ -556,13 +557,14 @@ bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values
 }
 
 // Cost order for a solve (kind 0 forward, 1 adjoint): with cell_order on,
-// per-cell gamma and at least two cells, sort the cells by gamma on the
+// cells solved on their own (not shared_scalars), per-cell gamma and at
+// least two cells, sort the cells by gamma on the
 // stream and point the solve at the order.  The order array grows on demand
 // (the only allocation a solve call can make).
 int cell_order(bcs_plan* p, int kind, bcs::KParams* P, hipStream_t stream) {
   P->order = nullptr;
-  if (p->opt.cell_order != 1 || p->opt.matrix_kind != BCS_J_GAMMA || P->gamma_stride == 0 || P->ncells < 2 ||
-      P->ncells > INT32_MAX)
+  if (p->opt.cell_order != 1 || p->opt.shared_scalars == 1 || p->opt.matrix_kind != BCS_J_GAMMA ||
+      P->gamma_stride == 0 || P->ncells < 2 || P->ncells > INT32_MAX)
     return BCS_OK;
   if (!p->order_state[kind]) HIP_TRY(hipMalloc((void**)&p->order_state[kind], bcs::kOrderStateWords * sizeof(uint32_t)));
   if (P->ncells > p->order_cap[kind]) {
@@ -718,6 +720,7 @@ void bcs_options_default(bcs_options* o) {
   o->jit = 1;
   o->autotune = 1;
   o->cell_order = 1;
+  o->shared_scalars = 0;
 }
 
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -748,7 +751,10 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (o.jit != 0 && o.jit != 1) return fail(BCS_ERR_ARG, "jit must be 0 or 1");
   if (o.autotune != 0 && o.autotune != 1) return fail(BCS_ERR_ARG, "autotune must be 0 or 1");
   if (o.cell_order != 0 && o.cell_order != 1) return fail(BCS_ERR_ARG, "cell_order must be 0 or 1");
-  for (int i = 0; i < 4; ++i)
+  if (o.shared_scalars != 0 && o.shared_scalars != 1) return fail(BCS_ERR_ARG, "shared_scalars must be 0 or 1");
+  if (o.shared_scalars == 1 && (o.precision != BCS_FP64 || o.jit != 1 || o.lanes_per_cell == 0))
+    return fail(BCS_ERR_ARG, "shared_scalars needs FP64, jit = 1 and lanes_per_cell 16, 32 or 64");
+  for (int i = 0; i < 3; ++i)
     if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
   const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI ||
@@ -819,7 +825,7 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     if (!adjoint_fits(n, trp, tci, tpos, L)) continue;
     Kernel K;
     g_err.clear();
-    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K);
+    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K, o.shared_scalars == 1);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) {
       rc = r;
@@ -870,6 +876,8 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   g_err.clear();
   if (!p) return fail(BCS_ERR_ARG, "plan is NULL");
   if (ncells <= 0) return fail(BCS_ERR_ARG, "autotune needs ncells > 0");
+  if (p->opt.shared_scalars == 1)
+    return fail(BCS_ERR_UNSUPPORTED, "a shared_scalars plan has a fixed lanes_per_cell; nothing to tune");
   if (!values || !b || !x || !iters || !resid || !status || (p->opt.matrix_kind == BCS_J_GAMMA && !gamma))
     return fail(BCS_ERR_ARG, "values/gamma/b/x/iters/resid/status is NULL");
   if (!(rtol > 0.0) || maxit < 1) return fail(BCS_ERR_ARG, "bad rtol/maxit");
@@ -1019,6 +1027,8 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   g_err.clear();
   int rc = check_common(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   if (rc != BCS_OK) return rc;
+  if (p->opt.shared_scalars == 1)
+    return fail(BCS_ERR_UNSUPPORTED, "the adjoint is not available for shared_scalars plans");
   if (ncells == 0) return BCS_OK;
   if (!x || !g || !grad_b || !grad_A || !iters || !resid || !status)
     return fail(BCS_ERR_ARG, "x/g/grad_b/grad_A/iters/resid/status is NULL");
@@ -1051,8 +1061,9 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     if (rc != BCS_OK) return rc;
     for (int q = 0; q < m; ++q)
       if (plans[q] == p) return fail(BCS_ERR_ARG, "a plan appears twice (mechanisms %d and %d)", q, m);
-    if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var)
-      return fail(BCS_ERR_UNSUPPORTED, "bcs_solve_multi needs FP64 plans created with jit = 1 (mechanism %d)", m);
+    if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var || p->opt.shared_scalars == 1)
+      return fail(BCS_ERR_UNSUPPORTED,
+                  "bcs_solve_multi needs FP64 plans created with jit = 1 and shared_scalars = 0 (mechanism %d)", m);
     if (ncells[m] == 0) continue;
     if (!b[m] || !x[m] || !iters[m] || !resid[m] || !status[m])
       return fail(BCS_ERR_ARG, "b/x/iters/resid/status of mechanism %d is NULL", m);

@@ -91,6 +91,15 @@ __device__ __forceinline__ T gsum(T v) {
   return v;
 }
 
+// The levels of gsum<64> above LANES: from a value summed over each cell's
+// LANES lanes to its sum over the whole wave (bitwise what gsum<64> gives).
+template <int LANES, typename T>
+__device__ __forceinline__ T cross_cells(T v) {
+  if constexpr (LANES <= 16) v = pair_sum<false>(v);
+  if constexpr (LANES <= 32) v = pair_sum<true>(v);
+  return v;
+}
+
 // All-reduce K values at once, level by level: every value goes through
 // exactly the steps of gsum (so each result is bitwise what gsum gives), and
 // the independent butterflies interleave, each one's moves and adds filling

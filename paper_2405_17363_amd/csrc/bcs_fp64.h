@@ -33,12 +33,20 @@ namespace bcs {
 // ADJ: -1 = forward or adjoint chosen by P.adjoint at run time (the
 // precompiled generic kernels), 0 = forward only, 1 = adjoint only (kernels
 // compiled per pattern, which then carry no code for the other mode).
-template <class S, int ADJ = -1>
+// GRP: Block-cells (N) (Section 3): the wave's 64 / LANES cells, consecutive
+// cells claimed together, are one system (the block-diagonal matrix of its
+// cells): every inner product, scalar and stopping test spans the wave.  A
+// slot past the last cell is padding with all-zero data.  Each cell reports
+// the run's iterations, its own true residual and CONVERGED only if that
+// residual is within rtol.
+template <class S, int ADJ = -1, bool GRP = false>
 __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, const int32_t* ent_lds,
                                          const int32_t* diag_lds) {
   using namespace dev;
+  static_assert(!GRP || ADJ == 0, "shared scalars: forward solves only");
   const bool adjoint = ADJ < 0 ? (P.adjoint != 0) : (ADJ == 1);
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
+  constexpr int RL = GRP ? 64 : LANES;  // lanes an inner product spans
   const S sch(P.sched);
   constexpr int NW = S::NW, PACK = S::PACK;
   const int lane = threadIdx.x & 63;
@@ -79,12 +87,18 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   int it = 0, restarts_left = 0;
   bool active = false, dead = false;
   int64_t cell = 0;
+  bool pad = false;  // GRP: a slot past the last cell
+  double bnc = 0;    // GRP: ||b|| of this slot's own cell
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
 
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {
+    if (GRP && pad) {
+      active = false;
+      return;
+    }
     if (P.precond) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) xv[j] = dinv[j] * xv[j];
@@ -124,7 +138,20 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held)) {
+      bool claimed;
+      if constexpr (GRP) {
+        // the wave's run of consecutive cells
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(P.queue, (unsigned long long)(64 / LANES));
+        c = __shfl(c, 0, 64);
+        claimed = c < (unsigned long long)P.ncells;
+        cell = (int64_t)c + grp;
+        pad = cell >= P.ncells;
+        if (pad) cell = 0;  // loads stay in bounds; the data is zeroed below
+      } else {
+        claimed = claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held);
+      }
+      if (!claimed) {
         dead = true;
       } else {
         // Stage the cell: A = I - gamma J (or A) into registers, b, and the
@@ -176,7 +203,19 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           for (int s = 0; s < KMAX; ++s) a[s] *= lds_load<double>(step_addr<PACK>(ado, s));
           wave_sync();
         }
-        const double bn2 = gsum<LANES>(ldot<RPL>(r, r));
+        if constexpr (GRP) {
+          if (pad) {
+#pragma unroll
+            for (int s = 0; s < KMAX; ++s) a[s] = 0;
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) bb[j] = r[j] = dinv[j] = dgv[j] = 0;
+          }
+        }
+        double bn2 = gsum<LANES>(ldot<RPL>(r, r));
+        if constexpr (GRP) {
+          bnc = __builtin_sqrt(bn2);
+          bn2 = cross_cells<LANES>(bn2);
+        }
         bn = __builtin_sqrt(bn2);
         tol2 = (P.rtol * bn) * (P.rtol * bn);
         it = 0;
@@ -211,7 +250,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
       for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       sch.spmv(a, ad, xb, yb, gl, rows, p, v, dgv, span);
-      const double sigma = gsum<LANES>(ldot<RPL>(rh, v));
+      const double sigma = gsum<RL>(ldot<RPL>(rh, v));
       if (!finite(sigma)) {
         ended = kNonfinite;
       } else if (sigma == 0.0) {
@@ -225,7 +264,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         // instead of two; t is discarded on a half-step exit)
         sch.spmv(a, ad, xb, yb, gl, rows, r, t, dgv, span);
         double red3[3] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r)};
-        gsum_n<LANES>(red3);
+        gsum_n<RL>(red3);
         const double sn2 = red3[0], tt = red3[1], ts = red3[2];
         if (!finite(sn2)) {
           ended = kNonfinite;
@@ -249,7 +288,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           // negative value from cancellation passes the test below; the true
           // residual then decides.)
           const double rn2 = sn2 - omega * ts;
-          const double rho_next = gsum<LANES>(ldot<RPL>(rh, r));
+          const double rho_next = gsum<RL>(ldot<RPL>(rh, r));
           if (!finite(rn2)) {
             ended = kNonfinite;
           } else if (rn2 <= tol2) {
@@ -269,12 +308,22 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       sch.spmv(a, ad, xb, yb, gl, rows, xv, t, dgv, span);
 #pragma unroll
       for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
-      const double tt2 = gsum<LANES>(ldot<RPL>(t, t));
+      const double tt2c = gsum<LANES>(ldot<RPL>(t, t));
+      const double tt2 = GRP ? cross_cells<LANES>(tt2c) : tt2c;
       const double res = __builtin_sqrt(tt2) / bn;
+      // GRP: the run's outcome, then each cell's own residual and status
+      auto done = [&](int st) {
+        if constexpr (GRP) {
+          const double own = bnc > 0 ? __builtin_sqrt(tt2c) / bnc : 0.0;
+          finish((st == kBreakdown || st == kNonfinite) ? st : (own <= P.rtol ? kConverged : kMaxit), own);
+        } else {
+          finish(st, res);
+        }
+      };
       if (ended == kNonfinite || !finite(res)) {
-        finish(kNonfinite, res);
+        done(kNonfinite);
       } else if (res <= P.rtol) {
-        finish(kConverged, res);
+        done(kConverged);
       } else if (it < P.maxit && ((ended == kConverged && P.rr) || (ended == kBreakdown && restarts_left > 0))) {
         if (ended == kBreakdown) --restarts_left;
 #pragma unroll
@@ -282,14 +331,14 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         restart();
         rho = tt2;  // (rhat, r) with rhat = r = b - A x
       } else {
-        finish(ended == kBreakdown ? kBreakdown : kMaxit, res);
+        done(ended == kBreakdown ? kBreakdown : kMaxit);
       }
     }
   }
 
 }
 
-template <class S, int ADJ = -1>
+template <class S, int ADJ = -1, bool GRP = false>
 __device__ __forceinline__ void fp64_body(const KParams& P) {
   extern __shared__ double lds[];
   // The schedule's value positions and the rows' diagonal positions, shared
@@ -300,7 +349,7 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  fp64_run<S, ADJ>(P, lds, wv, ent_lds, diag_lds);
+  fp64_run<S, ADJ, GRP>(P, lds, wv, ent_lds, diag_lds);
   dev::queue_wave_done(P.queue, P.total_waves);
 }
 

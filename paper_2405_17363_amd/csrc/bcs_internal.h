@@ -39,10 +39,11 @@ struct JitKernel {
 
 // Compile (or fetch from the cache) a solve kernel -- body "fp64_body" or
 // "mixed_body" -- for `lanes` lanes per cell, schedule shape `flags`
-// (kSchedSpan / kSchedDiag) and slot segment lengths seg[0..rpl).  Returns
+// (kSchedSpan / kSchedDiag) and slot segment lengths seg[0..rpl); grouped:
+// the FP64 forward body with one wave's cells solved as one system.  Returns
 // BCS_OK or an error code with the message in `err`.
-int jit_kernel(const char* body, int adjoint, int lanes, int flags, const int* seg, int rpl, int waves_per_eu,
-               size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
+int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
+               int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
 
 // Cost order of the cells (bcs_order.hip): fills order[0, ncells) with the
 // cell indices sorted by a bucket of gamma[c * stride], largest first, on

@@ -25,7 +25,7 @@ def test_options_struct_layout_and_defaults():
     assert o.precision == bcs.BCS_FP64 and o.precond == 1 and o.matrix_kind == bcs.BCS_J_GAMMA
     assert o.residual_replacement == 1 and o.breakdown_restarts == 1
     assert o.inner_rtol == 1e-4 and o.max_refine == 10
-    assert o.jit == 1 and o.autotune == 1 and o.cell_order == 1
+    assert o.jit == 1 and o.autotune == 1 and o.cell_order == 1 and o.shared_scalars == 0
     assert ctypes.sizeof(_Options) == 64
 
 
@@ -60,7 +60,8 @@ def test_invalid_patterns_are_rejected(rp, ci, what):
 
 @pytest.mark.parametrize("field,value", [("precision", 7), ("precond", 5), ("matrix_kind", 3),
                                           ("lanes_per_cell", 8), ("residual_replacement", 2),
-                                          ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3), ("cell_order", 2)])
+                                          ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3), ("cell_order", 2),
+                                          ("shared_scalars", 2)])
 def test_invalid_options_are_rejected(field, value):
     rc, msg, h = _create([0, 1, 2], [0, 1], **{field: value})
     assert rc == -1, msg
@@ -74,3 +75,10 @@ def test_missing_diagonal_allowed_without_jacobi_in_a_mode():
     assert rc in (0, -4), msg
     if rc == 0:
         bcs.lib().bcs_plan_destroy(h)
+
+
+@pytest.mark.parametrize("extra", [dict(), dict(lanes_per_cell=32, jit=0), dict(lanes_per_cell=32, precision=1)])
+def test_shared_scalars_needs_fixed_lanes_fp64_and_jit(extra):
+    rc, msg, h = _create([0, 1, 2], [0, 1], shared_scalars=1, **extra)
+    assert rc == -1 and "shared_scalars" in msg
+    assert not h.value
