@@ -27,6 +27,7 @@ sys.path.insert(0, HERE)
 METRIC = "cell-systems solved/s at rel. residual 1e-10, 100k cells (FP64 vs FP32+refine)"
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 FP64_VALU_PEAK = 78.6     # MI355X FP64 vector, TFLOP/s
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12  # 128 B per clock per CU, 256 CUs, 2.4 GHz: 78.6 TB/s
 RTOL = 1e-10
 MAXIT = 200
 
@@ -138,6 +139,11 @@ def main():
             traffic = round(tr["hbm_bytes_per_launch"])
 
     fracs = {"hbm": hbm_gbs / HBM_PEAK_GBS, "alu": valu_tfs / FP64_VALU_PEAK}
+    # on-chip operand gathers: every stored entry gathers one FP64 operand per
+    # SpMV (two per iteration, one for staging's column scaling, one for the
+    # true residual)
+    lds_bytes = float(np.sum(iters.astype(np.float64) * 16 * nnz + 16 * nnz))
+    lds_tbs = lds_bytes / avg_launch_s / 1e12
     bound = max(fracs, key=fracs.get)
     roofline = {
         "bound": bound,
@@ -155,6 +161,8 @@ def main():
         "fp64_frac": round(fracs["alu"], 4),
         "algorithmic_bytes_per_launch": bytes_launch,
         "algorithmic_flops_per_launch": flops_launch,
+        "lds_gather_tbs": round(lds_tbs, 2),
+        "lds_gather_frac": round(lds_tbs / LDS_PEAK_TBS, 4),
     }
 
     mixed = None
