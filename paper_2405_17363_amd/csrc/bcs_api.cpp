@@ -221,8 +221,8 @@ HostSchedule build_schedule_jit(int n, const std::vector<int>& rp, const std::ve
         if (e & bcs::kEntPad) continue;
         const int owner = (i == bcs::kRowSpan) ? S.row[l] : i;
         const int k = inv[e & bcs::kEntPosMask];
-        if (owner < 0 || k < rp[owner] || k >= rp[owner + 1] || !kept(k, owner) || S.col[(size_t)st * lanes + l] != ci[k] ||
-            seen[k]++) {
+        if (owner < 0 || k < rp[owner] || k >= rp[owner + 1] || !kept(k, owner) ||
+            S.col[(size_t)st * lanes + l] != ci[k] || seen[k]++) {
           S.ksteps = -1;
           return S;
         }
@@ -566,7 +566,8 @@ int cell_order(bcs_plan* p, int kind, bcs::KParams* P, hipStream_t stream) {
   if (p->opt.cell_order != 1 || p->opt.shared_scalars == 1 || p->opt.matrix_kind != BCS_J_GAMMA ||
       P->gamma_stride == 0 || P->ncells < 2 || P->ncells > INT32_MAX)
     return BCS_OK;
-  if (!p->order_state[kind]) HIP_TRY(hipMalloc((void**)&p->order_state[kind], bcs::kOrderStateWords * sizeof(uint32_t)));
+  if (!p->order_state[kind])
+    HIP_TRY(hipMalloc((void**)&p->order_state[kind], bcs::kOrderStateWords * sizeof(uint32_t)));
   if (P->ncells > p->order_cap[kind]) {
     if (p->order[kind]) HIP_TRY(hipFree(p->order[kind]));
     p->order[kind] = nullptr;

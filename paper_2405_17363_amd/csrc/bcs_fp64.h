@@ -12,13 +12,13 @@
 //   alpha = rho / sigma;  s = r - alpha v;  stop if ||s|| <= rtol ||b||
 //   t = A M^-1 s;  omega = (t, s) / (t, t);  x += alpha M^-1 p + omega M^-1 s
 //   r = s - omega t;  stop if ||r|| <= rtol ||b||
-// (||r||^2 = ||s||^2 - omega (t, s), an identity, so that the last
-// reduction of the iteration carries only (rhat, r)); then the true residual ||b - A x|| confirms convergence; a cell whose true
-// residual misses rtol restarts from it (residual replacement) while
-// iterations remain, and an exact breakdown restarts a bounded number of
-// times.  The adjoint mode runs the same loop on A^T (a transposed schedule
-// over the same per-cell values) with g as right-hand side and then writes
-// dL/dA_ij = -lambda_i x_j.
+// (||r||^2 = ||s||^2 - omega (t, s), an identity, so that the last reduction
+// of the iteration carries only (rhat, r)).  Then the true residual
+// ||b - A x|| confirms convergence; a cell whose true residual misses rtol
+// restarts from it (residual replacement) while iterations remain, and an
+// exact breakdown restarts a bounded number of times.  The adjoint mode runs
+// the same loop on A^T (a transposed schedule over the same per-cell values)
+// with g as right-hand side and then writes dL/dA_ij = -lambda_i x_j.
 #pragma once
 
 #include "bcs_device.h"

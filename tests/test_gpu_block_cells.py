@@ -60,7 +60,8 @@ def test_block_cells_n_matches_the_oracle(lanes, ncells):
     same = it == ito
     far = (reso <= RTOL / 10) | (reso >= 10 * RTOL) | (sto >= 2)
     assert np.mean(st[same & far] == sto[same & far]) >= 0.98
-    assert abs(np.mean(st == 0) - np.mean(sto == 0)) <= 0.03, (np.bincount(st, minlength=4), np.bincount(sto, minlength=4))
+    assert abs(np.mean(st == 0) - np.mean(sto == 0)) <= 0.03, (np.bincount(st, minlength=4),
+                                                              np.bincount(sto, minlength=4))
     first = np.arange(0, ncells, G)
     both = (st[first] == 0) & (sto[first] == 0)
     close = np.abs(it[first] - ito[first]) <= np.maximum(3, 0.15 * ito[first])
