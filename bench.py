@@ -36,7 +36,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # about 20 ms of untimed work: the GPU's clocks ramp up over the first
+    # launches, and shorter warm-ups time the ramp
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ncells", type=int, default=100_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the solve kernels.
 
-    python -m paper_2405_17363_amd.profiling stats  --trace DIR [--kernel NAME]
+    python -m paper_2405_17363_amd.profiling stats  --trace DIR [--kernel NAME] [--last N]
     python -m paper_2405_17363_amd.profiling traffic --fetch DIR --write DIR --ncells C --lanes L --out FILE
 
 The traffic summary is a text file: '#' lines describe how it was made, the
@@ -46,11 +46,20 @@ def _csv(dirname: str, suffix: str):
         return list(csv.DictReader(f))
 
 
-def kernel_stats(trace_dir: str, kernel: str = "bcs_solve_fp64") -> dict:
+def kernel_stats(trace_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0) -> dict:
+    """rocprofv3's statistics for `kernel`; with last > 0 also the mean
+    duration of its last `last` dispatches (the timed ones after a warm-up)."""
     for r in _csv(trace_dir, "kernel_stats.csv"):
         if r["Name"] == kernel:
-            return {"kernel": kernel, "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
-                    "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
+            out = {"kernel": kernel, "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                   "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
+            if last > 0:
+                d = [(int(t["Start_Timestamp"]), int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
+                     for t in _csv(trace_dir, "kernel_trace.csv") if t["Kernel_Name"] == kernel]
+                d = [ns for _, ns in sorted(d)][-last:]
+                out["last"] = len(d)
+                out["last_avg_ns"] = sum(d) / len(d)
+            return out
     raise KeyError(kernel)
 
 
@@ -97,6 +106,7 @@ def main(argv=None) -> int:
     s = sub.add_parser("stats")
     s.add_argument("--trace", required=True)
     s.add_argument("--kernel", default="bcs_solve_fp64")
+    s.add_argument("--last", type=int, default=0, help="also average the last N dispatches")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -107,7 +117,7 @@ def main(argv=None) -> int:
     t.add_argument("--note", action="append", default=[], help="header line for the summary (repeatable)")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        print(json.dumps(kernel_stats(a.trace, a.kernel)))
+        print(json.dumps(kernel_stats(a.trace, a.kernel, a.last)))
         return 0
     res = traffic(a.fetch, a.write, a.kernel)
     res.update({"ncells": a.ncells, "lanes_per_cell": a.lanes})
