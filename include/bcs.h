@@ -159,7 +159,8 @@ int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, cons
  *   pos [steps * lanes]             CSR position (in the pattern as given) of
  *                                   the value at step s on lane l, at
  *                                   s * lanes + l; -1 = padding step
- *   col [steps * lanes]             column (row, for A^T) gathered at that step
+ *   col [steps * lanes]             column (row, for A^T) gathered at that step;
+ *                                   n at a padding step (a zero spare element)
  * Each output may be NULL; the arrays must hold the sizes above (call once
  * with NULL arrays to learn steps).  Returns BCS_OK or an error code. */
 int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,

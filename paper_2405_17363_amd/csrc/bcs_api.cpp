@@ -54,7 +54,8 @@ struct HostSchedule {
 // pos[k]) to `rpl` slots of `lanes` lanes, longest rows first, and list each
 // lane's entries slot after slot.  Slot j spans the same LEN_j steps on every
 // lane, LEN_j = longest row in the slot (at least 1); shorter rows and absent
-// rows are padded with entries of value 0 that gather column 0.  If kmax > 0
+// rows are padded with entries that gather the slot's spare operand element
+// n, which is always 0.  If kmax > 0
 // the last slot is extended so that every lane runs exactly kmax steps (the
 // precompiled variants); kmax = 0 keeps the natural length (specialised
 // kernels).  ksteps > kmax on return means the pattern does not fit.
@@ -89,7 +90,7 @@ HostSchedule build_schedule(int n, const std::vector<int>& rp, const std::vector
   }
   S.seg = len;
   S.ent.assign((size_t)ks * lanes, bcs::kEntPad);
-  S.col.assign((size_t)ks * lanes, 0);
+  S.col.assign((size_t)ks * lanes, (uint8_t)n);  // padding gathers the slot's spare element, always 0
   int s0 = 0;
   for (int j = 0; j < rpl; ++j) {
     for (int l = 0; l < lanes; ++l) {
@@ -182,7 +183,7 @@ HostSchedule build_schedule_jit(int n, const std::vector<int>& rp, const std::ve
   for (int j = 0; j < rpl; ++j)
     for (int l = j < 2 ? nx : 0; l < lanes && q < n; ++l, ++q) S.row[(size_t)j * lanes + l] = (int16_t)order[q];
   S.ent.assign((size_t)ks * lanes, bcs::kEntPad);
-  S.col.assign((size_t)ks * lanes, 0);
+  S.col.assign((size_t)ks * lanes, (uint8_t)n);  // padding gathers the slot's spare element, always 0
   int s0 = 0;
   for (int j = 0; j < rpl; ++j) {
     for (int l = 0; l < lanes; ++l) {
@@ -471,7 +472,8 @@ namespace {
 
 // Validate a CSR pattern: row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
 // row_ptr, strictly increasing columns in [0, n) per row, the diagonal in
-// every row if need_diag, and n within the kernels' 256 rows.
+// every row if need_diag, and n within the kernels' 255 rows (8-bit gather
+// indices, with index n the zero spare element).
 int check_pattern(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, bool need_diag) {
   if (row_ptr[0] != 0) return fail(BCS_ERR_PATTERN, "row_ptr[0] must be 0");
   if (row_ptr[n] != nnz) return fail(BCS_ERR_PATTERN, "row_ptr[n] = %d but nnz = %d", row_ptr[n], nnz);
@@ -490,7 +492,7 @@ int check_pattern(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t*
   if (need_diag)
     for (int i = 0; i < n; ++i)
       if (diag[i] < 0) return fail(BCS_ERR_PATTERN, "row %d has no diagonal entry", i);
-  if (n > 256) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 256 rows per cell", n);
+  if (n > 255) return fail(BCS_ERR_UNSUPPORTED, "n = %d exceeds the supported 255 rows per cell", n);
   return BCS_OK;
 }
 

@@ -62,6 +62,10 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   uint32_t ad[NW];
   build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(xb), gl);
   // Owned rows; a padding row (-1) stages into the spare LDS element n.
+  // Padding rows only ever store 0 there, and padding steps of the schedule
+  // gather it, so it starts at 0 and a padding step adds value * 0.
+  if (gl == 0) xb[n] = 0.0;
+  wave_sync();
   int rows[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
@@ -173,12 +177,19 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           r[j] = bb[j];
           xv[j] = 0;
         }
-        asm volatile("" ::: "memory");  // re-read the flags below instead of keeping them live
+        // A = I - gamma J on the schedule's entries (a padding step keeps the
+        // finite value it loaded: it multiplies the zero spare element)
+        if constexpr ((S::FLAGS & kSchedDiag) != 0) {
+          // no diagonal entries in the schedule
 #pragma unroll
-        for (int s = 0; s < KMAX; ++s) {
-          const int32_t e = ent_lds[s * LANES + gl];
-          const double av = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * a[s]) : a[s];
-          a[s] = (e & kEntPad) ? 0.0 : av;
+          for (int s = 0; s < KMAX; ++s) a[s] = (P.kind == kJGamma) ? -g * a[s] : a[s];
+        } else {
+          asm volatile("" ::: "memory");  // re-read the flags below instead of keeping them live
+#pragma unroll
+          for (int s = 0; s < KMAX; ++s) {
+            const int32_t e = ent_lds[s * LANES + gl];
+            a[s] = (P.kind == kJGamma) ? (((e & kEntDiag) ? 1.0 : 0.0) - g * a[s]) : a[s];
+          }
         }
         if constexpr ((S::FLAGS & kSchedDiag) != 0) {
 #pragma unroll

@@ -38,6 +38,8 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 
   uint32_t ad[NW];
   build_addr<PACK, KMAX, LANES>(ad, P.sched.col, lds_addr(xb), gl);
+  if (gl == 0) xb[n] = 0.0;  // the spare element padding steps gather
+  wave_sync();
   int rows[RPL];
 #pragma unroll
   for (int j = 0; j < RPL; ++j) {
