@@ -82,3 +82,12 @@ def test_shared_scalars_needs_fixed_lanes_fp64_and_jit(extra):
     rc, msg, h = _create([0, 1, 2], [0, 1], shared_scalars=1, **extra)
     assert rc == -1 and "shared_scalars" in msg
     assert not h.value
+
+
+def test_more_than_255_rows_is_unsupported():
+    n = 256
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    rc, msg, h = _create(rp, ci)
+    assert rc == -3 and "255" in msg
+    assert not h.value

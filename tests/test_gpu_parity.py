@@ -267,6 +267,30 @@ def test_exact_breakdown_and_singular_cells():
     assert st[0] == bcs.BCS_NONFINITE
 
 
+def test_largest_supported_n():
+    """n = 255, the largest cell (8-bit gather indices; index 255 is the zero
+    spare element): only 64 lanes per cell fit its registers."""
+    mech = gen_mechanism(255, 510)
+    cells = gen_cells(mech, 300, seed=255, h_max=10.0)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    assert plan.info()["lanes_per_cell"] == 64
+    x, it, res, st = run(plan, cells["values"], cells["gamma"], cells["b"])
+    check_against_oracle(mech, cells, x, it, res, st, min_status_agree=0.98)
+    sample = np.random.default_rng(3).choice(300, 30, replace=False)
+    check_against_lu(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"], x, res, st, sample)
+
+
+def test_pattern_no_layout_holds_is_rejected():
+    """A dense 200-entry row needs more schedule steps than any lane count's
+    registers hold: plan creation fails with an error, nothing is launched."""
+    n = 200
+    rows = [list(range(n))] + [[i] for i in range(1, n)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.concatenate(rows).astype(np.int32)
+    with pytest.raises(bcs.BcsError, match="no kernel layout"):
+        bcs.Plan(rp, ci)
+
+
 def test_zero_cells_is_a_noop():
     mech = gen_mechanism(30, 50)
     plan = bcs.Plan(mech.row_ptr, mech.col_idx)
