@@ -374,10 +374,9 @@ void transpose_pattern(int n, const std::vector<int>& rp, const std::vector<int>
     }
 }
 
-// Schedule shapes the specialised FP64 kernels may use (the mixed form's
-// kernels take plain schedules).  BCS_SCHED overrides the mask (tuning).
-int sched_allowed(bool mixed) {
-  if (mixed) return 0;
+// Schedule shapes the specialised kernels may use.  BCS_SCHED overrides the
+// mask (tuning).
+int sched_allowed(bool /*mixed*/) {
   if (const char* e = std::getenv("BCS_SCHED")) return std::atoi(e) & (bcs::kSchedDiag | bcs::kSchedSpan);
   return bcs::kSchedDiag | bcs::kSchedSpan;
 }

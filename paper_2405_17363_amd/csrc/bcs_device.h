@@ -433,6 +433,14 @@ __device__ __forceinline__ double qdiv(double a, double b) {
   return __builtin_fma(__builtin_fma(-b, q, a), r, q);
 }
 
+// The same in FP32 (the mixed form's inner solve): the FP32 reciprocal is
+// accurate to about an ulp, so one quotient correction suffices.
+__device__ __forceinline__ float qdiv(float a, float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  const float q = a * r;
+  return __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 

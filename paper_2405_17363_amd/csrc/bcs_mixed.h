@@ -56,6 +56,15 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   float a32[KMAX];                      // Ahat = A D^-1 rounded to FP32
   double x64[RPL], r64[RPL], dg[RPL];   // FP64 iterate, residual, diag(A)
   float d[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];  // FP32 inner state
+  // Schedules without diagonal entries: the diagonal of Ahat in FP32 (that of
+  // A, for the FP64 residual, is dg); 0 for padding rows.
+  float dg32[RPL];
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) dg32[j] = 0.f;
+  // 1 on a lane whose slots 0 and 1 hold one long row
+  double span64 = 0;
+  if constexpr (S::FLAGS & kSchedSpan) span64 = (P.sched.row[LANES + gl] == kRowSpan) ? 1.0 : 0.0;
+  const float span32 = (float)span64;
   double bn = 0, rn = 0, g = 0;
   float itol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
   int it_in = 0, tot = 0, nref = 0, restarts_left = 0;
@@ -92,7 +101,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
       av[s] = (e & kEntPad) ? 0.0 : a;
     }
     double ax[RPL];
-    sch.spmv(av, ad, xb, yb, gl, rows, xin, ax);
+    sch.spmv(av, ad, xb, yb, gl, rows, xin, ax, dg, span64);
     const double* bc = P.b + cell * n;
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
@@ -139,7 +148,9 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           dg[j] = (P.kind == kJGamma) ? 1.0 - g * dvj : dvj;
           r64[j] = real ? bj : 0.0;
           x64[j] = 0.0;
-          xb[rows[j]] = real ? 1.0 / dg[j] : 0.0;  // D^-1 for the column scaling
+          const double dinv = real ? 1.0 / dg[j] : 0.0;
+          xb[rows[j]] = dinv;  // D^-1 for the column scaling
+          dg32[j] = (float)(dg[j] * dinv);
         }
         wave_sync();
         uint32_t ado[NW];
@@ -200,18 +211,18 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           for (int j = 0; j < RPL; ++j) p[j] = r[j];
           first = false;
         } else {
-          const float beta = (rho * alpha) / (rho_prev * omega);
+          const float beta = qdiv(rho * alpha, rho_prev * omega);
 #pragma unroll
           for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
         }
-        sch.spmv(a32, ad, xb, yb, gl, rows, p, v);
+        sch.spmv(a32, ad, xb, yb, gl, rows, p, v, dg32, span32);
         const float sigma = gsum<LANES>(ldot<RPL>(rh, v));
         if (!finite(sigma)) {
           ended = kNonfinite;
         } else if (sigma == 0.f) {
           ended = kBreakdown;
         } else {
-          alpha = rho / sigma;
+          alpha = qdiv(rho, sigma);
 #pragma unroll
           for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];
           const float sn2 = gsum<LANES>(ldot<RPL>(r, r));
@@ -222,7 +233,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
             for (int j = 0; j < RPL; ++j) d[j] = d[j] + alpha * p[j];
             ended = kConverged;
           } else {
-            sch.spmv(a32, ad, xb, yb, gl, rows, r, t);
+            sch.spmv(a32, ad, xb, yb, gl, rows, r, t, dg32, span32);
             float red2[2] = {ldot<RPL>(t, t), ldot<RPL>(t, r)};
             gsum_n<LANES>(red2);
             const float tt = red2[0], ts = red2[1];
@@ -231,15 +242,15 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
             } else if (tt == 0.f) {
               ended = kBreakdown;
             } else {
-              omega = ts / tt;
+              omega = qdiv(ts, tt);
 #pragma unroll
               for (int j = 0; j < RPL; ++j) {
                 d[j] = d[j] + alpha * p[j] + omega * r[j];
                 r[j] = r[j] - omega * t[j];
               }
-              float red2b[2] = {ldot<RPL>(r, r), ldot<RPL>(rh, r)};
-              gsum_n<LANES>(red2b);
-              const float rn2 = red2b[0], rho_next = red2b[1];
+              // ||r||^2 = ||s||^2 - omega (t, s) for r = s - omega t
+              const float rn2 = sn2 - omega * ts;
+              const float rho_next = gsum<LANES>(ldot<RPL>(rh, r));
               if (!finite(rn2)) {
                 ended = kNonfinite;
               } else if (rn2 <= itol2) {
@@ -266,7 +277,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         // restart from the FP32 true residual of the scaled system
         --restarts_left;
         float ad32[RPL];
-        sch.spmv(a32, ad, xb, yb, gl, rows, d, ad32);
+        sch.spmv(a32, ad, xb, yb, gl, rows, d, ad32, dg32, span32);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           r[j] = (float)(r64[j] / rn) - ad32[j];
