@@ -254,6 +254,8 @@ def main():
         MV = [torch.as_tensor(c["values"], device=dev) for _, c in mechs]
         MG = [torch.as_tensor(c["gamma"], device=dev) for _, c in mechs]
         MB = [torch.as_tensor(c["b"], device=dev) for _, c in mechs]
+        for pl, v, gg, bb in zip(mplans, MV, MG, MB):
+            pl.autotune(v, gg, bb, RTOL, MAXIT)  # each mechanism's layout tuned on its own cells
         res_m = {}
 
         def mstep_multi():
