@@ -222,6 +222,22 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
                     const double* const* b, double rtol, int32_t maxit, double* const* x,
                     int32_t* const* iters, double* const* resid, int32_t* const* status, void* stream);
 
+/* Autotuner of the one-launch form: choose every plan's lanes per cell for
+ * the combined launch by timing bcs_solve_multi on the caller's batches
+ * (coordinate descent: each mechanism in turn tries 16, 32 and 64 lanes with
+ * the others held, for up to two passes; plans created with a fixed
+ * lanes_per_cell keep it).  The choice is kept in the plans (adjoint kernels
+ * included).  The combined kernel runs at the occupancy of its most
+ * register-hungry mechanism, so the best lanes for it can differ from each
+ * plan's best alone.  Arguments as in bcs_solve_multi, on the null stream;
+ * the outputs serve as scratch and hold one solve's results afterwards;
+ * synchronises the device; lanes_out (may be NULL) receives nmech lane
+ * counts.  Not to be called while solves with the plans run. */
+int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* ncells, const double* const* values,
+                       const double* const* gamma, const int64_t* gamma_stride, const double* const* b,
+                       double rtol, int32_t maxit, double* const* x, int32_t* const* iters, double* const* resid,
+                       int32_t* const* status, int32_t* lanes_out);
+
 /* Description of the last error on this thread ("" if none). */
 const char* bcs_last_error(void);
 

@@ -29,6 +29,7 @@ from ._binding import (  # noqa: F401
     exported_symbols,
     lib,
     library_path,
+    multi_autotune,
     schedule_describe,
     solve_batch,
     solve_batch_adjoint,

@@ -85,6 +85,8 @@ def lib():
         L.bcs_solve_batch_adjoint.restype = ctypes.c_int
         L.bcs_solve_multi.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, VP]
         L.bcs_solve_multi.restype = ctypes.c_int
+        L.bcs_multi_autotune.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, P]
+        L.bcs_multi_autotune.restype = ctypes.c_int
         L.bcs_schedule_describe.argtypes = [I32, I32, P, P, I32, I32, I32, P, P, P, P, P, P, P]
         L.bcs_schedule_describe.restype = ctypes.c_int
         L.bcs_last_error.argtypes = []
@@ -282,21 +284,22 @@ def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, ma
     return grad_b, grad_A, iters, resid, status
 
 
-def solve_multi(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence, rtol: float = 1e-10,
-                maxit: int = 200):
-    """One persistent launch over several mechanisms; per mechanism (x, iters, resid, status)."""
+def _multi_args(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence):
+    """Pointer arrays of the one-launch form and the output tensors they point to."""
     torch = _torch()
     m = len(plans)
     outs = []
     arrs = {k: (ctypes.c_void_p * m)() for k in ("plans", "values", "gamma", "b", "x", "iters", "resid", "status")}
     nc = (ctypes.c_int64 * m)()
     gst = (ctypes.c_int64 * m)()
+    keep = []
     for i, (pl, v, g, b) in enumerate(zip(plans, values, gammas, bs)):
         _dev(v, torch.float64, "values")
         C = v.shape[0]
         _dev(v, torch.float64, "values", (C, pl.nnz))
         _dev(b, torch.float64, "b", (C, pl.n))
         gg, gs = _gamma_arg(g, C, v.device)
+        keep.append(gg)
         x = torch.empty((C, pl.n), dtype=torch.float64, device=v.device)
         it = torch.empty(C, dtype=torch.int32, device=v.device)
         rs = torch.empty(C, dtype=torch.float64, device=v.device)
@@ -308,12 +311,33 @@ def solve_multi(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: S
                      ("status", st)):
             arrs[k][i] = t.data_ptr()
         arrs["plans"][i] = pl.handle.value
-    keep = (values, gammas, bs)  # noqa: F841  (tensors stay alive across the call)
+    return m, arrs, nc, gst, outs, keep
+
+
+def solve_multi(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence, rtol: float = 1e-10,
+                maxit: int = 200):
+    """One persistent launch over several mechanisms; per mechanism (x, iters, resid, status)."""
+    m, arrs, nc, gst, outs, keep = _multi_args(plans, values, gammas, bs)  # keep: tensors alive across the call
     rc = lib().bcs_solve_multi(m, arrs["plans"], nc, arrs["values"], arrs["gamma"], gst, arrs["b"], float(rtol),
                                int(maxit), arrs["x"], arrs["iters"], arrs["resid"], arrs["status"],
                                _stream_handle())
     _check(rc)
     return outs
+
+
+def multi_autotune(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence, rtol: float = 1e-10,
+                   maxit: int = 200) -> list:
+    """Choose every plan's lanes per cell for the one-launch form by timing it on these batches.
+
+    The choice stays in the plans (their adjoint kernels follow it); returns the lane counts.
+    Synchronises the device.
+    """
+    m, arrs, nc, gst, outs, keep = _multi_args(plans, values, gammas, bs)  # keep: tensors alive across the call
+    lanes = (ctypes.c_int32 * m)()
+    _check(lib().bcs_multi_autotune(m, arrs["plans"], nc, arrs["values"], arrs["gamma"], gst, arrs["b"],
+                                    float(rtol), int(maxit), arrs["x"], arrs["iters"], arrs["resid"],
+                                    arrs["status"], lanes))
+    return list(lanes)
 
 
 class BatchedSolve:

@@ -1155,4 +1155,105 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
   return BCS_OK;
 }
 
+
+int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* ncells, const double* const* values,
+                       const double* const* gamma, const int64_t* gamma_stride, const double* const* b,
+                       double rtol, int32_t maxit, double* const* x, int32_t* const* iters, double* const* resid,
+                       int32_t* const* status, int32_t* lanes_out) {
+  g_err.clear();
+  if (nmech < 1 || nmech > bcs::kMaxMech || !plans) return fail(BCS_ERR_ARG, "nmech must be in [1, %d]", bcs::kMaxMech);
+  for (int m = 0; m < nmech; ++m)
+    if (!plans[m]) return fail(BCS_ERR_ARG, "plan %d is NULL", m);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(BCS_ERR_HIP, "device synchronisation failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(BCS_ERR_HIP, "multi autotune: event creation failed");
+  }
+  const bcs_plan* const* cplans = plans;
+  // one combined launch as the plans stand: a warm-up (which also compiles the
+  // combination), then the best of two timed launches
+  auto time_multi = [&](double* secs) -> int {
+    int rc = bcs_solve_multi(nmech, cplans, ncells, values, gamma, gamma_stride, b, rtol, maxit, x, iters, resid,
+                             status, nullptr);
+    if (rc != BCS_OK) return rc;
+    double best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, nullptr);
+      rc = bcs_solve_multi(nmech, cplans, ncells, values, gamma, gamma_stride, b, rtol, maxit, x, iters, resid,
+                           status, nullptr);
+      if (rc != BCS_OK) return rc;
+      (void)hipEventRecord(e1, nullptr);
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(BCS_ERR_HIP, "multi autotune: synchronisation failed");
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, (double)ms * 1e-3);
+    }
+    *secs = best;
+    return BCS_OK;
+  };
+  double best = 0;
+  int rc = time_multi(&best);
+  // coordinate descent: each mechanism in turn tries the other lane counts
+  // with the others held, keeping any that shortens the combined launch
+  for (int pass = 0; rc == BCS_OK && pass < 2; ++pass) {
+    bool improved = false;
+    for (int m = 0; rc == BCS_OK && m < nmech; ++m) {
+      bcs_plan* p = plans[m];
+      if (p->opt.lanes_per_cell != 0) continue;  // fixed by the caller
+      std::vector<int> pos(p->nnz), trp, tci, tpos;
+      for (int k = 0; k < p->nnz; ++k) pos[k] = k;
+      transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);
+      for (int L : {16, 32, 64}) {
+        if (L == p->fwd.lanes || !adjoint_fits(p->n, trp, tci, tpos, L)) continue;
+        Kernel K;
+        g_err.clear();
+        int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, p->opt.jit == 1, 0, false, &K);
+        if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
+        if (r != BCS_OK) {
+          rc = r;
+          break;
+        }
+        Kernel keep = p->fwd;
+        p->fwd = K;
+        double t = 0;
+        r = time_multi(&t);
+        if (verbose()) std::fprintf(stderr, "[bcs] multi autotune mechanism %d lanes=%d: %.1f us\n", m, L, t * 1e6);
+        if (r == BCS_OK && t < best) {
+          best = t;
+          free_kernel(&keep);
+          improved = true;
+        } else {
+          p->fwd = keep;
+          free_kernel(&K);
+          if (r != BCS_OK) {
+            rc = r;
+            break;
+          }
+        }
+      }
+    }
+    if (!improved) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BCS_OK) return rc;
+  // the adjoint kernels follow the chosen lane counts
+  for (int m = 0; m < nmech; ++m) {
+    bcs_plan* p = plans[m];
+    if (p->adj.lanes != p->fwd.lanes) {
+      std::vector<int> trp, tci, tpos;
+      transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);
+      Kernel A;
+      g_err.clear();
+      rc = make_kernel(p->n, trp, tci, tpos, p->fwd.lanes, 1, p->opt.jit == 1, 0, false, &A);
+      if (rc != BCS_OK) return g_err.empty() ? fail(rc, "no kernel layout holds the transposed pattern") : rc;
+      free_kernel(&p->adj);
+      p->adj = A;
+    }
+    if (lanes_out) lanes_out[m] = p->fwd.lanes;
+  }
+  return BCS_OK;
+}
+
 }  // extern "C"

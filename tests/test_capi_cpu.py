@@ -13,7 +13,8 @@ def test_library_exports_every_declared_symbol():
     L = bcs.lib()
     names = bcs.exported_symbols()
     assert {"bcs_plan_create", "bcs_solve_batch", "bcs_solve_batch_adjoint", "bcs_solve_multi",
-            "bcs_last_error", "bcs_plan_destroy", "bcs_options_default", "bcs_plan_info"} <= set(names)
+            "bcs_multi_autotune", "bcs_last_error", "bcs_plan_destroy", "bcs_options_default",
+            "bcs_plan_info"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -91,3 +92,24 @@ def test_more_than_255_rows_is_unsupported():
     rc, msg, h = _create(rp, ci)
     assert rc == -3 and "255" in msg
     assert not h.value
+
+
+@pytest.mark.parametrize("nmech,null_plan", [(0, False), (9, False), (2, True)])
+def test_multi_entry_points_reject_bad_counts_and_null_plans(nmech, null_plan):
+    # both entry points check the mechanism count (1..8) and, for the autotuner,
+    # NULL plans before any device call
+    L = bcs.lib()
+    m = max(nmech, 1)
+    plans = (ctypes.c_void_p * m)()  # all NULL
+    arrs = [(ctypes.c_void_p * m)() for _ in range(8)]
+    nc = (ctypes.c_int64 * m)()
+    gst = (ctypes.c_int64 * m)()
+    rc = L.bcs_multi_autotune(nmech, plans, nc, arrs[0], arrs[1], gst, arrs[2], 1e-10, 200, arrs[3], arrs[4],
+                              arrs[5], arrs[6], None)
+    assert rc == -1, L.bcs_last_error().decode()
+    msg = L.bcs_last_error().decode()
+    assert ("NULL" in msg) if null_plan else ("nmech" in msg)
+    if not null_plan:
+        rc = L.bcs_solve_multi(nmech, plans, nc, arrs[0], arrs[1], gst, arrs[2], 1e-10, 200, arrs[3], arrs[4],
+                               arrs[5], arrs[6], None)
+        assert rc == -1 and "nmech" in L.bcs_last_error().decode()

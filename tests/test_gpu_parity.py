@@ -360,6 +360,34 @@ def test_multi_rejects_bad_arguments_and_accepts_empty_mechanisms():
     assert torch.equal(outs[0][0], xs) and torch.equal(outs[0][3], sts)
 
 
+def test_multi_autotune_keeps_results_and_fixed_lanes():
+    """The one-launch autotuner only changes lane counts: afterwards each
+    mechanism's part of the combined launch still equals its own launch with
+    the chosen kernel, the adjoint kernels follow the choice, and a plan whose
+    lanes the caller fixed keeps them."""
+    mechs = config_inputs(4, ncells=6000)
+    m0 = mechs[0][0]  # n = 30, fixed at 32 lanes per cell
+    plans = [bcs.Plan(m0.row_ptr, m0.col_idx, lanes_per_cell=32)]
+    plans += [bcs.Plan(m.row_ptr, m.col_idx) for m, _ in mechs[1:]]
+    V = [gpu(c["values"]) for _, c in mechs]
+    Gm = [gpu(c["gamma"]) for _, c in mechs]
+    Bv = [gpu(c["b"]) for _, c in mechs]
+    lanes = bcs.multi_autotune(plans, V, Gm, Bv, RTOL, 200)
+    assert len(lanes) == len(plans) and all(L in (16, 32, 64) for L in lanes) and lanes[0] == 32
+    assert [p.info()["lanes_per_cell"] for p in plans] == lanes
+    outs = bcs.solve_multi(plans, V, Gm, Bv, RTOL, 200)
+    torch.cuda.synchronize()
+    for (mech, cells), plan, (x, it, res, st), v, g, b in zip(mechs, plans, outs, V, Gm, Bv):
+        xs, its, ress, sts, _ = bcs.solve_batch(plan, v, g, b, RTOL, 200)
+        torch.cuda.synchronize()
+        assert torch.equal(x, xs) and torch.equal(it, its) and torch.equal(res, ress) and torch.equal(st, sts)
+        check_against_oracle(mech, cells, *(t.cpu().numpy() for t in (x, it, res, st)), min_status_agree=0.98)
+        gb = torch.ones_like(b)
+        ast = bcs.solve_batch_adjoint(plan, v, g, xs, gb, RTOL, 200)[4]
+        torch.cuda.synchronize()
+        assert float((ast == 0).double().mean()) > 0.95
+
+
 @pytest.mark.parametrize("lanes", [16, 32, 64])
 def test_schedule_shapes_against_plain_schedule(lanes, monkeypatch):
     """The specialised kernels' schedules leave the diagonal out (its term
