@@ -106,7 +106,9 @@ typedef struct bcs_options {
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
                                      work-queue counters and cell-order scratch
-                                     (see the note above) */
+                                     (see the note above) and the kernels that
+                                     bcs_plan_autotune / bcs_multi_autotune
+                                     choose */
 
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
