@@ -1200,7 +1200,7 @@ int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* nce
     bool improved = false;
     for (int m = 0; rc == BCS_OK && m < nmech; ++m) {
       bcs_plan* p = plans[m];
-      if (p->opt.lanes_per_cell != 0) continue;  // fixed by the caller
+      if (p->opt.lanes_per_cell != 0 || ncells[m] == 0) continue;  // fixed by the caller, or nothing to time
       std::vector<int> pos(p->nnz), trp, tci, tpos;
       for (int k = 0; k < p->nnz; ++k) pos[k] = k;
       transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);

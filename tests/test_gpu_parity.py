@@ -358,6 +358,12 @@ def test_multi_rejects_bad_arguments_and_accepts_empty_mechanisms():
     xs, its, ress, sts, _ = bcs.solve_batch(plans[0], V[0], Gm[0], Bv[0])
     torch.cuda.synchronize()
     assert torch.equal(outs[0][0], xs) and torch.equal(outs[0][3], sts)
+    # the one-launch autotuner leaves a mechanism without cells as it is
+    before = plans[1].info()["lanes_per_cell"]
+    lanes = bcs.multi_autotune([plans[0], plans[1]], [V[0], empty[0]], [Gm[0], empty[1]], [Bv[0], empty[2]])
+    assert lanes[1] == before and lanes[0] in (16, 32, 64)
+    with pytest.raises(bcs.BcsError):
+        bcs.multi_autotune([plans[0], plans[0]], V[:1] * 2, Gm[:1] * 2, Bv[:1] * 2)
 
 
 def test_multi_autotune_keeps_results_and_fixed_lanes():
