@@ -171,18 +171,22 @@ def main():
     # residual of their dense-LU solution (numpy, FP64) exceeds rtol / 2, so
     # no FP64 method can report them within rtol ("floor-limited"; they are
     # never counted as solved).
-    unsolved = np.nonzero(~((status == 0) & (resid <= RTOL)))[0]
-    floor_limited = 0
-    if unsolved.size:
-        rp, ci = mech.row_ptr, mech.col_idx
-        rows = np.repeat(np.arange(n), np.diff(rp))
-        for c in unsolved:
+    lu_rows = np.repeat(np.arange(n), np.diff(mech.row_ptr))
+
+    def floor_limited_count(unsolved_cells, rhs, transpose=False):
+        count = 0
+        for c in unsolved_cells:
             A = np.zeros((n, n))
-            A[rows, ci] = -cells["gamma"][c] * cells["values"][c]
+            A[lu_rows, mech.col_idx] = -cells["gamma"][c] * cells["values"][c]
             A[np.arange(n), np.arange(n)] += 1.0
-            xl = np.linalg.solve(A, cells["b"][c])
-            rho = np.linalg.norm(cells["b"][c] - A @ xl) / np.linalg.norm(cells["b"][c])
-            floor_limited += int(rho > RTOL / 2)
+            if transpose:
+                A = A.T.copy()
+            xl = np.linalg.solve(A, rhs[c])
+            rho = np.linalg.norm(rhs[c] - A @ xl) / np.linalg.norm(rhs[c])
+            count += int(rho > RTOL / 2)
+        return count
+
+    floor_limited = floor_limited_count(np.nonzero(~((status == 0) & (resid <= RTOL)))[0], cells["b"])
 
     mixed = None
     if not args.no_mixed:
@@ -211,6 +215,8 @@ def main():
             mixed = {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4),
                      "solved_fraction": round(msolved / C, 5), "iters_mean": round(float(mit.mean()), 2),
                      "refinements_mean": round(float(mref.mean()), 3),
+                     "unsolved_floor_limited": floor_limited_count(
+                         np.nonzero(~((mst == 0) & (mres <= RTOL)))[0], cells["b"]),
                      "rel_diff_vs_fp64_max": float(err.max()) if err.size else None,
                      "rel_diff_vs_fp64_p99": float(np.percentile(err, 99)) if err.size else None}
         except bcs.BcsError as e:
@@ -231,7 +237,8 @@ def main():
     adjoint = multi = block_cells = None
     if not args.no_forms:
         # adjoint of the same batch: lambda = A^-T g (g ~ N(0,1)), dL/dA on the pattern
-        g = torch.as_tensor(np.random.default_rng(7).standard_normal((C, n)), device=dev)
+        g_host = np.random.default_rng(7).standard_normal((C, n))
+        g = torch.as_tensor(g_host, device=dev)
         xf = out[0].clone()
         res_adj = {}
 
@@ -245,6 +252,8 @@ def main():
         adjoint = {"value": round(asolved / (ams * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(ams, 4),
                    "solved_fraction": round(asolved / C, 5),
                    "iters_mean": round(float(res_adj["r"][2].float().mean().item()), 2),
+                   "unsolved_floor_limited": floor_limited_count(np.nonzero(~((ast == 0) & (ares <= RTOL)))[0],
+                                                                 g_host, transpose=True),
                    "algorithmic_bytes_per_cell": 16 * nnz + 24 * n + 32}
         del g, xf, res_adj
         # three mechanisms (n = 30 / 80 / 200, 12.5k / 25k / 12.5k cells) in one persistent launch,
