@@ -32,6 +32,28 @@ namespace {
 std::mutex g_mu;
 std::map<std::string, JitKernel> g_cache;
 
+// Options of every kernel compile (after --offload-arch), then the scheduling
+// option of the FP64 bodies.  Those are long straight-line bodies whose
+// occupancy is fixed by their register use, so the scheduler is asked to
+// order them for instruction-level parallelism (max-ilp) rather than for the
+// default occupancy/latency balance: with it, the n = 80 FP64 kernel at 32
+// lanes per cell runs 4% faster and the adjoint 3% faster, at the same
+// occupancy and with bitwise the same results.  The FP32 inner solve of the
+// mixed body ran 1.5% slower with it and keeps the default.
+const char* const kJitOptions[] = {"-O3",     "-std=c++17", "-Xclang", "-target-feature",
+                                   "-Xclang", "-packed-fp32-ops"};
+constexpr int kJitOptionCount = (int)(sizeof(kJitOptions) / sizeof(kJitOptions[0]));
+const char* const kIlpOptions[] = {"-mllvm", "-amdgpu-sched-strategy=max-ilp"};
+constexpr int kIlpOptionCount = (int)(sizeof(kIlpOptions) / sizeof(kIlpOptions[0]));
+
+std::string jit_options_key(bool ilp) {
+  std::string k;
+  for (int i = 0; i < kJitOptionCount; ++i) k += std::string(kJitOptions[i]) + " ";
+  if (ilp)
+    for (int i = 0; i < kIlpOptionCount; ++i) k += std::string(kIlpOptions[i]) + " ";
+  return k;
+}
+
 uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
   for (unsigned char c : s) {
     h ^= c;
@@ -76,7 +98,7 @@ void write_file_atomic(const std::string& path, const std::vector<char>& data) {
   std::rename(tmp.c_str(), path.c_str());
 }
 
-int compile(const std::string& src, const std::string& arch, std::vector<char>* code, std::string* log) {
+int compile(const std::string& src, const std::string& arch, bool ilp, std::vector<char>* code, std::string* log) {
   hiprtcProgram prog;
   if (hiprtcCreateProgram(&prog, src.c_str(), "bcs_jit.hip", kJitHeaderCount, kJitHeaderSources,
                           kJitHeaderNames) != HIPRTC_SUCCESS) {
@@ -84,9 +106,12 @@ int compile(const std::string& src, const std::string& arch, std::vector<char>* 
     return -1;
   }
   const std::string arch_opt = "--offload-arch=" + arch;
-  const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                        "-packed-fp32-ops"};
-  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  const char* opts[1 + kJitOptionCount + kIlpOptionCount] = {arch_opt.c_str()};
+  int nopt = 1;
+  for (int i = 0; i < kJitOptionCount; ++i) opts[nopt++] = kJitOptions[i];
+  if (ilp)
+    for (int i = 0; i < kIlpOptionCount; ++i) opts[nopt++] = kIlpOptions[i];
+  const hiprtcResult r = hiprtcCompileProgram(prog, nopt, opts);
   size_t ls = 0;
   hiprtcGetProgramLogSize(prog, &ls);
   if (ls > 1) {
@@ -110,8 +135,9 @@ int compile(const std::string& src, const std::string& arch, std::vector<char>* 
 
 namespace {
 
-// Compile (or load from the caches) `source`, whose kernel is `name`.
-int load_source(const std::string& source, const char* name, size_t lds_bytes, JitKernel* out, char* err,
+// Compile (or load from the caches) `source`, whose kernel is `name`;
+// `ilp` adds the FP64 bodies' scheduling option.
+int load_source(const std::string& source, const char* name, bool ilp, size_t lds_bytes, JitKernel* out, char* err,
                 size_t errlen) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
@@ -125,7 +151,7 @@ int load_source(const std::string& source, const char* name, size_t lds_bytes, J
   }
   std::string arch = prop.gcnArchName;
   const std::string base_arch = arch.substr(0, arch.find(':'));
-  const std::string key = std::string(kJitSourceHash) + "|" + arch + "|" + source;
+  const std::string key = std::string(kJitSourceHash) + "|" + arch + "|" + jit_options_key(ilp) + "|" + source;
 
   std::lock_guard<std::mutex> lock(g_mu);
   const std::string mkey = std::to_string(dev) + "|" + key;
@@ -138,7 +164,7 @@ int load_source(const std::string& source, const char* name, size_t lds_bytes, J
     std::vector<char> code;
     if (!read_file(path, &code)) {
       std::string log;
-      if (compile(source, base_arch, &code, &log) != 0) {
+      if (compile(source, base_arch, ilp, &code, &log) != 0) {
         snprintf(err, errlen, "hipRTC compile failed: %.400s", log.c_str());
         return BCS_ERR_HIP;
       }
@@ -194,7 +220,7 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
   sched_type(src, lanes, flags, seg, rpl);
   if (fp64) src << ", " << (adjoint ? 1 : 0) << ", " << (grouped ? "true" : "false");
   src << ">(P);\n}\n";
-  return load_source(src.str(), name, lds_bytes, out, err, errlen);
+  return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen);
 }
 
 int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,
@@ -210,7 +236,7 @@ int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* c
     sched_type(src, lanes[m], flags[m], seg[m], rpl[m]);
   }
   src << ">(P);\n}\n";
-  return load_source(src.str(), "bcs_solve_multi", lds_bytes, out, err, errlen);
+  return load_source(src.str(), "bcs_solve_multi", true, lds_bytes, out, err, errlen);
 }
 
 }  // namespace bcs
