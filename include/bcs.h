@@ -228,8 +228,10 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
  * the combined launch by timing bcs_solve_multi on the caller's batches
  * (coordinate descent: each mechanism in turn tries 16, 32 and 64 lanes with
  * the others held, for up to two passes; plans created with a fixed
- * lanes_per_cell keep it).  The choice is kept in the plans (adjoint kernels
- * included).  The combined kernel runs at the occupancy of its most
+ * lanes_per_cell keep it; mechanisms without cells are left as they are).
+ * Every combination tried is compiled once (hipRTC, cached on disk like the
+ * plans' kernels), so a first call can take seconds.  The choice is kept in
+ * the plans (adjoint kernels included).  The combined kernel runs at the occupancy of its most
  * register-hungry mechanism, so the best lanes for it can differ from each
  * plan's best alone.  Arguments as in bcs_solve_multi, on the null stream;
  * the outputs serve as scratch and hold one solve's results afterwards;
