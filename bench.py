@@ -99,9 +99,10 @@ def main():
            torch.empty(C, dtype=torch.float64, device=dev), torch.empty(C, dtype=torch.int32, device=dev),
            torch.empty(C, dtype=torch.int32, device=dev)]
     stream = torch.cuda.current_stream()
+    ws = plan.workspace(C, dev)
 
     def step():
-        bcs.solve_batch(plan, values, gamma, b, RTOL, MAXIT, out=out)
+        bcs.solve_batch(plan, values, gamma, b, RTOL, MAXIT, out=out, workspace=ws)
 
     for _ in range(args.warmup):
         step()
@@ -188,17 +189,16 @@ def main():
 
     floor_limited = floor_limited_count(np.nonzero(~((status == 0) & (resid <= RTOL)))[0], cells["b"])
 
-    mixed = None
-    if not args.no_mixed:
+    def mixed_form(budget):
         try:
             mplan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="jacobi", precision="fp32_refine",
-                             lanes_per_cell=args.lanes, cell_order=bool(args.cell_order))
+                             lanes_per_cell=args.lanes, cell_order=bool(args.cell_order), refine_budget=budget)
             if args.lanes == 0:
                 mplan.autotune(values, gamma, b, RTOL, MAXIT)
             mout = [torch.empty_like(o) for o in out]
 
             def mstep():
-                bcs.solve_batch(mplan, values, gamma, b, RTOL, MAXIT, out=mout)
+                bcs.solve_batch(mplan, values, gamma, b, RTOL, MAXIT, out=mout, workspace=ws)
 
             for _ in range(args.warmup):
                 mstep()
@@ -212,15 +212,21 @@ def main():
             msolved = int(np.sum((mst == 0) & (mres <= RTOL)))
             both = (mst == 0) & (status == 0)
             err = np.linalg.norm(mx[both] - x[both], axis=1) / np.linalg.norm(x[both], axis=1)
-            mixed = {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4),
-                     "solved_fraction": round(msolved / C, 5), "iters_mean": round(float(mit.mean()), 2),
-                     "refinements_mean": round(float(mref.mean()), 3),
-                     "unsolved_floor_limited": floor_limited_count(
-                         np.nonzero(~((mst == 0) & (mres <= RTOL)))[0], cells["b"]),
-                     "rel_diff_vs_fp64_max": float(err.max()) if err.size else None,
-                     "rel_diff_vs_fp64_p99": float(np.percentile(err, 99)) if err.size else None}
+            return {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4),
+                    "refine_budget": budget, "lanes_per_cell": mplan.info()["lanes_per_cell"],
+                    "solved_fraction": round(msolved / C, 5), "iters_mean": round(float(mit.mean()), 2),
+                    "refinements_mean": round(float(mref.mean()), 3),
+                    "unsolved_floor_limited": floor_limited_count(
+                        np.nonzero(~((mst == 0) & (mres <= RTOL)))[0], cells["b"]),
+                    "rel_diff_vs_fp64_max": float(err.max()) if err.size else None,
+                    "rel_diff_vs_fp64_p99": float(np.percentile(err, 99)) if err.size else None}
         except bcs.BcsError as e:
-            mixed = {"error": str(e)}
+            return {"error": str(e)}
+
+    mixed = mixed_cell = None
+    if not args.no_mixed:
+        mixed = mixed_form("inner")
+        mixed_cell = mixed_form("cell")
 
     def timed(fn, steps):
         for _ in range(args.warmup):
@@ -243,15 +249,15 @@ def main():
         res_adj = {}
 
         def astep():
-            res_adj["r"] = bcs.solve_batch_adjoint(plan, values, gamma, xf, g, RTOL, MAXIT)
+            res_adj["r"] = bcs.solve_batch_adjoint(plan, values, gamma, xf, g, RTOL, MAXIT, workspace=ws)
 
         ams = timed(astep, args.steps)
-        ast = res_adj["r"][4].cpu().numpy()
-        ares = res_adj["r"][3].cpu().numpy()
+        ast = res_adj["r"][5].cpu().numpy()
+        ares = res_adj["r"][4].cpu().numpy()
         asolved = int(np.sum((ast == 0) & (ares <= RTOL)))
         adjoint = {"value": round(asolved / (ams * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(ams, 4),
                    "solved_fraction": round(asolved / C, 5),
-                   "iters_mean": round(float(res_adj["r"][2].float().mean().item()), 2),
+                   "iters_mean": round(float(res_adj["r"][3].float().mean().item()), 2),
                    "unsolved_floor_limited": floor_limited_count(np.nonzero(~((ast == 0) & (ares <= RTOL)))[0],
                                                                  g_host, transpose=True),
                    "algorithmic_bytes_per_cell": 16 * nnz + 24 * n + 32}
@@ -371,6 +377,7 @@ def main():
         "unsolved_floor_limited": floor_limited,
         "roofline": roofline,
         "fp32_refine": mixed,
+        "fp32_refine_cell_budget": mixed_cell,
         "adjoint": adjoint,
         "multi_mechanism": multi,
         "block_cells_n": block_cells,

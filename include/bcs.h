@@ -19,17 +19,20 @@
  *     in the CSR order of the plan's pattern, vectors [ncells, n].
  *   - Solves are asynchronous on `stream` (a hipStream_t; NULL = the default
  *     stream).  Outputs are valid once the stream has been synchronised.
+ *   - Solves allocate no memory.  Their scratch (the work queue of the
+ *     persistent grid and the cells' cost order) lives in a caller-owned
+ *     DEVICE `workspace` of at least bcs_workspace_bytes(plan, ncells) bytes,
+ *     256-byte aligned, which the solve initialises itself on `stream` (no
+ *     memset needed; any previous contents are ignored).  A plan holds no
+ *     mutable state: several solves with one plan may run at the same time
+ *     (different streams or host threads) provided each has its own
+ *     workspace.  Solves that share a workspace race unless serialised.
  *   - Return value: BCS_OK (0), or a negative BCS_ERR_* code for argument,
  *     pattern, support or HIP runtime errors, detected synchronously before
  *     any launch; bcs_last_error() then describes it (thread-local string).
  *     Numerical outcomes are never return codes: they are per-cell in
  *     `status`.
  *   - ncells == 0 is a no-op that returns BCS_OK.
- *   - Solves that share a plan and overlap in time (different streams, or
- *     several host threads) race on the plan's work-queue counters and cell
- *     order scratch: serialise them, or create one plan per stream.
- *   - With cell_order on, a solve may allocate (once, then whenever ncells
- *     grows) a device array of 4 * ncells bytes that the plan keeps.
  */
 #ifndef BCS_H
 #define BCS_H
@@ -61,6 +64,8 @@ extern "C" {
 #define BCS_PRECOND_JACOBI 1 /* right preconditioning with M = diag(A) */
 #define BCS_J_GAMMA 0        /* values hold J; A = I - gamma*J (pattern must hold the diagonal) */
 #define BCS_A_DIRECT 1       /* values hold A itself; gamma is ignored */
+#define BCS_BUDGET_INNER 0   /* FP32_REFINE: maxit bounds each inner solve */
+#define BCS_BUDGET_CELL 1    /* FP32_REFINE: maxit bounds a cell's inner iterations over all inner solves */
 
 typedef struct bcs_options {
   int32_t precision;            /* BCS_FP64 | BCS_FP32_REFINE                          */
@@ -83,11 +88,12 @@ typedef struct bcs_options {
                                    bcs_plan_autotune for tuning on real data        */
   int32_t cell_order;           /* 1: in a BCS_J_GAMMA solve with one gamma per cell,
                                    hand the cells to the solver in a cost order:
-                                   cells sorted by gamma on the device (two small
-                                   kernels per call), handed out alternately from
-                                   the large-gamma and the small-gamma end, so that
-                                   expensive cells start early.  Results are
-                                   identical to index order.  0: index order       */
+                                   cells sorted by gamma on the device (small
+                                   kernels on the solve's stream), handed out
+                                   alternately from the large-gamma and the
+                                   small-gamma end, so that expensive cells start
+                                   early.  Results are identical to index order.
+                                   0: index order                                  */
   int32_t shared_scalars;       /* 1: Block-cells (N) of Section 3, an experiment
                                    mode: each run of 64 / lanes_per_cell consecutive
                                    cells (one wave's cells; the last run may be
@@ -100,42 +106,61 @@ typedef struct bcs_options {
                                    BCS_MAXIT, or the run's BREAKDOWN / NONFINITE).
                                    Needs FP64, jit = 1 and lanes_per_cell 16, 32 or
                                    64 (1 cell per run); forward solves only, cells
-                                   in index order.  0: every cell on its own      */
-  int32_t reserved[3];          /* must be zero                                       */
+                                   in index order, no initial guess.  0: every cell
+                                   on its own                                      */
+  int32_t refine_budget;        /* FP32_REFINE: BCS_BUDGET_INNER (each inner solve
+                                   may take maxit iterations, at most max_refine
+                                   inner solves) or BCS_BUDGET_CELL (maxit bounds the
+                                   cell's inner iterations summed over its inner
+                                   solves, as it bounds the FP64 solve's iterations
+                                   summed over its restarts)                       */
+  int32_t reserved[2];          /* must be zero                                       */
 } bcs_options;
 
-typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation except for its
-                                     work-queue counters and cell-order scratch
-                                     (see the note above) and the kernels that
-                                     bcs_plan_autotune / bcs_multi_autotune
-                                     choose */
+typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation, except for the
+                                     kernels that bcs_plan_autotune /
+                                     bcs_multi_autotune choose */
 
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
- * max_refine 10, jit 1, autotune 1, cell_order 1, shared_scalars 0. */
+ * max_refine 10, refine_budget BCS_BUDGET_INNER, jit 1, autotune 1,
+ * cell_order 1, shared_scalars 0. */
 void bcs_options_default(bcs_options* opt);
 
-/* Create a plan for an n x n pattern with nnz entries in CSR form
- * (row_ptr[n+1], col_idx[nnz], HOST int32 arrays).  The pattern must have
- * row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing row_ptr, strictly
- * increasing columns in [0, n) within each row, and (for BCS_J_GAMMA or
- * Jacobi preconditioning) every diagonal entry.  opt == NULL means defaults.
- * Allocates the plan's device tables on the current HIP device; the plan
- * must be used on that device.  On error *out is set to NULL. */
+/* Create a plan: the shared sparsity pattern of every cell's Jacobian
+ * (Section 2.2) and the kernels that solve one cell per workgroup slot
+ * (Section 3.1).  The n x n pattern has nnz entries in CSR form (row_ptr[n+1],
+ * col_idx[nnz], HOST int32 arrays) with row_ptr[0] = 0, row_ptr[n] = nnz,
+ * non-decreasing row_ptr, strictly increasing columns in [0, n) within each
+ * row, and (for BCS_J_GAMMA, Jacobi preconditioning or FP32_REFINE) every
+ * diagonal entry; n <= 255.  opt == NULL means defaults.  Allocates the plan's
+ * device tables on the current HIP device (the plan must be used on that
+ * device) and may compile kernels (hipRTC) and time them on a synthetic batch.
+ * On error *out is set to NULL. */
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                     const bcs_options* opt, bcs_plan** out);
 
-/* Release a plan (NULL is allowed).  The caller must ensure no solve using it
- * is still running. */
+/* Release a plan and its device tables (NULL is allowed).  The caller must
+ * ensure no solve using it is still running. */
 void bcs_plan_destroy(bcs_plan* plan);
 
-/* Autotuner on the caller's data: time the forward solve of this batch with
- * every lanes-per-cell layout that holds the pattern (16, 32, 64 lanes per
- * cell, i.e. 16, 8 or 4 cells per workgroup of four waves) and keep the
- * fastest in the plan, adjoint included.  Arguments as in bcs_solve_batch
- * (x/iters/resid/status serve as scratch and hold one solve's outputs
- * afterwards); synchronises the device; *lanes_out (may be NULL) receives the
- * chosen lanes per cell.  Not to be called while solves with the plan run. */
+/* Bytes of device workspace a solve of `ncells` cells with this plan needs
+ * (forward, adjoint and the no-allocation variant alike): the work queue
+ * (256 bytes), the cost-order sort state and 4 bytes per cell for the order.
+ * Returns 0 only for a NULL plan or ncells < 0.  The cells of Section 3.2's
+ * Block-cells arrangement are handed to persistent workgroups through this
+ * queue instead of one block per cell. */
+size_t bcs_workspace_bytes(const bcs_plan* plan, int64_t ncells);
+
+/* Autotuner on the caller's data (the kernel configurations of Section 3.2,
+ * chosen by measurement instead of fixed per mechanism): time the forward
+ * solve of this batch with every lanes-per-cell layout that holds the pattern
+ * (16, 32, 64 lanes per cell, i.e. 16, 8 or 4 cells per workgroup of four
+ * waves) and keep the fastest in the plan, adjoint included.  Arguments as in
+ * bcs_solve_batch (x/iters/resid/status serve as scratch and hold one solve's
+ * outputs afterwards); allocates and frees its own workspace, synchronises the
+ * device; *lanes_out (may be NULL) receives the chosen lanes per cell.  Not to
+ * be called while solves with the plan run. */
 int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, const double* gamma,
                       int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
                       int32_t* iters, double* resid, int32_t* status, int32_t* lanes_out);
@@ -147,8 +172,9 @@ int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, cons
 /* Describe, on the host (no device needed), the gather schedule the
  * specialised solve kernels use for a pattern: its rows dealt to row slots of
  * `lanes` lanes (16, 32 or 64) by decreasing length, each lane's entries step
- * after step (the sliced-ELL layout of Section 3.1's per-cell SpMV), for A
- * (transpose = 0) or for A^T as the adjoint solves it (transpose = 1), with
+ * after step (the sliced-ELL layout of the per-cell SpMV that Section 3.1's
+ * solver performs, one row per thread there, several rows per lane here), for
+ * A (transpose = 0) or for A^T as the adjoint solves it (transpose = 1), with
  * the schedule shapes allowed by `shapes` (BCS_SCHED_* mask; the diagonal is
  * left out only if every row holds it).  For tests and tuning.
  *   *steps          gather steps per lane
@@ -169,22 +195,27 @@ int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const 
                           int32_t transpose, int32_t shapes, int32_t* steps, int32_t* rows_per_lane,
                           int32_t* shape, int32_t* seg, int16_t* row, int32_t* pos, uint8_t* col);
 
-/* Describe the plan's launch configuration (for logs and tests):
- * lanes per cell, rows per lane, schedule steps per lane, cells per
- * workgroup.  Any output pointer may be NULL. */
+/* Describe the plan's launch configuration (the threads- and cells-per-block
+ * choice of Section 3.2's Table 1, here per wavefront): lanes per cell, rows
+ * per lane, schedule steps per lane, cells per workgroup.  Any output pointer
+ * may be NULL. */
 int bcs_plan_info(const bcs_plan* plan, int32_t* lanes_per_cell, int32_t* rows_per_lane,
                   int32_t* steps_per_lane, int32_t* cells_per_wg);
 
 /* Solve (I - gamma_c J_c) x_c = b_c (or A_c x_c = b_c) for every cell c by
- * BiCGStab with x0 = 0, stopping when the relative residual ||r||/||b|| is
- * <= rtol and confirming it on the true residual (Section 3.1's linear
- * solve, one workgroup-resident solve per cell).
+ * BiCGStab, stopping when the relative residual ||r||/||b|| is <= rtol and
+ * confirming it on the true residual (Section 3.1's linear solve, one
+ * workgroup-resident solve per cell, the whole batch in one kernel call with
+ * no host reduction).
  *   values [ncells, nnz]  device, FP64: J (BCS_J_GAMMA) or A (BCS_A_DIRECT)
  *   gamma                 device, FP64: gamma of cell c is gamma[c*gamma_stride]
  *                         (gamma_stride 0 = one shared value); unused for A_DIRECT
  *   b [ncells, n]         device, FP64
+ *   x0 [ncells, n]        device, FP64 initial guess, or NULL for x0 = 0.  A cell
+ *                         whose initial true residual already meets rtol returns
+ *                         x0 with 0 iterations.  Not with shared_scalars.
  *   rtol > 0, 1 <= maxit <= 1000000: the iteration budget of a cell
- *                         (FP32_REFINE: over all its inner solves)
+ *                         (FP32_REFINE: see refine_budget)
  *   x [ncells, n]         device, FP64 out: last iterate (also when not converged)
  *   iters [ncells]        device, int32 out: BiCGStab iterations (half-step exit
  *                         counts 1; FP32_REFINE: total inner iterations)
@@ -193,36 +224,58 @@ int bcs_plan_info(const bcs_plan* plan, int32_t* lanes_per_cell, int32_t* rows_p
  *   status [ncells]       device, int32 out: BCS_CONVERGED .. BCS_NONFINITE
  *   refinements [ncells]  device, int32 out or NULL: FP32_REFINE inner solves
  *                         performed (0 for FP64)
- * The input arrays must not overlap the output arrays. */
+ *   workspace             device, >= bcs_workspace_bytes(plan, ncells) bytes
+ * The input arrays must not overlap the output arrays (x0 may equal x). */
 int bcs_solve_batch(const bcs_plan* plan, int64_t ncells, const double* values, const double* gamma,
-                    int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x,
-                    int32_t* iters, double* resid, int32_t* status, int32_t* refinements, void* stream);
+                    int64_t gamma_stride, const double* b, const double* x0, double rtol, int32_t maxit,
+                    double* x, int32_t* iters, double* resid, int32_t* status, int32_t* refinements,
+                    void* workspace, size_t workspace_bytes, void* stream);
 
-/* Adjoint of the solve for a loss L(x): given the forward solution x and
- * g = dL/dx, solve A_c^T lambda_c = g_c by the same batched BiCGStab run on
- * the transposed pattern (same workgroup layout, FP64), then write
- *   grad_b [ncells, n]   = lambda                          (dL/db)
- *   grad_A [ncells, nnz] = -lambda_i * x_j at entry (i, j) (dL/dA on the pattern)
- * iters/resid/status describe the transposed solve.  The chain rule to J and
- * gamma (A = I - gamma J) is left to the caller:
- *   dL/dJ_k = -gamma * grad_A[k],  dL/dgamma = -sum_k J_k grad_A[k].
- * Arguments as in bcs_solve_batch; x and g are device [ncells, n] FP64. */
+/* What the adjoint writes into grad_vals. */
+#define BCS_GRAD_A 0      /* dL/dA on the pattern: -lambda_i x_j at entry (i, j) */
+#define BCS_GRAD_VALUES 1 /* dL/d(values): in BCS_J_GAMMA mode dL/dJ = gamma_c lambda_i x_j
+                             (A = I - gamma J); in BCS_A_DIRECT mode the same as BCS_GRAD_A */
+
+/* Adjoint of the solve for a loss L(x), the reverse-mode derivative of the
+ * linear solve in the BDF Newton step (Section 2.2): given the forward
+ * solution x and g = dL/dx, solve A_c^T lambda_c = g_c by the same batched
+ * BiCGStab run on the transposed pattern (same workgroup layout, FP64), then
+ * write
+ *   grad_b [ncells, n]       = lambda                                  (dL/db)
+ *   grad_vals [ncells, nnz]  = per grad_kind (BCS_GRAD_A / BCS_GRAD_VALUES)
+ *   grad_gamma [ncells]      = dL/dgamma_c = sum over entries (i, j) of
+ *                              J_ij lambda_i x_j (BCS_J_GAMMA only; may be NULL;
+ *                              must be NULL in BCS_A_DIRECT mode).  With
+ *                              gamma_stride 0 the derivative with respect to the
+ *                              shared gamma is the sum of these per-cell terms.
+ * iters/resid/status describe the transposed solve.  Other arguments as in
+ * bcs_solve_batch; x and g are device [ncells, n] FP64. */
 int bcs_solve_batch_adjoint(const bcs_plan* plan, int64_t ncells, const double* values,
                             const double* gamma, int64_t gamma_stride, const double* x, const double* g,
-                            double rtol, int32_t maxit, double* grad_b, double* grad_A, int32_t* iters,
-                            double* resid, int32_t* status, void* stream);
+                            double rtol, int32_t maxit, int32_t grad_kind, double* grad_b, double* grad_vals,
+                            double* grad_gamma, int32_t* iters, double* resid, int32_t* status,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of device workspace bcs_solve_multi needs for these mechanisms: the
+ * sum over mechanisms of bcs_workspace_bytes(plans[m], ncells[m]) (each part
+ * 256-byte aligned).  Returns 0 on a bad argument. */
+size_t bcs_multi_workspace_bytes(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells);
 
 /* One persistent launch over several mechanisms (plans), each with its own
  * cells: workgroups pull cells from per-mechanism work queues, so a cell
  * slot that converges takes the next unsolved cell (the remainder kernel of
  * Section 3.2 and the fixed cells-per-block choices of Table 1 replaced by
  * work stealing).  Arrays are per mechanism m (host arrays of device
- * pointers, length nmech); semantics per cell as in bcs_solve_batch.  All
- * plans must use BCS_FP64.  nmech <= 8. */
+ * pointers, length nmech); semantics per cell as in bcs_solve_batch with
+ * x0 = 0.  All plans must use BCS_FP64 and jit = 1.  nmech <= 8.  The
+ * mechanisms' LDS layouts must fit one workgroup together (64 KiB); a
+ * combination that does not is rejected with BCS_ERR_UNSUPPORTED before
+ * anything is compiled or launched. */
 int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells,
                     const double* const* values, const double* const* gamma, const int64_t* gamma_stride,
                     const double* const* b, double rtol, int32_t maxit, double* const* x,
-                    int32_t* const* iters, double* const* resid, int32_t* const* status, void* stream);
+                    int32_t* const* iters, double* const* resid, int32_t* const* status, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /* Autotuner of the one-launch form: choose every plan's lanes per cell for
  * the combined launch by timing bcs_solve_multi on the caller's batches
@@ -231,12 +284,13 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
  * lanes_per_cell keep it; mechanisms without cells are left as they are).
  * Every combination tried is compiled once (hipRTC, cached on disk like the
  * plans' kernels), so a first call can take seconds.  The choice is kept in
- * the plans (adjoint kernels included).  The combined kernel runs at the occupancy of its most
- * register-hungry mechanism, so the best lanes for it can differ from each
- * plan's best alone.  Arguments as in bcs_solve_multi, on the null stream;
- * the outputs serve as scratch and hold one solve's results afterwards;
- * synchronises the device; lanes_out (may be NULL) receives nmech lane
- * counts.  Not to be called while solves with the plans run. */
+ * the plans (adjoint kernels included).  The combined kernel runs at the
+ * occupancy of its most register-hungry mechanism, so the best lanes for it
+ * can differ from each plan's best alone.  Arguments as in bcs_solve_multi,
+ * on the null stream, with a workspace it allocates itself; the outputs serve
+ * as scratch and hold one solve's results afterwards; synchronises the
+ * device; lanes_out (may be NULL) receives nmech lane counts.  Not to be
+ * called while solves with the plans run. */
 int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* ncells, const double* const* values,
                        const double* const* gamma, const int64_t* gamma_stride, const double* const* b,
                        double rtol, int32_t maxit, double* const* x, int32_t* const* iters, double* const* resid,

@@ -6,7 +6,8 @@ the mixed form, FP32) implementation in C (``oracle.c``), loaded through
 ctypes.  It shares no code with the HIP library.
 
 Functions (all take/return numpy arrays):
-  solve_batch   BiCGStab per cell (FP64)                   -> x, iters, resid, status
+  solve_batch   BiCGStab per cell (FP64), optional x0      -> x, iters, resid, status
+  solve_batch_f the same BiCGStab in FP32 (mixed form's inner solver)
   lu_batch      dense LU with partial pivoting per cell   -> x (ground truth)
   adjoint_batch lambda = A^-T g and dL/dA on the pattern   -> grad_b, grad_A, iters, resid, status
   mixed_batch   FP32 inner BiCGStab + FP64 refinement      -> x, iters, refinements, resid, status
@@ -56,17 +57,22 @@ def _load():
         return _lib
     build()
     lib = ctypes.CDLL(_LIB_PATH)
-    lib.oracle_solve_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _dbl, _int, _int, _int,
-                                       _int, _D, _I, _D, _I, _int]
+    _vp = ctypes.c_void_p
+    lib.oracle_solve_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _vp, _dbl, _int, _int,
+                                       _int, _int, _D, _I, _D, _I, _int]
     lib.oracle_solve_batch.restype = None
     lib.oracle_lu_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _int, _D, _D, _I, _int]
     lib.oracle_lu_batch.restype = None
     lib.oracle_adjoint_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _D, _dbl, _int, _int,
                                          _int, _int, _D, _D, _I, _D, _I, _int]
     lib.oracle_adjoint_batch.restype = None
-    lib.oracle_mixed_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _dbl, _int, _dbl, _int,
-                                       _D, _I, _I, _D, _I, _int]
+    lib.oracle_mixed_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _vp, _dbl, _int, _dbl,
+                                       _int, _int, _D, _I, _I, _D, _I, _int]
     lib.oracle_mixed_batch.restype = None
+    _F = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+    lib.oracle_solve_batch_f.argtypes = [_i64, _int, _int, _I, _I, _F, _F, _dbl, _int, _int, _int, _int, _F, _I, _D,
+                                         _I]
+    lib.oracle_solve_batch_f.restype = None
     lib.oracle_form_a.argtypes = [_int, _I, _I, _D, _dbl, _D]
     lib.oracle_form_a.restype = None
     lib.oracle_lu_solve.argtypes = [_int, _D, _D]
@@ -99,16 +105,43 @@ def _prep(row_ptr, col_idx, values, gamma, b=None):
     return out
 
 
+def _x0_arg(x0, C, n):
+    if x0 is None:
+        return None, None
+    a = np.ascontiguousarray(x0, dtype=np.float64).reshape(C, n)
+    return a, a.ctypes.data
+
+
 def solve_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, precond=0, kind=J_GAMMA,
-                residual_replacement=1, breakdown_restarts=1, nthreads=0):
+                residual_replacement=1, breakdown_restarts=1, nthreads=0, x0=None):
     rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
     x = np.zeros((C, n))
     iters = np.zeros(C, dtype=np.int32)
     resid = np.zeros(C)
     status = np.zeros(C, dtype=np.int32)
-    _load().oracle_solve_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, float(rtol), int(maxit), int(precond),
+    x0a, x0p = _x0_arg(x0, C, n)
+    _load().oracle_solve_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, x0p, float(rtol), int(maxit), int(precond),
                                int(residual_replacement), int(breakdown_restarts), x, iters, resid, status,
                                int(nthreads))
+    return x, iters, resid, status
+
+
+def solve_batch_f(row_ptr, col_idx, A32, b32, rtol=1e-6, maxit=200, precond=0, residual_replacement=1,
+                  breakdown_restarts=1):
+    """The BiCGStab of solve_batch carried out entirely in FP32 (the mixed form's inner solver), on FP32 matrices
+    [ncells, nnz] (values of A) and right-hand sides, from x0 = 0.  Returns x (float32), iters, resid, status."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n, nnz = rp.shape[0] - 1, ci.shape[0]
+    A = np.ascontiguousarray(A32, dtype=np.float32).reshape(-1, nnz)
+    C = A.shape[0]
+    bb = np.ascontiguousarray(b32, dtype=np.float32).reshape(C, n)
+    x = np.zeros((C, n), dtype=np.float32)
+    iters = np.zeros(C, dtype=np.int32)
+    resid = np.zeros(C)
+    status = np.zeros(C, dtype=np.int32)
+    _load().oracle_solve_batch_f(C, n, nnz, rp, ci, A, bb, float(rtol), int(maxit), int(precond),
+                                 int(residual_replacement), int(breakdown_restarts), x, iters, resid, status)
     return x, iters, resid, status
 
 
@@ -191,16 +224,20 @@ def adjoint_batch(row_ptr, col_idx, values, gamma, x, g, rtol=1e-10, maxit=200, 
 
 
 def mixed_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, inner_rtol=1e-4, max_refine=10,
-                kind=J_GAMMA, nthreads=0):
+                kind=J_GAMMA, nthreads=0, budget="inner", x0=None):
+    """budget "inner": maxit bounds each inner solve; "cell": the cell's inner iterations over all inner solves."""
     rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
     x = np.zeros((C, n))
     iters = np.zeros(C, dtype=np.int32)
     refin = np.zeros(C, dtype=np.int32)
     resid = np.zeros(C)
     status = np.zeros(C, dtype=np.int32)
-    _load().oracle_mixed_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, float(rtol), int(maxit),
-                               float(inner_rtol), int(max_refine), x, iters, refin, resid, status,
-                               int(nthreads))
+    if budget not in ("inner", "cell"):
+        raise ValueError("budget must be 'inner' or 'cell'")
+    x0a, x0p = _x0_arg(x0, C, n)
+    _load().oracle_mixed_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, x0p, float(rtol), int(maxit),
+                               float(inner_rtol), int(max_refine), int(budget == "cell"), x, iters, refin, resid,
+                               status, int(nthreads))
     return x, iters, refin, resid, status
 
 

@@ -11,7 +11,9 @@
  * names its linear solver only as the BSC "Biconjugate Gradient" GPU solver
  * (Section 3.1) and prints no algorithm, so the published BiCGStab is
  * followed.  Readings taken where the paper is silent:
- *   - initial guess x0 = 0 and shadow residual rhat = r0 = b;
+ *   - initial guess x0 = 0 unless the caller gives one, shadow residual
+ *     rhat = r0 = b - A x0; a cell whose initial residual already meets
+ *     rtol takes no iteration;
  *   - stop when ||s||/||b|| or ||r||/||b|| (2-norm, recurrence residual) is
  *     <= rtol, then confirm on the true residual ||b - A x||/||b||;
  *   - if the true residual misses rtol: residual replacement (r <- b - A x,
@@ -51,9 +53,10 @@ static void FN(spmv_)(int n, const int* rp, const int* ci, const REAL* A, const 
   }
 }
 
-/* Returns the iteration count.  w must hold 10*n elements. */
-static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, double rtol,
-                         int maxit, int precond, int rr, int brs, REAL* x, double* resid_out,
+/* Returns the iteration count.  x0 is the initial guess (NULL: zero).  w must
+ * hold 10*n elements. */
+static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, const REAL* x0,
+                         double rtol, int maxit, int precond, int rr, int brs, REAL* x, double* resid_out,
                          int* status_out, REAL* w) {
   REAL *r = w, *rh = w + n, *p = w + 2 * n, *v = w + 3 * n, *s = w + 4 * n;
   REAL *t = w + 5 * n, *ph = w + 6 * n, *sh = w + 7 * n, *dinv = w + 8 * n, *rt = w + 9 * n;
@@ -77,7 +80,22 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
       dinv[i] = (REAL)1 / d;
     }
   }
-  for (int i = 0; i < n; ++i) r[i] = b[i];
+  /* r0 = b - A x0 */
+  if (x0) {
+    for (int i = 0; i < n; ++i) x[i] = x0[i];
+    FN(spmv_)(n, rp, ci, A, x, rt);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - rt[i];
+  } else {
+    for (int i = 0; i < n; ++i) r[i] = b[i];
+  }
+  {
+    double r0 = (double)FN(nrm2_)(n, r) / (double)bn;
+    if (r0 <= rtol) {
+      *resid_out = r0;
+      *status_out = OR_CONVERGED;
+      return 0;
+    }
+  }
 
   int it = 0, restarts_left = brs, ended = OR_MAXIT;
   double res = 0.0;

@@ -78,11 +78,12 @@ static void cell_matrix(int n, int nnz, const int* rp, const int* ci, const doub
   }
 }
 
-/* FP64 BiCGStab over a batch of cells (OpenMP over cells, static schedule). */
+/* FP64 BiCGStab over a batch of cells (OpenMP over cells, static schedule).
+ * x0: initial guesses [ncells, n], or NULL for zero. */
 void oracle_solve_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
-                        const double* gamma, int64_t gamma_stride, int kind, const double* b, double rtol,
-                        int maxit, int precond, int rr, int brs, double* x, int32_t* iters, double* resid,
-                        int32_t* status, int nthreads) {
+                        const double* gamma, int64_t gamma_stride, int kind, const double* b, const double* x0,
+                        double rtol, int maxit, int precond, int rr, int brs, double* x, int32_t* iters,
+                        double* resid, int32_t* status, int nthreads) {
   set_threads(nthreads);
 #pragma omp parallel
   {
@@ -92,12 +93,29 @@ void oracle_solve_batch(int64_t ncells, int n, int nnz, const int* rp, const int
     for (int64_t c = 0; c < ncells; ++c) {
       cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
       int st = 0;
-      iters[c] = bicgstab_d(n, rp, ci, A, b + c * n, rtol, maxit, precond, rr, brs, x + c * n, &resid[c], &st, w);
+      iters[c] = bicgstab_d(n, rp, ci, A, b + c * n, x0 ? x0 + c * n : NULL, rtol, maxit, precond, rr, brs,
+                            x + c * n, &resid[c], &st, w);
       status[c] = st;
     }
     free(A);
     free(w);
   }
+}
+
+/* The same BiCGStab entirely in FP32 (the inner solver of the mixed form) on
+ * FP32 matrices A [ncells, nnz] (A_DIRECT) and right-hand sides, x0 = 0.
+ * Exposed so that the FP32 solver can be pinned on its own. */
+void oracle_solve_batch_f(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const float* A,
+                          const float* b, double rtol, int maxit, int precond, int rr, int brs, float* x,
+                          int32_t* iters, double* resid, int32_t* status) {
+  float* w = (float*)malloc(sizeof(float) * 10 * (size_t)(n > 0 ? n : 1));
+  for (int64_t c = 0; c < ncells; ++c) {
+    int st = 0;
+    iters[c] = bicgstab_f(n, rp, ci, A + c * (int64_t)nnz, b + c * n, NULL, rtol, maxit, precond, rr, brs,
+                          x + c * n, &resid[c], &st, w);
+    status[c] = st;
+  }
+  free(w);
 }
 
 /* Dense LU with partial pivoting (Doolittle; pivot = largest |a|, lowest row
@@ -207,7 +225,8 @@ void oracle_adjoint_batch(int64_t ncells, int n, int nnz, const int* rp, const i
       for (int q = 0; q < nnz; ++q) AT[q] = A[perm[q]];
       int st = 0;
       double* lam = grad_b + c * n;
-      iters[c] = bicgstab_d(n, trp, tci, AT, g + c * n, rtol, maxit, precond, rr, brs, lam, &resid[c], &st, w);
+      iters[c] = bicgstab_d(n, trp, tci, AT, g + c * n, NULL, rtol, maxit, precond, rr, brs, lam, &resid[c], &st,
+                            w);
       status[c] = st;
       const double* xc = x + c * n;
       for (int i = 0; i < n; ++i)
@@ -224,22 +243,22 @@ void oracle_adjoint_batch(int64_t ncells, int n, int nnz, const int* rp, const i
 
 /* Mixed precision: FP32 inner BiCGStab inside FP64 iterative refinement.
  *   D = diag(A) (FP64); Ahat = A D^-1 (FP64 division, then rounded to float);
- *   x = 0, r = b;
- *   repeat up to max_refine times while ||r||/||b|| > rtol and fewer than
- *   maxit inner iterations were spent (maxit is the cell's iteration budget
- *   over all inner solves, as it bounds the FP64 solve's iterations over its
- *   restarts):
+ *   x = x0 (or 0), r = b - A x;
+ *   repeat up to max_refine times while ||r||/||b|| > rtol (and, with
+ *   budget_cell, while fewer than maxit inner iterations were spent: maxit is
+ *   then the cell's iteration budget over all inner solves):
  *     rhat32 = float(r / ||r||);
- *     solve Ahat d = rhat32 in FP32 to inner_rtol (no residual replacement);
+ *     solve Ahat d = rhat32 in FP32 to inner_rtol (no residual replacement)
+ *     within maxit iterations (budget_cell: the cell's remaining budget);
  *     x_new = x + ||r|| * D^-1 * d (FP64); r_new = b - A x_new (FP64);
  *     if ||r_new|| >= ||r||: stop (refinement stagnates; x is kept).
  * iters = sum of inner iterations, refinements = inner solves performed.
  * Status: CONVERGED if the final FP64 relative residual <= rtol, NONFINITE on
  * non-finite values, otherwise MAXIT. */
 void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
-                        const double* gamma, int64_t gamma_stride, int kind, const double* b, double rtol,
-                        int maxit, double inner_rtol, int max_refine, double* x, int32_t* iters,
-                        int32_t* refinements, double* resid, int32_t* status, int nthreads) {
+                        const double* gamma, int64_t gamma_stride, int kind, const double* b, const double* x0,
+                        double rtol, int maxit, double inner_rtol, int max_refine, int budget_cell, double* x,
+                        int32_t* iters, int32_t* refinements, double* resid, int32_t* status, int nthreads) {
   set_threads(nthreads);
 #pragma omp parallel
   {
@@ -278,16 +297,29 @@ void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int
         }
         for (int i = 0; i < n; ++i)
           for (int k = rp[i]; k < rp[i + 1]; ++k) A32[k] = (float)(A[k] / dg[ci[k]]);
-        for (int i = 0; i < n; ++i) r[i] = bc[i];
         double rn = bn;
+        if (x0) {
+          for (int i = 0; i < n; ++i) xc[i] = x0[c * n + i];
+          for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) acc += A[k] * xc[ci[k]];
+            r[i] = bc[i] - acc;
+          }
+          rn = 0.0;
+          for (int i = 0; i < n; ++i) rn += r[i] * r[i];
+          rn = sqrt(rn);
+        } else {
+          for (int i = 0; i < n; ++i) r[i] = bc[i];
+        }
         while (1) {
           if (!isfinite(rn)) { st = OR_NONFINITE; break; }
           if (rn / bn <= rtol) { st = OR_CONVERGED; break; }
-          if (nref >= max_refine || tot >= maxit) { st = OR_MAXIT; break; }
+          if (nref >= max_refine || (budget_cell && tot >= maxit)) { st = OR_MAXIT; break; }
           for (int i = 0; i < n; ++i) r32[i] = (float)(r[i] / rn);
           double ires;
           int ist;
-          tot += bicgstab_f(n, rp, ci, A32, r32, inner_rtol, maxit - tot, 0, 0, 1, d32, &ires, &ist, w32);
+          tot += bicgstab_f(n, rp, ci, A32, r32, NULL, inner_rtol, budget_cell ? maxit - tot : maxit, 0, 0, 1, d32,
+                            &ires, &ist, w32);
           ++nref;
           if (ist == OR_NONFINITE) { st = OR_NONFINITE; break; }
           for (int i = 0; i < n; ++i) xn[i] = xc[i] + rn * ((double)d32[i] / dg[i]);

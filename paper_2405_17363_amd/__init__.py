@@ -7,17 +7,21 @@ no fallback: if the library is missing or fails to load, the import of the
 entry points raises.
 
     plan = Plan(row_ptr, col_idx, precond="jacobi")          # shared pattern
-    x, iters, resid, status = solve_batch(plan, J, gamma, b)  # per-cell values
-    x = BatchedSolve.apply(J, gamma, b, plan)                 # differentiable
+    x, iters, resid, status, _ = solve_batch(plan, J, gamma, b)  # per-cell values
+    x, status = BatchedSolve.apply(J, gamma, b, plan)            # differentiable
 """
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
     BCS_A_DIRECT,
     BCS_BREAKDOWN,
+    BCS_BUDGET_CELL,
+    BCS_BUDGET_INNER,
     BCS_CONVERGED,
     BCS_FP32_REFINE,
     BCS_FP64,
+    BCS_GRAD_A,
+    BCS_GRAD_VALUES,
     BCS_J_GAMMA,
     BCS_MAXIT,
     BCS_NONFINITE,
@@ -25,6 +29,7 @@ from ._binding import (  # noqa: F401
     BCS_SCHED_SPAN,
     BcsError,
     BatchedSolve,
+    BatchedSolveWarning,
     Plan,
     exported_symbols,
     lib,

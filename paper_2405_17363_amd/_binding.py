@@ -19,10 +19,14 @@ BCS_FP64, BCS_FP32_REFINE = 0, 1
 BCS_PRECOND_NONE, BCS_PRECOND_JACOBI = 0, 1
 BCS_J_GAMMA, BCS_A_DIRECT = 0, 1
 BCS_SCHED_SPAN, BCS_SCHED_DIAG = 1, 2
+BCS_BUDGET_INNER, BCS_BUDGET_CELL = 0, 1
+BCS_GRAD_A, BCS_GRAD_VALUES = 0, 1
 
 _PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI}
 _PRECISION = {"fp64": BCS_FP64, "fp32_refine": BCS_FP32_REFINE}
 _KIND = {"j_gamma": BCS_J_GAMMA, "a_direct": BCS_A_DIRECT}
+_BUDGET = {"inner": BCS_BUDGET_INNER, "cell": BCS_BUDGET_CELL}
+_GRAD = {"A": BCS_GRAD_A, "values": BCS_GRAD_VALUES}
 
 
 class BcsError(RuntimeError):
@@ -45,7 +49,8 @@ class _Options(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("cell_order", ctypes.c_int32),
         ("shared_scalars", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("refine_budget", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -79,11 +84,16 @@ def lib():
         L.bcs_plan_autotune.restype = ctypes.c_int
         L.bcs_plan_info.argtypes = [P, P, P, P, P]
         L.bcs_plan_info.restype = ctypes.c_int
-        L.bcs_solve_batch.argtypes = [P, I64, P, P, I64, P, D, I32, P, P, P, P, P, VP]
+        SZ = ctypes.c_size_t
+        L.bcs_workspace_bytes.argtypes = [P, I64]
+        L.bcs_workspace_bytes.restype = SZ
+        L.bcs_solve_batch.argtypes = [P, I64, P, P, I64, P, P, D, I32, P, P, P, P, P, P, SZ, VP]
         L.bcs_solve_batch.restype = ctypes.c_int
-        L.bcs_solve_batch_adjoint.argtypes = [P, I64, P, P, I64, P, P, D, I32, P, P, P, P, P, VP]
+        L.bcs_solve_batch_adjoint.argtypes = [P, I64, P, P, I64, P, P, D, I32, I32, P, P, P, P, P, P, P, SZ, VP]
         L.bcs_solve_batch_adjoint.restype = ctypes.c_int
-        L.bcs_solve_multi.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, VP]
+        L.bcs_multi_workspace_bytes.argtypes = [I32, P, P]
+        L.bcs_multi_workspace_bytes.restype = SZ
+        L.bcs_solve_multi.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, P, SZ, VP]
         L.bcs_solve_multi.restype = ctypes.c_int
         L.bcs_multi_autotune.argtypes = [I32, P, P, P, P, P, P, D, I32, P, P, P, P, P]
         L.bcs_multi_autotune.restype = ctypes.c_int
@@ -161,7 +171,7 @@ class Plan:
                  matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
                  breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10,
                  jit: bool = True, autotune: bool = True, cell_order: bool = True,
-                 shared_scalars: bool = False):
+                 shared_scalars: bool = False, refine_budget: str = "inner"):
         L = lib()
         rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
         ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
@@ -182,6 +192,7 @@ class Plan:
         opt.autotune = int(bool(autotune))
         opt.cell_order = int(bool(cell_order))
         opt.shared_scalars = int(bool(shared_scalars))
+        opt.refine_budget = _BUDGET[refine_budget]
         self.options = opt
         self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
         h = ctypes.c_void_p()
@@ -194,6 +205,13 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def workspace_bytes(self, ncells: int) -> int:
+        return int(lib().bcs_workspace_bytes(self._h, int(ncells)))
+
+    def workspace(self, ncells: int, device=None):
+        """A device workspace for a solve of `ncells` cells (a uint8 tensor)."""
+        return _workspace(self.workspace_bytes(ncells), device)
 
     def info(self) -> dict:
         v = [ctypes.c_int32() for _ in range(4)]
@@ -238,14 +256,40 @@ def _gamma_arg(gamma, ncells, device):
     return gamma, 1
 
 
-def solve_batch(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 200, out=None):
-    """Solve every cell's system; returns (x, iters, resid, status, refinements)."""
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("the device allocator returned a workspace that is not 256-byte aligned")
+    return ws
+
+
+def _check_ws(ws, need: int, device):
+    torch = _torch()
+    if ws is None:
+        return _workspace(need, device)
+    _dev(ws, torch.uint8, "workspace")
+    if ws.numel() < need:
+        raise ValueError(f"workspace holds {ws.numel()} bytes, {need} needed")
+    return ws
+
+
+def solve_batch(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 200, out=None, x0=None,
+                workspace=None):
+    """Solve every cell's system; returns (x, iters, resid, status, refinements).
+
+    x0: optional initial guess [ncells, n] (may be the `x` of `out`); workspace:
+    optional uint8 device tensor of at least plan.workspace_bytes(ncells) bytes
+    (one is allocated through torch's caching allocator otherwise)."""
     torch = _torch()
     values = _dev(values, torch.float64, "values")
     ncells = values.shape[0] if values.dim() == 2 else 0
     _dev(values, torch.float64, "values", (ncells, plan.nnz))
     _dev(b, torch.float64, "b", (ncells, plan.n))
+    if x0 is not None:
+        _dev(x0, torch.float64, "x0", (ncells, plan.n))
     g, gs = _gamma_arg(gamma, ncells, values.device)
+    ws = _check_ws(workspace, plan.workspace_bytes(ncells), values.device)
     if out is None:
         x = torch.empty((ncells, plan.n), dtype=torch.float64, device=values.device)
         iters = torch.empty(ncells, dtype=torch.int32, device=values.device)
@@ -255,15 +299,21 @@ def solve_batch(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 
     else:
         x, iters, resid, status, refin = out
     rc = lib().bcs_solve_batch(plan.handle, ncells, values.data_ptr(), g.data_ptr(), gs, b.data_ptr(),
-                               float(rtol), int(maxit), x.data_ptr(), iters.data_ptr(), resid.data_ptr(),
-                               status.data_ptr(), refin.data_ptr() if refin is not None else None,
+                               x0.data_ptr() if x0 is not None else None, float(rtol), int(maxit), x.data_ptr(),
+                               iters.data_ptr(), resid.data_ptr(), status.data_ptr(),
+                               refin.data_ptr() if refin is not None else None, ws.data_ptr(), ws.numel(),
                                _stream_handle())
     _check(rc)
     return x, iters, resid, status, refin
 
 
-def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, maxit: int = 200):
-    """Adjoint solve: returns (grad_b = lambda, grad_A, iters, resid, status)."""
+def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, maxit: int = 200,
+                        grad_kind: str = "A", grad_gamma: bool = False, workspace=None):
+    """Adjoint solve: returns (grad_b = lambda, grad_vals, grad_gamma, iters, resid, status).
+
+    grad_kind "A": grad_vals = dL/dA on the pattern; "values": dL/d(values)
+    (dL/dJ in J mode).  grad_gamma: also return dL/dgamma per cell (J mode),
+    else None."""
     torch = _torch()
     values = _dev(values, torch.float64, "values")
     ncells = values.shape[0]
@@ -271,17 +321,20 @@ def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, ma
     _dev(g, torch.float64, "g", (ncells, plan.n))
     gm, gs = _gamma_arg(gamma, ncells, values.device)
     dev = values.device
+    ws = _check_ws(workspace, plan.workspace_bytes(ncells), dev)
     grad_b = torch.empty((ncells, plan.n), dtype=torch.float64, device=dev)
-    grad_A = torch.empty((ncells, plan.nnz), dtype=torch.float64, device=dev)
+    grad_v = torch.empty((ncells, plan.nnz), dtype=torch.float64, device=dev)
+    grad_g = torch.empty(ncells, dtype=torch.float64, device=dev) if grad_gamma else None
     iters = torch.empty(ncells, dtype=torch.int32, device=dev)
     resid = torch.empty(ncells, dtype=torch.float64, device=dev)
     status = torch.empty(ncells, dtype=torch.int32, device=dev)
     rc = lib().bcs_solve_batch_adjoint(plan.handle, ncells, values.data_ptr(), gm.data_ptr(), gs, x.data_ptr(),
-                                       g.data_ptr(), float(rtol), int(maxit), grad_b.data_ptr(),
-                                       grad_A.data_ptr(), iters.data_ptr(), resid.data_ptr(), status.data_ptr(),
-                                       _stream_handle())
+                                       g.data_ptr(), float(rtol), int(maxit), _GRAD[grad_kind], grad_b.data_ptr(),
+                                       grad_v.data_ptr(), grad_g.data_ptr() if grad_g is not None else None,
+                                       iters.data_ptr(), resid.data_ptr(), status.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), _stream_handle())
     _check(rc)
-    return grad_b, grad_A, iters, resid, status
+    return grad_b, grad_v, grad_g, iters, resid, status
 
 
 def _multi_args(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence):
@@ -315,12 +368,14 @@ def _multi_args(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: S
 
 
 def solve_multi(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs: Sequence, rtol: float = 1e-10,
-                maxit: int = 200):
+                maxit: int = 200, workspace=None):
     """One persistent launch over several mechanisms; per mechanism (x, iters, resid, status)."""
     m, arrs, nc, gst, outs, keep = _multi_args(plans, values, gammas, bs)  # keep: tensors alive across the call
+    need = int(lib().bcs_multi_workspace_bytes(m, arrs["plans"], nc))
+    ws = _check_ws(workspace, need, values[0].device)
     rc = lib().bcs_solve_multi(m, arrs["plans"], nc, arrs["values"], arrs["gamma"], gst, arrs["b"], float(rtol),
-                               int(maxit), arrs["x"], arrs["iters"], arrs["resid"], arrs["status"],
-                               _stream_handle())
+                               int(maxit), arrs["x"], arrs["iters"], arrs["resid"], arrs["status"], ws.data_ptr(),
+                               ws.numel(), _stream_handle())
     _check(rc)
     return outs
 
@@ -340,13 +395,22 @@ def multi_autotune(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs
     return list(lanes)
 
 
+class BatchedSolveWarning(UserWarning):
+    """Cells of a differentiable solve whose forward or adjoint solve did not converge."""
+
+
 class BatchedSolve:
     """Differentiable batched solve x = (I - gamma J)^-1 b (J mode) or A^-1 b.
 
-    ``BatchedSolve.apply(values, gamma, b, plan, rtol, maxit)`` returns x.
-    Backward runs the library's adjoint solve (transposed BiCGStab) and maps
-    dL/dA to the inputs: in J mode dL/dJ = -gamma dL/dA and
-    dL/dgamma = -sum_k J_k dL/dA_k per cell; in A mode dL/dA is returned as is.
+    ``BatchedSolve.apply(values, gamma, b, plan, rtol, maxit)`` returns
+    ``(x, status)``: x differentiable, status the per-cell int32 solve status
+    (not differentiable; cells with status != 0 carry the solver's best
+    iterate, not the solution).  Backward runs the library's adjoint solve
+    (transposed BiCGStab), whose epilogue writes the gradients with respect to
+    the inputs themselves (dL/dJ and dL/dgamma in J mode, dL/dA in A mode);
+    cells whose adjoint solve did not converge are reported with a
+    BatchedSolveWarning.  A scalar gamma tensor is expanded to one value per
+    cell, so autograd sums the per-cell gamma gradients.
     """
 
     _fn = None
@@ -359,33 +423,38 @@ class BatchedSolve:
             class _F(torch.autograd.Function):
                 @staticmethod
                 def forward(ctx, values, gamma, b, plan, rtol=1e-10, maxit=200):
-                    x, iters, resid, status, _ = solve_batch(plan, values.contiguous(), gamma, b.contiguous(),
-                                                             rtol, maxit)
+                    values_c = values.contiguous()
+                    x, iters, resid, status, _ = solve_batch(plan, values_c, gamma, b.contiguous(), rtol, maxit)
                     ctx.plan, ctx.rtol, ctx.maxit = plan, rtol, maxit
-                    ctx.save_for_backward(values, gamma if isinstance(gamma, torch.Tensor) else None, x)
+                    ctx.save_for_backward(values_c, gamma if isinstance(gamma, torch.Tensor) else None, x)
                     ctx.gamma_obj = gamma
-                    return x
+                    ctx.mark_non_differentiable(status)
+                    return x, status
 
                 @staticmethod
-                def backward(ctx, gx):
+                def backward(ctx, gx, _gstatus):
                     values, gamma_t, x = ctx.saved_tensors
                     plan = ctx.plan
                     gamma = gamma_t if gamma_t is not None else ctx.gamma_obj
-                    grad_b, grad_A, _, _, _ = solve_batch_adjoint(plan, values, gamma, x, gx.contiguous(),
-                                                                  ctx.rtol, ctx.maxit)
-                    if plan.matrix_kind == "a_direct":
-                        return grad_A, None, grad_b, None, None, None
-                    g = gamma_t.reshape(-1, 1) if gamma_t is not None else float(gamma)
-                    grad_J = -g * grad_A
-                    grad_gamma = None
-                    if gamma_t is not None and ctx.needs_input_grad[1]:
-                        per_cell = -(values * grad_A).sum(dim=1)
-                        grad_gamma = per_cell if gamma_t.numel() > 1 else per_cell.sum().reshape(gamma_t.shape)
-                    return grad_J, grad_gamma, grad_b, None, None, None
+                    j_mode = plan.matrix_kind != "a_direct"
+                    want_g = j_mode and gamma_t is not None and ctx.needs_input_grad[1]
+                    grad_b, grad_v, grad_g, _, _, st = solve_batch_adjoint(
+                        plan, values, gamma, x, gx.contiguous(), ctx.rtol, ctx.maxit, grad_kind="values",
+                        grad_gamma=want_g)
+                    bad = int((st != BCS_CONVERGED).sum().item())
+                    if bad:
+                        import warnings
+
+                        warnings.warn(f"{bad} of {st.numel()} cells: the adjoint solve did not converge; their "
+                                      "gradients come from the best iterate", BatchedSolveWarning, stacklevel=2)
+                    return grad_v, grad_g, grad_b, None, None, None
 
             cls._fn = _F
         return cls._fn
 
     @classmethod
     def apply(cls, values, gamma, b, plan, rtol=1e-10, maxit=200):
+        torch = _torch()
+        if isinstance(gamma, torch.Tensor) and gamma.numel() == 1 and values.dim() == 2 and values.shape[0] > 1:
+            gamma = gamma.reshape(1).expand(values.shape[0]).contiguous()
         return cls._function().apply(values, gamma, b, plan, rtol, maxit)

@@ -507,12 +507,6 @@ struct bcs_plan {
   int32_t* diag_pos = nullptr;
   int16_t* coo_row = nullptr;
   int16_t* coo_col = nullptr;
-  unsigned long long* queue = nullptr;  // forward solves' work queue, then the adjoint's (kQueueWords each)
-  // cost order of the cells (forward, adjoint): sort state and order arrays
-  // of `order_cap` cells, grown on demand
-  uint32_t* order_state[2] = {nullptr, nullptr};
-  int32_t* order[2] = {nullptr, nullptr};
-  int64_t order_cap[2] = {0, 0};
 };
 
 namespace {
@@ -525,11 +519,6 @@ void release(bcs_plan* p) {
   free_kernel(&p->adj);
   if (p->diag_pos) (void)hipFree(p->diag_pos);
   if (p->coo_row) (void)hipFree(p->coo_row);
-  if (p->queue) (void)hipFree(p->queue);
-  for (int k = 0; k < 2; ++k) {
-    if (p->order_state[k]) (void)hipFree(p->order_state[k]);
-    if (p->order[k]) (void)hipFree(p->order[k]);
-  }
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
 }
@@ -551,37 +540,61 @@ bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values
   P.brs = p->opt.breakdown_restarts;
   P.inner_rtol = p->opt.inner_rtol;
   P.max_refine = p->opt.max_refine;
+  P.budget = p->opt.refine_budget == BCS_BUDGET_CELL ? 1 : 0;
   P.diag_pos = p->diag_pos;
   P.coo_row = p->coo_row;
   P.coo_col = p->coo_col;
   return P;
 }
 
-// Cost order for a solve (kind 0 forward, 1 adjoint): with cell_order on,
-// cells solved on their own (not shared_scalars), per-cell gamma and at
-// least two cells, sort the cells by gamma on the
-// stream and point the solve at the order.  The order array grows on demand
-// (the only allocation a solve call can make).
-int cell_order(bcs_plan* p, int kind, bcs::KParams* P, hipStream_t stream) {
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t ws_bytes(int64_t ncells) {
+  return align256((size_t)bcs::kWsOrderOffset + (size_t)std::max<int64_t>(ncells, 0) * sizeof(int32_t));
+}
+
+// Prologue of a solve on `stream`: point the kernel at its work queue in the
+// workspace and clear it, and, with cell_order on, cells solved on their own
+// (not shared_scalars), per-cell gamma and at least two cells, sort the cells
+// by gamma into the workspace's order array and point the solve at it.
+int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream) {
+  char* w = (char*)ws;
+  P->queue = (unsigned long long*)w;
   P->order = nullptr;
-  if (p->opt.cell_order != 1 || p->opt.shared_scalars == 1 || p->opt.matrix_kind != BCS_J_GAMMA ||
-      P->gamma_stride == 0 || P->ncells < 2 || P->ncells > INT32_MAX)
-    return BCS_OK;
-  if (!p->order_state[kind])
-    HIP_TRY(hipMalloc((void**)&p->order_state[kind], bcs::kOrderStateWords * sizeof(uint32_t)));
-  if (P->ncells > p->order_cap[kind]) {
-    if (p->order[kind]) HIP_TRY(hipFree(p->order[kind]));
-    p->order[kind] = nullptr;
-    p->order_cap[kind] = 0;
-    HIP_TRY(hipMalloc((void**)&p->order[kind], (size_t)P->ncells * sizeof(int32_t)));
-    p->order_cap[kind] = P->ncells;
-  }
-  const hipError_t e =
-      bcs::launch_cell_order(P->gamma, P->gamma_stride, P->ncells, p->order_state[kind], p->order[kind], stream);
-  if (e != hipSuccess) return fail(BCS_ERR_HIP, "cell order launch: %s", hipGetErrorString(e));
-  P->order = p->order[kind];
+  const bool use_order = p->opt.cell_order == 1 && p->opt.shared_scalars == 0 && p->opt.matrix_kind == BCS_J_GAMMA &&
+                         P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX;
+  int32_t* order = use_order ? (int32_t*)(w + bcs::kWsOrderOffset) : nullptr;
+  const hipError_t e = bcs::launch_solve_prologue(P->queue, P->gamma, P->gamma_stride, P->ncells,
+                                                  (uint32_t*)(w + bcs::kWsStateOffset), order, stream);
+  if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve prologue launch: %s", hipGetErrorString(e));
+  P->order = order;
   return BCS_OK;
 }
+
+int check_workspace(const bcs_plan* p, int64_t ncells, void* ws, size_t bytes) {
+  (void)p;
+  if (!ws) return fail(BCS_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255u) != 0) return fail(BCS_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < ws_bytes(ncells))
+    return fail(BCS_ERR_ARG, "workspace of %zu bytes is smaller than the %zu bytes needed for %lld cells", bytes,
+                ws_bytes(ncells), (long long)ncells);
+  return BCS_OK;
+}
+
+// A device workspace owned by the autotuners (they may allocate).
+struct OwnedWorkspace {
+  void* ptr = nullptr;
+  ~OwnedWorkspace() {
+    if (ptr) (void)hipFree(ptr);
+  }
+  int alloc(size_t bytes) {
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+      ptr = nullptr;
+      return fail(BCS_ERR_HIP, "autotune: workspace allocation of %zu bytes failed", bytes);
+    }
+    return BCS_OK;
+  }
+};
 
 int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
   const int64_t cells_per_wg = (int64_t)bcs::kWavesPerWg * (64 / K.lanes);
@@ -590,8 +603,9 @@ int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
   return (int)std::max<int64_t>(1, std::min(need, cap));
 }
 
-// Fill the launch-specific fields and launch kernel K (forward or adjoint).
-int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, unsigned long long* queue, hipStream_t stream) {
+// Fill the launch-specific fields and launch kernel K (forward or adjoint);
+// P.queue / P.order come from the prologue.
+int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, hipStream_t stream) {
   P.sched = K.d;
   P.adjoint = K.adjoint;
   const WgLayout& L = K.layout;
@@ -602,17 +616,16 @@ int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, unsigned long lon
   P.wbs = L.wbs;
   P.yoff = L.yoff;
   P.tbase = L.tbase;
-  P.queue = queue;
   const int grid = grid_for(p, K, P.ncells);
-  P.total_waves = grid * bcs::kWavesPerWg;
   const hipError_t e = K.launch(P, grid, stream);
   if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve launch: %s", hipGetErrorString(e));
   return BCS_OK;
 }
 
-// Time one launch of kernel K (forward) on a batch already on the device:
-// a warm-up launch, then the best of `reps` timed launches.
-int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P, int reps, double* seconds) {
+// Time one solve (prologue and launch) with kernel K (forward) on a batch
+// already on the device, with workspace ws: a warm-up solve, then the best of
+// `reps` timed solves.
+int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P0, void* ws, int reps, double* seconds) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -622,7 +635,9 @@ int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P, int
   int rc = BCS_OK;
   for (int rep = 0; rep <= reps && rc == BCS_OK; ++rep) {
     (void)hipEventRecord(e0, nullptr);
-    rc = launch(p, K, P, p->queue, nullptr);
+    bcs::KParams P = P0;
+    rc = prologue(p, &P, ws, nullptr);
+    if (rc == BCS_OK) rc = launch(p, K, P, nullptr);
     (void)hipEventRecord(e1, nullptr);
     if (rc != BCS_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -696,8 +711,11 @@ int time_kernel_synthetic(const bcs_plan* p, const Kernel& K, double* seconds) {
   P.iters = di;
   P.resid = dr;
   P.status = ds;
-  P.grad_a = nullptr;
-  const int rc = time_launches(p, K, P, 2, seconds);
+  P.grad_vals = nullptr;
+  P.x0 = nullptr;
+  OwnedWorkspace ws;
+  int rc = ws.alloc(ws_bytes(C));
+  if (rc == BCS_OK) rc = time_launches(p, K, P, ws.ptr, 2, seconds);
   cleanup();
   return rc;
 }
@@ -723,6 +741,7 @@ void bcs_options_default(bcs_options* o) {
   o->autotune = 1;
   o->cell_order = 1;
   o->shared_scalars = 0;
+  o->refine_budget = BCS_BUDGET_INNER;
 }
 
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -756,7 +775,9 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (o.shared_scalars != 0 && o.shared_scalars != 1) return fail(BCS_ERR_ARG, "shared_scalars must be 0 or 1");
   if (o.shared_scalars == 1 && (o.precision != BCS_FP64 || o.jit != 1 || o.lanes_per_cell == 0))
     return fail(BCS_ERR_ARG, "shared_scalars needs FP64, jit = 1 and lanes_per_cell 16, 32 or 64");
-  for (int i = 0; i < 3; ++i)
+  if (o.refine_budget != BCS_BUDGET_INNER && o.refine_budget != BCS_BUDGET_CELL)
+    return fail(BCS_ERR_ARG, "refine_budget must be BCS_BUDGET_INNER or BCS_BUDGET_CELL");
+  for (int i = 0; i < 2; ++i)
     if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
   const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI ||
@@ -796,8 +817,6 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     e = hipMemcpy(p->coo_row, crow.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemcpy(p->coo_col, ccol.data(), sizeof(int16_t) * nnz, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->queue, 2 * bcs::kQueueWords * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMemset(p->queue, 0, 2 * bcs::kQueueWords * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     release(p);
@@ -894,6 +913,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
+  P.x0 = nullptr;
   std::vector<int> pos(p->nnz);
   for (int k = 0; k < p->nnz; ++k) pos[k] = k;
   const bool jit = p->opt.jit == 1;
@@ -901,7 +921,10 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);
   int best_lanes = p->fwd.lanes;
   double best = 1e300;
-  int rc = time_launches(p, p->fwd, P, 2, &best);
+  OwnedWorkspace ws;
+  int rc = ws.alloc(ws_bytes(ncells));
+  if (rc != BCS_OK) return rc;
+  rc = time_launches(p, p->fwd, P, ws.ptr, 2, &best);
   if (rc != BCS_OK) return rc;
   if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
   const int cand[3] = {16, 32, 64};
@@ -913,7 +936,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) return r;
     double t = 0;
-    r = time_launches(p, K, P, 2, &t);
+    r = time_launches(p, K, P, ws.ptr, 2, &t);
     if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", L, t * 1e6);
     if (r != BCS_OK) {
       free_kernel(&K);
@@ -1002,61 +1025,95 @@ static int check_common(const bcs_plan* p, int64_t ncells, const double* values,
   return BCS_OK;
 }
 
+size_t bcs_workspace_bytes(const bcs_plan* p, int64_t ncells) {
+  if (!p || ncells < 0) return 0;
+  return ws_bytes(ncells);
+}
+
 int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
-                    int64_t gamma_stride, const double* b, double rtol, int32_t maxit, double* x, int32_t* iters,
-                    double* resid, int32_t* status, int32_t* refinements, void* stream) {
+                    int64_t gamma_stride, const double* b, const double* x0, double rtol, int32_t maxit, double* x,
+                    int32_t* iters, double* resid, int32_t* status, int32_t* refinements, void* workspace,
+                    size_t workspace_bytes, void* stream) {
   g_err.clear();
   int rc = check_common(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   if (rc != BCS_OK) return rc;
   if (ncells == 0) return BCS_OK;
   if (!b || !x || !iters || !resid || !status) return fail(BCS_ERR_ARG, "b/x/iters/resid/status is NULL");
+  if (x0 && p->opt.shared_scalars == 1)
+    return fail(BCS_ERR_UNSUPPORTED, "shared_scalars plans take no initial guess");
+  rc = check_workspace(p, ncells, workspace, workspace_bytes);
+  if (rc != BCS_OK) return rc;
   bcs::KParams P = base_params(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   P.b = b;
+  P.x0 = x0;
   P.x = x;
   P.iters = iters;
   P.resid = resid;
   P.status = status;
   P.refinements = refinements;
-  rc = cell_order(const_cast<bcs_plan*>(p), 0, &P, (hipStream_t)stream);
+  rc = prologue(p, &P, workspace, (hipStream_t)stream);
   if (rc != BCS_OK) return rc;
-  return launch(p, p->fwd, P, p->queue, (hipStream_t)stream);
+  return launch(p, p->fwd, P, (hipStream_t)stream);
 }
 
 int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
                             int64_t gamma_stride, const double* x, const double* g, double rtol, int32_t maxit,
-                            double* grad_b, double* grad_A, int32_t* iters, double* resid, int32_t* status,
-                            void* stream) {
+                            int32_t grad_kind, double* grad_b, double* grad_vals, double* grad_gamma,
+                            int32_t* iters, double* resid, int32_t* status, void* workspace,
+                            size_t workspace_bytes, void* stream) {
   g_err.clear();
   int rc = check_common(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   if (rc != BCS_OK) return rc;
   if (p->opt.shared_scalars == 1)
     return fail(BCS_ERR_UNSUPPORTED, "the adjoint is not available for shared_scalars plans");
+  if (grad_kind != BCS_GRAD_A && grad_kind != BCS_GRAD_VALUES)
+    return fail(BCS_ERR_ARG, "grad_kind must be BCS_GRAD_A or BCS_GRAD_VALUES");
+  if (grad_gamma && p->opt.matrix_kind != BCS_J_GAMMA)
+    return fail(BCS_ERR_ARG, "grad_gamma needs a BCS_J_GAMMA plan");
   if (ncells == 0) return BCS_OK;
-  if (!x || !g || !grad_b || !grad_A || !iters || !resid || !status)
-    return fail(BCS_ERR_ARG, "x/g/grad_b/grad_A/iters/resid/status is NULL");
+  if (!x || !g || !grad_b || !grad_vals || !iters || !resid || !status)
+    return fail(BCS_ERR_ARG, "x/g/grad_b/grad_vals/iters/resid/status is NULL");
+  rc = check_workspace(p, ncells, workspace, workspace_bytes);
+  if (rc != BCS_OK) return rc;
   bcs::KParams P = base_params(p, ncells, values, gamma, gamma_stride, rtol, maxit);
   P.b = g;
+  P.x0 = nullptr;
   P.xin = x;
   P.x = grad_b;
-  P.grad_a = grad_A;
+  P.grad_kind = grad_kind == BCS_GRAD_VALUES ? 1 : 0;
+  P.grad_vals = grad_vals;
+  P.grad_gamma = grad_gamma;
   P.iters = iters;
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
-  rc = cell_order(const_cast<bcs_plan*>(p), 1, &P, (hipStream_t)stream);
+  rc = prologue(p, &P, workspace, (hipStream_t)stream);
   if (rc != BCS_OK) return rc;
-  return launch(p, p->adj, P, p->queue + bcs::kQueueWords, (hipStream_t)stream);
+  return launch(p, p->adj, P, (hipStream_t)stream);
+}
+
+size_t bcs_multi_workspace_bytes(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells) {
+  if (nmech < 1 || nmech > bcs::kMaxMech || !plans || !ncells) return 0;
+  size_t total = 0;
+  for (int m = 0; m < nmech; ++m) {
+    if (!plans[m] || ncells[m] < 0) return 0;
+    total += ws_bytes(ncells[m]);
+  }
+  return total;
 }
 
 int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* ncells,
                     const double* const* values, const double* const* gamma, const int64_t* gamma_stride,
                     const double* const* b, double rtol, int32_t maxit, double* const* x, int32_t* const* iters,
-                    double* const* resid, int32_t* const* status, void* stream) {
+                    double* const* resid, int32_t* const* status, void* workspace, size_t workspace_bytes,
+                    void* stream) {
   g_err.clear();
   if (nmech < 1 || nmech > bcs::kMaxMech) return fail(BCS_ERR_ARG, "nmech must be in [1, %d]", bcs::kMaxMech);
   if (!plans || !ncells || !values || !gamma || !gamma_stride || !b || !x || !iters || !resid || !status)
     return fail(BCS_ERR_ARG, "an array argument is NULL");
   std::vector<int> order;
+  std::vector<size_t> ws_off(nmech, 0);  // each mechanism's part of the workspace, in argument order
+  size_t ws_need = 0;
   for (int m = 0; m < nmech; ++m) {
     const bcs_plan* p = plans[m];
     int rc = check_common(p, ncells[m], values[m], gamma[m], gamma_stride[m], rtol, maxit);
@@ -1066,12 +1123,18 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var || p->opt.shared_scalars == 1)
       return fail(BCS_ERR_UNSUPPORTED,
                   "bcs_solve_multi needs FP64 plans created with jit = 1 and shared_scalars = 0 (mechanism %d)", m);
+    ws_off[m] = ws_need;
+    ws_need += ws_bytes(ncells[m]);
     if (ncells[m] == 0) continue;
     if (!b[m] || !x[m] || !iters[m] || !resid[m] || !status[m])
       return fail(BCS_ERR_ARG, "b/x/iters/resid/status of mechanism %d is NULL", m);
     order.push_back(m);
   }
   if (order.empty()) return BCS_OK;
+  if (!workspace) return fail(BCS_ERR_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0) return fail(BCS_ERR_ARG, "workspace must be 256-byte aligned");
+  if (workspace_bytes < ws_need)
+    return fail(BCS_ERR_ARG, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, ws_need);
   // heaviest cells first: their slots take longest, the light cells fill the tail
   std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
     return (int64_t)plans[u]->fwd.ksteps * plans[u]->fwd.lanes > (int64_t)plans[v]->fwd.ksteps * plans[v]->fwd.lanes;
@@ -1100,10 +1163,15 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     M.ent_off[q] = (int32_t)off;
     off += table_doubles(plans[order[q]]->n, K.lanes, K.ksteps);
   }
+  // The gathers' 16-bit LDS addresses reach only the first 64 KiB: the
+  // operand blocks must end below it, and the whole layout must fit the
+  // device's LDS per workgroup.  Checked before anything is compiled.
   const size_t lds = off * 8;
   if ((size_t)operand * 8 > 65536 || lds > device_max_lds())
-    return fail(BCS_ERR_UNSUPPORTED, "the mechanisms need %zu bytes of LDS per workgroup (device limit %zu)", lds,
-                device_max_lds());
+    return fail(BCS_ERR_UNSUPPORTED,
+                "the mechanisms need %zu bytes of LDS per workgroup (%zu of them gathered operands), above the "
+                "limit of %zu (operands: 65536)",
+                lds, (size_t)operand * 8, device_max_lds());
   std::vector<int> lanes(nm), rpl(nm), flags(nm);
   std::vector<const int*> segs(nm);
   for (int q = 0; q < nm; ++q) {
@@ -1138,16 +1206,14 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.wbs = lay[q].wbs;
     P.yoff = lay[q].yoff;
     P.tbase = M.ent_off[q];
-    P.queue = p->queue;
-    rc = cell_order(const_cast<bcs_plan*>(p), 0, &P, (hipStream_t)stream);  // each mechanism in its cost order
+    P.x0 = nullptr;
+    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream);  // each mechanism in its cost order
     if (rc != BCS_OK) return rc;
     M.m[q] = P;
     const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
     need += (ncells[m] + cpw - 1) / cpw;
   }
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)jk.max_blocks * plans[order[0]]->num_cu));
-  M.total_waves = grid * bcs::kWavesPerWg;
-  for (int q = 0; q < nm; ++q) M.m[q].total_waves = M.total_waves;
   void* args[] = {&M};
   const hipError_t e = hipModuleLaunchKernel(jk.fn, grid, 1, 1, bcs::kWgThreads, 1, 1, (unsigned)lds,
                                              (hipStream_t)stream, args, nullptr);
@@ -1171,17 +1237,29 @@ int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* nce
     return fail(BCS_ERR_HIP, "multi autotune: event creation failed");
   }
   const bcs_plan* const* cplans = plans;
+  OwnedWorkspace ws;
+  const size_t ws_need = bcs_multi_workspace_bytes(nmech, cplans, ncells);
+  if (ws_need == 0) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return fail(BCS_ERR_ARG, "bad cell counts");
+  }
+  if (ws.alloc(ws_need) != BCS_OK) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return BCS_ERR_HIP;
+  }
   // one combined launch as the plans stand: a warm-up (which also compiles the
   // combination), then the best of two timed launches
   auto time_multi = [&](double* secs) -> int {
     int rc = bcs_solve_multi(nmech, cplans, ncells, values, gamma, gamma_stride, b, rtol, maxit, x, iters, resid,
-                             status, nullptr);
+                             status, ws.ptr, ws_need, nullptr);
     if (rc != BCS_OK) return rc;
     double best = 1e300;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, nullptr);
       rc = bcs_solve_multi(nmech, cplans, ncells, values, gamma, gamma_stride, b, rtol, maxit, x, iters, resid,
-                           status, nullptr);
+                           status, ws.ptr, ws_need, nullptr);
       if (rc != BCS_OK) return rc;
       (void)hipEventRecord(e1, nullptr);
       if (hipEventSynchronize(e1) != hipSuccess) return fail(BCS_ERR_HIP, "multi autotune: synchronisation failed");

@@ -238,19 +238,6 @@ __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int3
   return true;
 }
 
-// Called once per wave when it leaves the solve: the last wave re-arms the
-// queue for the next launch.
-__device__ __forceinline__ void queue_wave_done(unsigned long long* queue, int total_waves) {
-  if ((threadIdx.x & 63) == 0) {
-    const unsigned long long done = atomicAdd(queue + kQueueDone, 1ull);
-    if (done == (unsigned long long)(total_waves - 1)) {
-      atomicExch(queue, 0ull);
-      atomicExch(queue + kQueueDone, 0ull);
-    }
-  }
-}
-
-
 // Schedule policies.  Both run out = M * in for the cell's matrix held as
 // schedule values a[] (this lane's KMAX steps) and packed LDS byte addresses
 // ad[] (absolute LDS byte addresses, one or two 16-bit addresses per word).

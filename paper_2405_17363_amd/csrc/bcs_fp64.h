@@ -16,9 +16,11 @@
 // of the iteration carries only (rhat, r)).  Then the true residual
 // ||b - A x|| confirms convergence; a cell whose true residual misses rtol
 // restarts from it (residual replacement) while iterations remain, and an
-// exact breakdown restarts a bounded number of times.  The adjoint mode runs
-// the same loop on A^T (a transposed schedule over the same per-cell values)
-// with g as right-hand side and then writes dL/dA_ij = -lambda_i x_j.
+// exact breakdown restarts a bounded number of times.  With an initial guess
+// x0 the loop solves for the correction x - x0.  The adjoint mode runs the
+// same loop on A^T (a transposed schedule over the same per-cell values) with
+// g as right-hand side and then writes dL/dA_ij = -lambda_i x_j (or its chain
+// rule to J and gamma for A = I - gamma J).
 #pragma once
 
 #include "bcs_device.h"
@@ -88,6 +90,8 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   double span = 0;
   if constexpr (S::FLAGS & kSchedSpan) span = (P.sched.row[LANES + gl] == kRowSpan) ? 1.0 : 0.0;
   double bn = 0, tol2 = 0, rho = 0, rho_prev = 1, alpha = 1, omega = 1;
+  double gam = 0;     // the cell's gamma (adjoint chain rule)
+  bool warm = false;  // the cell starts from the caller's x0
   int it = 0, restarts_left = 0;
   bool active = false, dead = false;
   int64_t cell = 0;
@@ -107,14 +111,33 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
       for (int j = 0; j < RPL; ++j) xv[j] = dinv[j] * xv[j];
     }
+    if (warm) {
+      const double* x0c = P.x0 + cell * n;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j)
+        if (rows[j] < n) xv[j] = x0c[rows[j]] + xv[j];
+    }
     if (adjoint) {
+      // lambda through the slot's LDS block, so every lane reaches every row
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
         xb[rows[j]] = xv[j];
       }
       wave_sync();
-      for (int k = gl; k < nnz; k += LANES)
-        P.grad_a[cell * nnz + k] = -xb[P.coo_row[k]] * P.xin[cell * n + P.coo_col[k]];
+      // entry k = (i, j): lambda_i x_j; dL/dA_k = -lambda_i x_j, and in J mode
+      // dL/dJ_k = gamma lambda_i x_j and dL/dgamma = sum_k J_k lambda_i x_j
+      const bool to_j = P.grad_kind == 1 && P.kind == kJGamma;
+      const double* vals = P.values + cell * nnz;
+      double gpart = 0;
+      for (int k = gl; k < nnz; k += LANES) {
+        const double lx = xb[P.coo_row[k]] * P.xin[cell * n + P.coo_col[k]];
+        P.grad_vals[cell * nnz + k] = to_j ? gam * lx : -lx;
+        if (P.grad_gamma) gpart = __builtin_fma(vals[k], lx, gpart);
+      }
+      if (P.grad_gamma) {
+        const double tot = gsum<LANES>(gpart);
+        if (gl == 0) P.grad_gamma[cell] = tot;
+      }
       wave_sync();
     }
 #pragma unroll
@@ -164,6 +187,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         // they all issue back to back (one memory latency per refill).
         const double* vals = P.values + cell * nnz;
         const double g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
+        gam = g;
 #pragma unroll
         for (int s = 0; s < KMAX; ++s) a[s] = vals[ent_lds[s * LANES + gl] & kEntPosMask];
         const double* bc = P.b + cell * n;
@@ -198,6 +222,20 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
             dgv[j] = (rows[j] < n) ? d : 0.0;
           }
         }
+        // Initial guess x0: the iteration runs on the correction e = x - x0,
+        // A e = r0 = b - A x0 from e = 0, with r0 in place of b in the
+        // true-residual checks (relative residuals stay relative to ||b||).
+        // r0 is formed here with the unscaled matrix and kept in t.
+        const bool use_x0 = !GRP && P.x0 != nullptr;
+        if (use_x0) {
+          const double* x0c = P.x0 + cell * n;
+          double x0v[RPL];
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) x0v[j] = (rows[j] < n) ? x0c[rows[j]] : 0.0;
+          sch.spmv(a, ad, xb, yb, gl, rows, x0v, t, dgv, span);
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
+        }
         if (P.precond) {
           // column scaling by diag(A)^-1, gathered through the LDS slice
 #pragma unroll
@@ -229,15 +267,24 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         }
         bn = __builtin_sqrt(bn2);
         tol2 = (P.rtol * bn) * (P.rtol * bn);
+        double rr2 = bn2;  // ||r0||^2
+        warm = use_x0 && finite(bn) && bn != 0.0;
+        if (warm) {
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) bb[j] = r[j] = t[j];
+          rr2 = gsum<LANES>(ldot<RPL>(r, r));
+        }
         it = 0;
         restarts_left = P.brs;
         restart();
-        rho = bn2;  // (rhat, r) with rhat = r = b
+        rho = rr2;  // (rhat, r) with rhat = r = r0
         active = true;
         if (!finite(bn)) {
           finish(kNonfinite, __builtin_nan(""));
         } else if (bn == 0.0) {
           finish(kConverged, 0.0);
+        } else if (rr2 <= tol2) {
+          finish(kConverged, __builtin_sqrt(rr2) / bn);  // the initial guess already meets rtol
         }
       }
     }
@@ -361,7 +408,6 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   fp64_run<S, ADJ, GRP>(P, lds, wv, ent_lds, diag_lds);
-  dev::queue_wave_done(P.queue, P.total_waves);
 }
 
 // Several mechanisms in one persistent launch.  Every wave drains the
@@ -392,16 +438,6 @@ __device__ __forceinline__ void multi_body(const MultiParams& M) {
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   multi_run<0, Ss...>(M, lds, wv);
-  // The last wave re-arms every mechanism's queue (mechanism 0's counts the
-  // finished waves).
-  if ((threadIdx.x & 63) == 0) {
-    const unsigned long long done = atomicAdd(M.m[0].queue + kQueueDone, 1ull);
-    if (done == (unsigned long long)(M.total_waves - 1)) {
-#pragma unroll
-      for (int m = 0; m < NM; ++m) atomicExch(M.m[m].queue, 0ull);
-      atomicExch(M.m[0].queue + kQueueDone, 0ull);
-    }
-  }
 }
 
 // Precompiled generic variant (segment boundaries read at run time).

@@ -45,11 +45,12 @@ struct JitKernel {
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
                int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
 
-// Cost order of the cells (bcs_order.hip): fills order[0, ncells) with the
-// cell indices sorted by a bucket of gamma[c * stride], largest first, on
-// `stream`.  state: kOrderStateWords words of device scratch.
-hipError_t launch_cell_order(const double* gamma, int64_t stride, int64_t ncells, uint32_t* state, int32_t* order,
-                             hipStream_t stream);
+// Prologue of every solve (bcs_order.hip), on `stream`: zero the work queue
+// (kQueueWords words) and, when `order` is not null, fill order[0, ncells)
+// with the cell indices sorted by a bucket of gamma[c * stride], largest
+// first (state: kOrderStateWords words of scratch).
+hipError_t launch_solve_prologue(unsigned long long* queue, const double* gamma, int64_t stride, int64_t ncells,
+                                 uint32_t* state, int32_t* order, hipStream_t stream);
 
 // The multi-mechanism kernel for mechanisms with the given layouts, in order.
 int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,

@@ -40,10 +40,13 @@ constexpr int32_t kEntPosMask = kEntPad - 1;
 // choice.  Rows are dealt to (slot j, lane l) in the order of decreasing row
 // length (a sliced-ELL layout with slice height = lanes per cell), so every
 // slot j spans the same steps [seg_begin_j, seg_end_j) on every lane.
-// Work queue of one solve: word 0 hands out cell indices, word 1 counts
-// finished waves; kQueueWords words are reserved per queue.
-constexpr int kQueueDone = 1;
-constexpr int kQueueWords = 16;
+// Workspace of one solve (caller-owned device memory, 256-byte aligned):
+// the work queue (word 0 hands out cell indices; kWsQueueBytes reserved),
+// then the cost-order sort state (kOrderStateWords words), then the order
+// itself (4 bytes per cell).  A clear kernel on the solve's stream zeroes the
+// queue and the sort state before every solve.
+constexpr int kQueueWords = 32;
+constexpr int kWsQueueBytes = kQueueWords * 8;
 
 // Cost order of the cells: a counting sort of the cells by a bucket of
 // gamma (kOrderBuckets buckets of a quarter octave each, from 2^-16 up;
@@ -53,6 +56,8 @@ constexpr int kQueueWords = 16;
 // even.  The sort state is the bucket counts, then the bucket cursors.
 constexpr int kOrderBuckets = 128;
 constexpr int kOrderStateWords = 2 * kOrderBuckets;
+constexpr int kWsStateOffset = kWsQueueBytes;
+constexpr int kWsOrderOffset = kWsStateOffset + kOrderStateWords * 4;
 
 // Shapes of the specialised kernels' schedules (bits of their FLAGS).
 // kSchedSpan: a lane whose slot-1 row is kRowSpan holds one long row over
@@ -81,6 +86,7 @@ struct KParams {
   const double* gamma;
   int64_t gamma_stride;
   const double* b;
+  const double* x0;    // forward: initial guess [ncells, n], or null for x0 = 0
   const double* xin;   // adjoint: forward solution x
   double rtol;
   int32_t maxit;
@@ -90,8 +96,11 @@ struct KParams {
   int32_t brs;
   double inner_rtol;
   int32_t max_refine;
+  int32_t budget;      // mixed form: 0 = maxit per inner solve, 1 = per cell over its inner solves
+  int32_t grad_kind;   // adjoint: 0 = dL/dA, 1 = dL/d(values) (dL/dJ in J mode)
   double* x;           // solution (adjoint: lambda)
-  double* grad_a;      // adjoint only: dL/dA on the pattern
+  double* grad_vals;   // adjoint only: gradient on the pattern (per grad_kind)
+  double* grad_gamma;  // adjoint only, J mode: dL/dgamma per cell, or null
   int32_t* iters;
   double* resid;
   int32_t* status;
@@ -101,9 +110,8 @@ struct KParams {
   const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
   const int16_t* coo_col;   // [nnz] column of each CSR position
   int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
-  unsigned long long* queue;  // kQueueWords words: claim counter, then finished waves
+  unsigned long long* queue;  // claim counter (workspace word 0), zeroed before the launch
   const int32_t* order;       // cells in decreasing cost order, or null for index order
-  int32_t total_waves;
   // Workgroup LDS, in doubles: the operand block of slot g of wave w at
   // w * wxs + g * xs (the only region gathers address, kept below 64 KiB
   // for 16-bit addresses), its state block at bbase + w * wbs + g * bs, then
@@ -120,7 +128,6 @@ struct KParams {
 constexpr int kMaxMech = 8;
 struct MultiParams {
   int32_t nmech;
-  int32_t total_waves;
   int32_t ent_off[kMaxMech];    // LDS offset (doubles) of each mechanism's schedule copy
   KParams m[kMaxMech];          // per-mechanism solve arguments (queue[0] = its work queue)
 };

@@ -4,11 +4,14 @@
 //
 // Per cell (D = diag(A)):
 //   Ahat = A D^-1 is formed in FP64 and held in VGPRs in FP32;
-//   x = 0, r = b (FP64);
+//   x = x0 (or 0), r = b - A x (FP64);
 //   repeat while ||r||/||b|| > rtol, fewer than max_refine inner solves ran
-//   and fewer than maxit inner iterations (over all inner solves) were spent:
-//     solve Ahat d = float(r / ||r||) by FP32 BiCGStab to inner_rtol (x0 = 0;
-//     an exact breakdown restarts once from the FP32 true residual);
+//   and (budget per cell) fewer than maxit inner iterations over all inner
+//   solves were spent:
+//     solve Ahat d = float(r / ||r||) by FP32 BiCGStab to inner_rtol, within
+//     maxit iterations (budget per inner solve) or the cell's remaining
+//     budget (d0 = 0; an exact breakdown restarts once from the FP32 true
+//     residual);
 //     x_new = x + ||r|| D^-1 d (FP64); r_new = b - A x_new (FP64, with A
 //     streamed again from memory, so the FP64 matrix never occupies VGPRs);
 //     stop without accepting x_new if ||r_new|| >= ||r|| (stagnation).
@@ -166,6 +169,14 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         wave_sync();
         bn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r64, r64)));
         rn = bn;
+        if (P.x0 != nullptr && finite(bn) && bn != 0.0) {
+          // initial guess: refinement starts from x0 and r = b - A x0
+          const double* x0c = P.x0 + cell * n;
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) x64[j] = (rows[j] < n) ? x0c[rows[j]] : 0.0;
+          residual64(x64, r64);
+          rn = __builtin_sqrt(gsum<LANES>(ldot<RPL>(r64, r64)));
+        }
         tot = 0;
         nref = 0;
         phase = 0;
@@ -189,7 +200,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         finish(kConverged, rn / bn);
         continue;
       }
-      if (nref >= P.max_refine || tot >= P.maxit) {
+      if (nref >= P.max_refine || (P.budget && tot >= P.maxit)) {
         finish(kMaxit, rn / bn);
         continue;
       }
@@ -265,15 +276,17 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
           }
         }
       }
-      // maxit bounds the cell's inner iterations over all its refinements
-      if (ended < 0 && tot + it_in >= P.maxit) ended = kMaxit;
+      // maxit bounds each inner solve, or (budget) the cell's inner
+      // iterations over all its refinements
+      const int used = P.budget ? tot : 0;
+      if (ended < 0 && used + it_in >= P.maxit) ended = kMaxit;
       if (ended == kNonfinite) {
         tot += it_in;
         ++nref;
         finish(kNonfinite, __builtin_nan(""));
         continue;
       }
-      if (ended == kBreakdown && restarts_left > 0 && tot + it_in < P.maxit) {
+      if (ended == kBreakdown && restarts_left > 0 && used + it_in < P.maxit) {
         // restart from the FP32 true residual of the scaled system
         --restarts_left;
         float ad32[RPL];
@@ -319,8 +332,6 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
       phase = 0;
     }
   }
-
-  dev::queue_wave_done(P.queue, P.total_waves);
 }
 
 }  // namespace bcs

@@ -27,6 +27,7 @@ def test_options_struct_layout_and_defaults():
     assert o.residual_replacement == 1 and o.breakdown_restarts == 1
     assert o.inner_rtol == 1e-4 and o.max_refine == 10
     assert o.jit == 1 and o.autotune == 1 and o.cell_order == 1 and o.shared_scalars == 0
+    assert o.refine_budget == bcs.BCS_BUDGET_INNER
     assert ctypes.sizeof(_Options) == 64
 
 
@@ -62,7 +63,7 @@ def test_invalid_patterns_are_rejected(rp, ci, what):
 @pytest.mark.parametrize("field,value", [("precision", 7), ("precond", 5), ("matrix_kind", 3),
                                           ("lanes_per_cell", 8), ("residual_replacement", 2),
                                           ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3), ("cell_order", 2),
-                                          ("shared_scalars", 2)])
+                                          ("shared_scalars", 2), ("refine_budget", 2)])
 def test_invalid_options_are_rejected(field, value):
     rc, msg, h = _create([0, 1, 2], [0, 1], **{field: value})
     assert rc == -1, msg
@@ -111,5 +112,22 @@ def test_multi_entry_points_reject_bad_counts_and_null_plans(nmech, null_plan):
     assert ("NULL" in msg) if null_plan else ("nmech" in msg)
     if not null_plan:
         rc = L.bcs_solve_multi(nmech, plans, nc, arrs[0], arrs[1], gst, arrs[2], 1e-10, 200, arrs[3], arrs[4],
-                               arrs[5], arrs[6], None)
+                               arrs[5], arrs[6], None, 0, None)
         assert rc == -1 and "nmech" in L.bcs_last_error().decode()
+        assert L.bcs_multi_workspace_bytes(nmech, plans, nc) == 0
+
+
+def test_workspace_size_needs_a_plan_and_a_cell_count():
+    L = bcs.lib()
+    assert L.bcs_workspace_bytes(None, 10) == 0
+    assert L.bcs_workspace_bytes(None, -1) == 0
+
+
+def test_solve_entry_points_reject_a_null_plan_before_any_device_call():
+    L = bcs.lib()
+    rc = L.bcs_solve_batch(None, 1, None, None, 0, None, None, 1e-10, 200, None, None, None, None, None, None, 0,
+                           None)
+    assert rc == -1 and "plan" in L.bcs_last_error().decode()
+    rc = L.bcs_solve_batch_adjoint(None, 1, None, None, 0, None, None, 1e-10, 200, 0, None, None, None, None, None,
+                                   None, None, 0, None)
+    assert rc == -1 and "plan" in L.bcs_last_error().decode()

@@ -1,16 +1,19 @@
 """GPU adjoint: transposed batched BiCGStab and dL/dA, dL/db, dL/dJ, dL/dgamma.
 
-lambda = A^-T g is compared with the oracle's dense LU of A^T within the
-residual-implied bound; dL/dA_ij = -lambda_i x_j is checked exactly from the
-GPU's own lambda and x; duality g.x = lambda.b; central finite differences of
-L = w.x (dense-LU evaluations, relative steps 1e-6 |A_k|, with an error bar
-from a second step of half the size) on 16 sampled cells; and the autograd
-chain rule to J and gamma against the oracle.
+lambda = A^-T g is compared with the oracle's dense LU of A^T on every cell
+within the residual-implied bound; dL/dA_ij = -lambda_i x_j and dL/dJ_ij =
+gamma lambda_i x_j are checked exactly from the GPU's own lambda and x, and
+dL/dgamma within the rounding of its sum; duality g.x = lambda.b;
+homogeneity; central finite differences of L = w.x (dense-LU evaluations,
+relative steps 1e-6 |A_k|, with an error bar from a second step of half the
+size) on 16 sampled cells; and the autograd chain rule to J and gamma against
+the oracle.
 """
 import numpy as np
 import pytest
 
 import oracle
+from parity import iters_close, lu_check, perturb_ulp
 from workload import config_inputs
 
 torch = pytest.importorskip("torch")
@@ -34,43 +37,47 @@ def cfg5():
     plan = bcs.Plan(mech.row_ptr, mech.col_idx)
     V, G, B, W = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"]), gpu(cells["w"])
     x, it, res, st, _ = bcs.solve_batch(plan, V, G, B, RTOL, 200)
-    gb, gA, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, W, RTOL, 200)
+    gb, gA, _, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, W, RTOL, 200)
+    gb2, gJ, gG, _, _, _ = bcs.solve_batch_adjoint(plan, V, G, x, W, RTOL, 200, grad_kind="values", grad_gamma=True)
     torch.cuda.synchronize()
     out = dict(x=x.cpu().numpy(), st=st.cpu().numpy(), gb=gb.cpu().numpy(), gA=gA.cpu().numpy(),
-               ait=ait.cpu().numpy(), ares=ares.cpu().numpy(), ast=ast.cpu().numpy())
+               ait=ait.cpu().numpy(), ares=ares.cpu().numpy(), ast=ast.cpu().numpy(), gb2=gb2.cpu().numpy(),
+               gJ=gJ.cpu().numpy(), gG=gG.cpu().numpy())
     return mech, cells, plan, out
 
 
 def test_adjoint_lambda_matches_transposed_lu(cfg5):
+    """lambda against the dense LU of A^T on every cell of config 5 (same bound as the forward solve)."""
     mech, cells, plan, o = cfg5
     rp, ci = mech.row_ptr, mech.col_idx
     assert np.mean(o["ast"] == bcs.BCS_CONVERGED) >= 0.99
     assert np.all(o["ares"][o["ast"] == 0] <= RTOL)
-    rng = np.random.default_rng(55)
-    sample = np.sort(rng.choice(len(o["st"]), 300, replace=False))
-    lam, info = oracle.lu_batch(rp, ci, cells["values"][sample], cells["gamma"][sample], cells["w"][sample],
-                                transpose=True)
-    for q, c in enumerate(sample):
-        if o["ast"][c] != 0:
-            continue
-        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
-        kappa = np.linalg.cond(A)
-        rlu = np.linalg.norm(cells["w"][c] - A.T @ lam[q]) / np.linalg.norm(cells["w"][c])
-        err = np.linalg.norm(o["gb"][c] - lam[q]) / np.linalg.norm(lam[q])
-        assert err <= max(1e-8, 4 * kappa * max(o["ares"][c], rlu)), (c, err, kappa)
+    out = lu_check(rp, ci, cells["values"], cells["gamma"], cells["w"], o["gb"], o["ares"], o["ast"],
+                   np.arange(len(o["st"])), transpose=True)
+    print("LU check of lambda", out)
+    assert out["checked"] >= 0.99 * len(o["st"])
 
 
 def test_adjoint_matches_oracle_adjoint_statuses(cfg5):
+    """Statuses and iteration counts of the transposed solve against the
+    oracle's, at least as close as the oracle to itself under a one-ulp
+    perturbation of g (less one point).  The adjoint systems (A^T with a random
+    g) are more rounding-sensitive than the forward ones: the oracle agrees
+    with itself on about 94% of the cells' iteration counts within
+    max(3, 15%), so the bar comes from that control, not a fixed 95%."""
     mech, cells, plan, o = cfg5
-    gb, gA, it, res, st = oracle.adjoint_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], o["x"],
-                                               cells["w"], precond=1)
-    assert np.mean(st == o["ast"]) >= 0.99
+    args = (mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], o["x"])
+    gb, gA, it, res, st = oracle.adjoint_batch(*args, cells["w"], precond=1)
+    gbp, gAp, itp, resp, stp = oracle.adjoint_batch(*args, perturb_ulp(cells["w"]), precond=1)
+    bar_status = min(0.99, float(np.mean(stp == st)) - 0.01)
+    bar_close = min(0.95, iters_close(itp, it, stp, st) - 0.01)
+    agree = float(np.mean(st == o["ast"]))
+    close = iters_close(o["ait"], it, o["ast"], st)
+    print(f"adjoint status agreement {agree:.4f} (bar {bar_status:.4f}), iterations close {close:.4f} "
+          f"(bar {bar_close:.4f}; oracle against itself {bar_close + 0.01:.4f})")
+    assert agree >= bar_status
+    assert close >= bar_close
     both = (st == 0) & (o["ast"] == 0)
-    # iteration counts are rounding sensitive (the GPU folds the Jacobi scaling
-    # into the matrix, the oracle applies M^-1 to the vectors): agreement on
-    # 90% of cells and on the mean
-    close = np.abs(it[both] - o["ait"][both]) <= np.maximum(3, 0.15 * it[both])
-    assert np.mean(close) >= 0.90
     assert abs(o["ait"][both].mean() - it[both].mean()) <= 0.05 * it[both].mean()
 
 
@@ -79,6 +86,30 @@ def test_pattern_gradient_is_minus_lambda_x(cfg5):
     rows = np.repeat(np.arange(mech.n), np.diff(mech.row_ptr))
     expect = -o["gb"][:, rows] * o["x"][:, mech.col_idx]
     assert np.array_equal(o["gA"], expect)
+
+
+def test_gradients_with_respect_to_j_and_gamma_from_the_epilogue(cfg5):
+    """grad_kind "values": dL/dJ = gamma lambda_i x_j, written by the adjoint
+    kernel, bitwise from its own lambda and x; dL/dgamma = sum_k J_k lambda_i
+    x_j per cell, within the rounding of the sum; lambda the same in both
+    calls."""
+    mech, cells, plan, o = cfg5
+    rows = np.repeat(np.arange(mech.n), np.diff(mech.row_ptr))
+    assert np.array_equal(o["gb2"], o["gb"])
+    lx = o["gb"][:, rows] * o["x"][:, mech.col_idx]
+    assert np.array_equal(o["gJ"], cells["gamma"][:, None] * lx)
+    terms = cells["values"] * lx
+    expect = terms.sum(axis=1)
+    scale = np.abs(terms).sum(axis=1)
+    assert np.all(np.abs(o["gG"] - expect) <= 64 * np.finfo(float).eps * scale + 1e-300)
+    # homogeneity: sum_k A_k dL/dA_k = -g^T x (L is of degree -1 in A)
+    A = np.stack([oracle.form_a(mech.row_ptr, mech.col_idx, cells["values"][c], cells["gamma"][c])
+                  for c in range(0, 10_000, 97)])
+    ok = ((o["st"] == 0) & (o["ast"] == 0))[::97]
+    lhs = np.sum(A * o["gA"][::97], axis=1)
+    rhs = -np.sum(cells["w"][::97] * o["x"][::97], axis=1)
+    mag = np.sum(np.abs(A * o["gA"][::97]), axis=1)
+    assert np.all(np.abs(lhs - rhs)[ok] <= 1e-8 * mag[ok])
 
 
 def test_duality(cfg5):
@@ -146,13 +177,15 @@ def test_autograd_chain_rule_to_J_gamma_b():
     G = gpu(cells["gamma"]).requires_grad_(True)
     B = gpu(cells["b"]).requires_grad_(True)
     W = gpu(cells["w"])
-    x = bcs.BatchedSolve.apply(V, G, B, plan)
+    x, status = bcs.BatchedSolve.apply(V, G, B, plan)
+    assert not status.requires_grad and status.dtype == torch.int32
     loss = (W * x).sum()
     loss.backward()
     torch.cuda.synchronize()
     xn = x.detach().cpu().numpy()
     gb_o, gA_o, it, res, st = oracle.adjoint_batch(mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"],
                                                    xn, cells["w"], precond=1)
+    assert np.mean(status.cpu().numpy() == 0) >= 0.99
     ok = st == 0
     gJ = V.grad.cpu().numpy()
     gG = G.grad.cpu().numpy()
@@ -168,6 +201,45 @@ def test_autograd_chain_rule_to_J_gamma_b():
         assert abs(gG[c] - expect_G[c]) <= 1e-6 * gscale + 1e-12
 
 
+def test_autograd_with_non_contiguous_values_and_scalar_gamma():
+    """A non-contiguous values tensor works in forward and backward (the
+    contiguous copy is what backward reuses); a scalar gamma tensor gets the
+    sum of the per-cell gamma gradients."""
+    mech, cells = config_inputs(5, ncells=300)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    Vt = gpu(np.ascontiguousarray(cells["values"].T)).t().requires_grad_(True)  # [C, nnz] view, not contiguous
+    assert not Vt.is_contiguous()
+    g0 = 0.37
+    G = torch.tensor([g0], dtype=torch.float64, device="cuda", requires_grad=True)
+    B = gpu(cells["b"]).requires_grad_(True)
+    W = gpu(cells["w"])
+    x, status = bcs.BatchedSolve.apply(Vt, G, B, plan)
+    (W * x).sum().backward()
+    torch.cuda.synchronize()
+    xn = x.detach().cpu().numpy()
+    gb_o, gA_o, _, _, st = oracle.adjoint_batch(mech.row_ptr, mech.col_idx, cells["values"], [g0], xn, cells["w"],
+                                                precond=1)
+    ok = (st == 0) & (status.cpu().numpy() == 0)
+    assert ok.mean() >= 0.95
+    expect_J = -g0 * gA_o
+    gJ = Vt.grad.cpu().numpy()
+    for c in np.nonzero(ok)[0][:100]:
+        assert np.allclose(gJ[c], expect_J[c], rtol=1e-6, atol=1e-9 * np.abs(expect_J[c]).max())
+    per_cell = -np.sum(cells["values"] * gA_o, axis=1)
+    scale = np.sum(np.abs(cells["values"] * gA_o))
+    assert abs(G.grad.item() - per_cell.sum()) <= 1e-6 * scale
+
+
+def test_unconverged_adjoint_cells_are_reported():
+    mech, cells = config_inputs(5, ncells=200)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx)
+    V = gpu(cells["values"]).requires_grad_(True)
+    x, status = bcs.BatchedSolve.apply(V, gpu(cells["gamma"]), gpu(cells["b"]), plan, 1e-10, 3)
+    assert (status != 0).any()
+    with pytest.warns(bcs.BatchedSolveWarning, match="did not converge"):
+        (gpu(cells["w"]) * x).sum().backward()
+
+
 def test_data_autotune_keeps_results_valid():
     mech, cells = config_inputs(2, ncells=6000)[0]
     plan = bcs.Plan(mech.row_ptr, mech.col_idx)
@@ -181,6 +253,6 @@ def test_data_autotune_keeps_results_valid():
                                             cells["b"], precond=1)
     assert np.mean(st == sto) >= 0.99
     # the adjoint kernel follows the tuned layout and still works
-    gb, gA, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, B)
+    gb, gA, _, ait, ares, ast = bcs.solve_batch_adjoint(plan, V, G, x, B)
     torch.cuda.synchronize()
     assert np.mean(ast.cpu().numpy() == 0) >= 0.99

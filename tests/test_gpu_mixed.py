@@ -1,16 +1,20 @@
 """GPU mixed precision (FP32 inner BiCGStab, FP64 residual and refinement)
 against the oracle's FP32/FP64 emulation and dense LU.
 
-Bound for the final x: the same residual-implied bound as FP64,
-max(1e-8, 4 kappa_2 max(resid, rho_LU)), with resid <= rtol required for
-converged cells.  Statuses agree with the oracle's emulation on >= 95% of
-cells (refinement in FP32 is sensitive to rounding order near kappa u32 ~ 1);
-refinement counts agree within one on >= 90%.
+Bound for the final x: the same residual-implied bound as FP64
+(tests/parity.py), with resid <= rtol required for converged cells.
+Statuses agree with the oracle's emulation at least as well as the emulation
+agrees with itself when b is perturbed by one ulp per entry, less one point
+(refinement in FP32 is sensitive to rounding near kappa u32 ~ 1); refinement
+counts agree within one on >= 95% of the cells both solve.  Both readings of
+the iteration budget are checked: maxit per inner solve (the default) and per
+cell over its inner solves.
 """
 import numpy as np
 import pytest
 
 import oracle
+from parity import lu_check, perturb_ulp
 from workload import config_inputs
 
 torch = pytest.importorskip("torch")
@@ -28,38 +32,78 @@ def gpu(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def run_mixed(plan, cells):
-    x, it, res, st, ref = bcs.solve_batch(plan, gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"]), RTOL,
-                                          200)
+def run_mixed(plan, cells, x0=None, tune=False):
+    V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
+    if tune:
+        plan.autotune(V, G, B, RTOL, 200)
+    x, it, res, st, ref = bcs.solve_batch(plan, V, G, B, RTOL, 200, x0=None if x0 is None else gpu(x0))
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in (x, it, res, st, ref)]
 
 
-@pytest.mark.parametrize("cfg,nc", [(1, None), (2, 4000), (3, 4000)])
-def test_mixed_matches_emulation_and_lu(cfg, nc):
-    mech, cells = config_inputs(cfg, ncells=nc)[0]
+def check_mixed(mech, cells, out, budget, lu_sample, x0=None):
     rp, ci = mech.row_ptr, mech.col_idx
-    plan = bcs.Plan(rp, ci, precision="fp32_refine")
-    x, it, res, st, ref = run_mixed(plan, cells)
-    xo, ito, refo, reso, sto = oracle.mixed_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
-    print("gpu status", np.bincount(st, minlength=4), "oracle", np.bincount(sto, minlength=4),
-          "iters", it.mean(), ito.mean(), "refinements", ref.mean(), refo.mean())
-    assert np.mean(st == sto) >= 0.95
+    x, it, res, st, ref = out
+    args = (rp, ci, cells["values"], cells["gamma"])
+    xo, ito, refo, reso, sto = oracle.mixed_batch(*args, cells["b"], budget=budget, x0=x0)
+    _, _, refp, _, stp = oracle.mixed_batch(*args, perturb_ulp(cells["b"]), budget=budget, x0=x0)
+    agree = float(np.mean(st == sto))
+    bar = min(0.99, float(np.mean(stp == sto)) - 0.01)
+    print(f"budget {budget}: gpu status {np.bincount(st, minlength=4)}, oracle {np.bincount(sto, minlength=4)}, "
+          f"agreement {agree:.4f} (bar {bar:.4f}); iters {it.mean():.2f} / {ito.mean():.2f}, refinements "
+          f"{ref.mean():.3f} / {refo.mean():.3f}")
+    assert agree >= bar
     conv = st == bcs.BCS_CONVERGED
     assert np.all(res[conv] <= RTOL)
     both = conv & (sto == 0)
-    assert np.mean(np.abs(ref[both] - refo[both]) <= 1) >= 0.90
-    sample = np.nonzero(conv)[0][:200]
-    xl, _ = oracle.lu_batch(rp, ci, cells["values"][sample], cells["gamma"][sample], cells["b"][sample])
-    for q, c in enumerate(sample):
-        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
-        kappa = np.linalg.cond(A)
-        bn = np.linalg.norm(cells["b"][c])
-        rlu = np.linalg.norm(cells["b"][c] - A @ xl[q]) / bn
-        err = np.linalg.norm(x[c] - xl[q]) / np.linalg.norm(xl[q])
-        assert err <= max(1e-8, 4 * kappa * max(res[c], rlu)), (c, err, kappa)
-        rel = np.linalg.norm(cells["b"][c] - A @ x[c]) / bn
-        assert rel <= RTOL + 64 * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(x[c])) / bn
+    assert np.mean(np.abs(ref[both] - refo[both]) <= 1) >= 0.95
+    out = lu_check(rp, ci, cells["values"], cells["gamma"], cells["b"], x, res, st, lu_sample)
+    print("LU check", out)
+    return out, ref
+
+
+@pytest.mark.parametrize("budget", ["inner", "cell"])
+@pytest.mark.parametrize("cfg,nc", [(1, None), (2, 4000)])
+def test_mixed_matches_emulation_and_lu(cfg, nc, budget):
+    mech, cells = config_inputs(cfg, ncells=nc)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precision="fp32_refine", refine_budget=budget)
+    out = run_mixed(plan, cells)
+    C = len(out[3])
+    check_mixed(mech, cells, out, budget, np.arange(0, C, max(1, C // 300)))
+
+
+@pytest.mark.parametrize("budget", ["inner", "cell"])
+def test_mixed_config3_full_100k_cells(budget):
+    """The mixed form on the benchmark workload at full size (100,000 cells,
+    h up to 100 s), as the benchmark runs it (autotuned on the batch, cost
+    order on, so slots refill many times and the refinement phases restart on
+    new cells): statuses of every cell against the emulation, dense LU on 256
+    sampled converged cells of which at least half needed three or more
+    refinements."""
+    mech, cells = config_inputs(3)[0]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precision="fp32_refine", refine_budget=budget)
+    out = run_mixed(plan, cells, tune=True)
+    x, it, res, st, ref = out
+    rng = np.random.default_rng(8)
+    conv = np.nonzero(st == 0)[0]
+    multi = conv[ref[conv] >= 3]
+    sample = np.unique(np.concatenate([rng.choice(multi, min(128, multi.size), replace=False),
+                                       rng.choice(conv, 128, replace=False)]))
+    assert sample.size >= 250
+    res_lu, _ = check_mixed(mech, cells, out, budget, sample)
+    assert res_lu["checked"] >= 250
+
+
+def test_mixed_warm_start():
+    mech, cells = config_inputs(2, ncells=2000)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    x0 = xl * (1 + 1e-5 * np.random.default_rng(2).standard_normal(xl.shape))
+    plan = bcs.Plan(rp, ci, precision="fp32_refine")
+    out = run_mixed(plan, cells, x0=x0)
+    _, ref = check_mixed(mech, cells, out, "inner", np.arange(0, 2000, 10), x0=x0)
+    cold = run_mixed(plan, cells)
+    assert out[4].mean() < cold[4].mean()
 
 
 def test_mixed_edge_cases():

@@ -486,3 +486,140 @@ def test_mixed_zero_rhs_and_nan():
     x, it, ref, res, st = oracle.mixed_batch(mech.row_ptr, mech.col_idx, vals, cells["gamma"], b)
     assert st[0] == CONVERGED and ref[0] == 0 and np.all(x[0] == 0)
     assert st[2] == NONFINITE
+
+
+# ----------------------------------------------------------- initial guess --
+
+def test_initial_guess_at_the_solution_takes_no_iteration():
+    mech, cells = config_inputs(1, ncells=20)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    x, it, res, st = oracle.solve_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], precond=1, x0=xl)
+    for c in range(20):
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        rlu = np.linalg.norm(cells["b"][c] - A @ xl[c]) / np.linalg.norm(cells["b"][c])
+        if rlu <= 1e-10:  # the LU solution meets rtol: returned as is, no iteration
+            assert st[c] == CONVERGED and it[c] == 0 and np.array_equal(x[c], xl[c])
+            # the same residual, summed in another order
+            slack = 64 * np.finfo(float).eps * np.linalg.norm(np.abs(A) @ np.abs(xl[c])) / np.linalg.norm(cells["b"][c])
+            assert abs(res[c] - rlu) <= slack
+
+
+def test_initial_guess_solves_for_the_correction():
+    """BiCGStab from x0 on A x = b is BiCGStab from 0 on A e = b - A x0 with
+    x = x0 + e (the Krylov space of r0): the same iteration count (rounding
+    may move it by one) and x within the residual-implied bound of the LU
+    solution."""
+    mech, cells = config_inputs(1, ncells=40)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    rng = np.random.default_rng(4)
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    x0 = xl * (1 + 1e-3 * rng.standard_normal(xl.shape))
+    x, it, res, st = oracle.solve_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], precond=1, x0=x0)
+    agree = 0
+    for c in range(40):
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        r0 = cells["b"][c] - A @ x0[c]
+        scale = np.linalg.norm(cells["b"][c]) / np.linalg.norm(r0)
+        e, ite, rese, ste = oracle.solve_batch(rp, ci, cells["values"][c][None], [cells["gamma"][c]], r0[None],
+                                               rtol=1e-10 * scale, precond=1)
+        agree += abs(int(ite[0]) - int(it[c])) <= 1
+        if st[c] == CONVERGED:
+            kappa = np.linalg.cond(A)
+            err = np.linalg.norm(x[c] - xl[c]) / np.linalg.norm(xl[c])
+            assert err <= max(1e-8, 4 * kappa * res[c]), (c, err)
+            assert res[c] <= 1e-10
+    assert agree >= 38
+    # a warm start needs fewer iterations than a cold one on these cells
+    _, it_cold, _, _ = oracle.solve_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], precond=1)
+    assert it.mean() < it_cold.mean()
+
+
+def test_zero_initial_guess_equals_no_initial_guess():
+    mech, cells = config_inputs(1, ncells=15)[0]
+    args = (mech.row_ptr, mech.col_idx, cells["values"], cells["gamma"], cells["b"])
+    a = oracle.solve_batch(*args, precond=1)
+    # x0 = 0 forms r0 = b - A 0 = b exactly
+    b = oracle.solve_batch(*args, precond=1, x0=np.zeros_like(cells["b"]))
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_mixed_initial_guess_at_the_solution_takes_no_refinement():
+    mech, cells = config_inputs(1, ncells=10)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    xl, _ = oracle.lu_batch(rp, ci, cells["values"], cells["gamma"], cells["b"])
+    x, it, ref, res, st = oracle.mixed_batch(rp, ci, cells["values"], cells["gamma"], cells["b"], x0=xl)
+    done = res <= 1e-10
+    assert done.sum() >= 8
+    assert np.all(st[done] == CONVERGED) and np.all(it[done] == 0) and np.all(ref[done] == 0)
+    assert np.array_equal(x[done], xl[done])
+
+
+# ------------------------------------------ the FP32 inner solver on its own --
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fp32_solver_finite_termination(k):
+    """In FP32 too, an SPD matrix with k distinct eigenvalues gives termination
+    within k iterations (the residual polynomial of degree k vanishes on the
+    spectrum); a dropped term or wrong sign in the FP32 recurrences breaks it."""
+    eigs = [1.0, 2.5, 4.0][:k]
+    rng = np.random.default_rng(100 + k)
+    n = 12
+    for trial in range(20):
+        M = _eig_construct(eigs, n, rng, True)
+        rp, ci, vals = dense_to_csr(M)
+        b = rng.standard_normal(n)
+        x, it, res, st = oracle.solve_batch_f(rp, ci, vals[None].astype(np.float32), b[None].astype(np.float32),
+                                              rtol=1e-5, maxit=50)
+        assert st[0] == CONVERGED and it[0] <= k, (k, it[0], res[0])
+        xr = np.linalg.solve(M, b)
+        assert np.linalg.norm(x[0] - xr) <= 1e-4 * np.linalg.norm(xr)
+
+
+def test_fp32_solver_identity_gives_b_exactly_in_one_half_step():
+    """A = I: alpha = (b, b) / (b, I b) is exactly 1 in any precision, s = 0,
+    so x = b in one half step."""
+    n = 30
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    b = np.random.default_rng(8).standard_normal((5, n)).astype(np.float32)
+    x, it, res, st = oracle.solve_batch_f(rp, ci, np.ones((5, n), np.float32), b, rtol=1e-6)
+    assert np.all(st == CONVERGED) and np.all(it == 1) and np.array_equal(x, b)
+
+
+def test_fp32_solver_meets_the_fp32_bound_on_tiny_systems():
+    rng = np.random.default_rng(21)
+    checked = 0
+    for trial in range(400):
+        n = int(rng.integers(1, 9))
+        M = random_sparse(n, 0.5, rng)
+        kappa = np.linalg.cond(M)
+        if kappa > 1e3:
+            continue
+        rp, ci, vals = dense_to_csr(M)
+        M32 = oracle.to_dense(rp, ci, vals.astype(np.float32).astype(np.float64))
+        b = rng.standard_normal(n).astype(np.float32)
+        x, it, res, st = oracle.solve_batch_f(rp, ci, vals[None].astype(np.float32), b[None], rtol=1e-5, maxit=100)
+        if st[0] == BREAKDOWN:
+            continue
+        assert st[0] == CONVERGED and res[0] <= 1e-5
+        xr = np.linalg.solve(M32, b.astype(np.float64))
+        # residual-implied bound plus the FP32 evaluation of the residual
+        assert np.linalg.norm(x[0] - xr) <= 4 * kappa * (1e-5 + 64 * 2.0 ** -24) * np.linalg.norm(xr)
+        checked += 1
+    assert checked > 250
+
+
+def test_mixed_budget_per_cell_never_spends_more_than_maxit():
+    mech, cells = config_inputs(3, ncells=300)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    args = (rp, ci, cells["values"], cells["gamma"], cells["b"])
+    _, it_c, ref_c, res_c, st_c = oracle.mixed_batch(*args, maxit=200, budget="cell")
+    _, it_i, ref_i, res_i, st_i = oracle.mixed_batch(*args, maxit=200, budget="inner")
+    assert it_c.max() <= 200 and it_i.max() <= 200 * 10
+    assert np.all(ref_i <= 10) and np.all(ref_c <= 10)
+    # the per-inner-solve budget never solves fewer cells: every cell the
+    # per-cell budget solves within 200 iterations, it solves the same way
+    assert np.all(st_i[st_c == CONVERGED] == CONVERGED)
+    assert (st_i == CONVERGED).sum() >= (st_c == CONVERGED).sum()
