@@ -8,6 +8,7 @@ ctypes.  It shares no code with the HIP library.
 Functions (all take/return numpy arrays):
   solve_batch   BiCGStab per cell (FP64), optional x0      -> x, iters, resid, status
   solve_batch_f the same BiCGStab in FP32 (mixed form's inner solver)
+  ilu0          ILU(0) factors of one matrix on its pattern; ilu_apply: (LU)^-1 p
   lu_batch      dense LU with partial pivoting per cell   -> x (ground truth)
   adjoint_batch lambda = A^-T g and dL/dA on the pattern   -> grad_b, grad_A, iters, resid, status
   mixed_batch   FP32 inner BiCGStab + FP64 refinement      -> x, iters, refinements, resid, status
@@ -59,7 +60,11 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     _vp = ctypes.c_void_p
     lib.oracle_solve_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _vp, _dbl, _int, _int,
-                                       _int, _int, _D, _I, _D, _I, _int]
+                                       _int, _int, _int, _D, _I, _D, _I, _int]
+    lib.oracle_ilu0.argtypes = [_int, _I, _I, _D, _D]
+    lib.oracle_ilu0.restype = _int
+    lib.oracle_ilu_apply.argtypes = [_int, _I, _I, _D, _int, _D, _D]
+    lib.oracle_ilu_apply.restype = None
     lib.oracle_solve_batch.restype = None
     lib.oracle_lu_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _int, _D, _D, _I, _int]
     lib.oracle_lu_batch.restype = None
@@ -112,8 +117,12 @@ def _x0_arg(x0, C, n):
     return a, a.ctypes.data
 
 
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_ILU0 = 0, 1, 2
+
+
 def solve_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, precond=0, kind=J_GAMMA,
-                residual_replacement=1, breakdown_restarts=1, nthreads=0, x0=None):
+                residual_replacement=1, breakdown_restarts=1, nthreads=0, x0=None, ilu_sweeps=3):
+    """precond 0 none, 1 Jacobi, 2 ILU(0) applied with ilu_sweeps Jacobi sweeps per triangle (0 = exact)."""
     rp, ci, n, nnz, vals, C, g, gs, bb = _prep(row_ptr, col_idx, values, gamma, b)
     x = np.zeros((C, n))
     iters = np.zeros(C, dtype=np.int32)
@@ -121,8 +130,8 @@ def solve_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, preco
     status = np.zeros(C, dtype=np.int32)
     x0a, x0p = _x0_arg(x0, C, n)
     _load().oracle_solve_batch(C, n, nnz, rp, ci, vals, g, gs, kind, bb, x0p, float(rtol), int(maxit), int(precond),
-                               int(residual_replacement), int(breakdown_restarts), x, iters, resid, status,
-                               int(nthreads))
+                               int(ilu_sweeps), int(residual_replacement), int(breakdown_restarts), x, iters, resid,
+                               status, int(nthreads))
     return x, iters, resid, status
 
 
@@ -143,6 +152,29 @@ def solve_batch_f(row_ptr, col_idx, A32, b32, rtol=1e-6, maxit=200, precond=0, r
     _load().oracle_solve_batch_f(C, n, nnz, rp, ci, A, bb, float(rtol), int(maxit), int(precond),
                                  int(residual_replacement), int(breakdown_restarts), x, iters, resid, status)
     return x, iters, resid, status
+
+
+def ilu0(row_ptr, col_idx, A):
+    """ILU(0) factors (L strictly lower with unit diagonal implied, U upper) of one matrix A [nnz] on its
+    pattern; raises if a row has no diagonal entry."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    Av = np.ascontiguousarray(A, dtype=np.float64)
+    F = np.zeros_like(Av)
+    rc = _load().oracle_ilu0(rp.shape[0] - 1, rp, ci, Av, F)
+    if rc:
+        raise ValueError(f"row {rc - 1} has no diagonal entry")
+    return F
+
+
+def ilu_apply(row_ptr, col_idx, F, p, sweeps=3):
+    """(L U)^-1 p with ILU(0) factors F: exact substitution (sweeps = 0) or `sweeps` Jacobi sweeps per triangle."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    out = np.zeros(rp.shape[0] - 1)
+    _load().oracle_ilu_apply(rp.shape[0] - 1, rp, ci, np.ascontiguousarray(F, dtype=np.float64), int(sweeps),
+                             np.ascontiguousarray(p, dtype=np.float64), out)
+    return out
 
 
 def block_pattern(row_ptr, col_idx, copies):

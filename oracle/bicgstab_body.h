@@ -7,7 +7,11 @@
  *
  * Method: BiCGStab of van der Vorst (1992), as given in the BiCGSTAB template
  * of Barrett et al., "Templates for the Solution of Linear Systems" (SIAM
- * 1994), with optional right Jacobi preconditioning M = diag(A).  The paper
+ * 1994), with optional right preconditioning: Jacobi, M = diag(A), or
+ * ILU(0), M = L U with the incomplete factors on A's own pattern (Saad,
+ * Iterative Methods for Sparse Linear Systems, 2nd ed., Algorithm 10.4; the
+ * paper names a preconditioner as the most promising next optimisation,
+ * Section 5.2).  The paper
  * names its linear solver only as the BSC "Biconjugate Gradient" GPU solver
  * (Section 3.1) and prints no algorithm, so the published BiCGStab is
  * followed.  Readings taken where the paper is silent:
@@ -53,11 +57,90 @@ static void FN(spmv_)(int n, const int* rp, const int* ci, const REAL* A, const 
   }
 }
 
-/* Returns the iteration count.  x0 is the initial guess (NULL: zero).  w must
- * hold 10*n elements. */
-static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, const REAL* x0,
-                         double rtol, int maxit, int precond, int rr, int brs, REAL* x, double* resid_out,
-                         int* status_out, REAL* w) {
+/* ILU(0) of A on its own pattern (Saad, Algorithm 10.4, the IKJ variant):
+ * for each row i and each k < i with (i, k) in the pattern, in increasing k:
+ * a_ik <- a_ik / a_kk, then a_ij <- a_ij - a_ik a_kj for every j > k with both
+ * (i, j) and (k, j) in the pattern.  F receives L (strictly lower part, unit
+ * diagonal implied) and U (diagonal and upper part) on the pattern; diag[i]
+ * is the position of (i, i).  Returns 0, or i + 1 if row i has no diagonal
+ * entry.  A zero pivot is not trapped: the division gives an infinity and
+ * the solve reports a non-finite value. */
+static int FN(ilu0_)(int n, const int* rp, const int* ci, const REAL* A, REAL* F, int* diag) {
+  int nnz = rp[n];
+  for (int k = 0; k < nnz; ++k) F[k] = A[k];
+  for (int i = 0; i < n; ++i) {
+    diag[i] = -1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) diag[i] = k;
+    if (diag[i] < 0) return i + 1;
+  }
+  for (int i = 1; i < n; ++i) {
+    for (int pk = rp[i]; pk < rp[i + 1] && ci[pk] < i; ++pk) {
+      int k = ci[pk];
+      F[pk] = F[pk] / F[diag[k]];
+      for (int pj = pk + 1; pj < rp[i + 1]; ++pj) {
+        int j = ci[pj];
+        for (int q = diag[k] + 1; q < rp[k + 1]; ++q)
+          if (ci[q] == j) {
+            F[pj] = F[pj] - F[pk] * F[q];
+            break;
+          }
+      }
+    }
+  }
+  return 0;
+}
+
+/* out = (L U)^-1 p with the ILU(0) factors F.  sweeps = 0: exact forward and
+ * back substitution.  sweeps = s > 0: each triangular system solved by s
+ * Jacobi sweeps from the diagonal solution (L y = p: y <- p, then s times
+ * y <- p - L_strict y; U z = y: z <- D^-1 y, then s times
+ * z <- D^-1 (y - U_strict z)), a fixed linear operator (the truncated
+ * Neumann series), exact once s reaches the depth of the triangle.  t must
+ * hold 2n elements. */
+static void FN(ilu_apply_)(int n, const int* rp, const int* ci, const REAL* F, const int* diag, int sweeps,
+                           const REAL* p, REAL* out, REAL* t) {
+  REAL *y = t, *u = t + n;
+  if (sweeps == 0) {
+    for (int i = 0; i < n; ++i) {
+      REAL acc = p[i];
+      for (int k = rp[i]; k < diag[i]; ++k) acc -= F[k] * y[ci[k]];
+      y[i] = acc;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      REAL acc = y[i];
+      for (int k = diag[i] + 1; k < rp[i + 1]; ++k) acc -= F[k] * out[ci[k]];
+      out[i] = acc / F[diag[i]];
+    }
+    return;
+  }
+  for (int i = 0; i < n; ++i) y[i] = p[i];
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int i = 0; i < n; ++i) {
+      REAL acc = p[i];
+      for (int k = rp[i]; k < diag[i]; ++k) acc -= F[k] * y[ci[k]];
+      u[i] = acc;
+    }
+    for (int i = 0; i < n; ++i) y[i] = u[i];
+  }
+  for (int i = 0; i < n; ++i) out[i] = y[i] / F[diag[i]];
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int i = 0; i < n; ++i) {
+      REAL acc = y[i];
+      for (int k = diag[i] + 1; k < rp[i + 1]; ++k) acc -= F[k] * out[ci[k]];
+      u[i] = acc / F[diag[i]];
+    }
+    for (int i = 0; i < n; ++i) out[i] = u[i];
+  }
+}
+
+/* Returns the iteration count.  x0 is the initial guess (NULL: zero).
+ * precond: 0 none, 1 Jacobi, 2 ILU(0) applied with ilu_sweeps (0 = exact).
+ * w must hold 10*n elements. */
+static int FN(bicgstab_core_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, const REAL* x0,
+                              double rtol, int maxit, int precond, int ilu_sweeps, int rr, int brs, REAL* x,
+                              double* resid_out, int* status_out, REAL* w, const REAL* F, const int* fdiag,
+                              REAL* ft) {
   REAL *r = w, *rh = w + n, *p = w + 2 * n, *v = w + 3 * n, *s = w + 4 * n;
   REAL *t = w + 5 * n, *ph = w + 6 * n, *sh = w + 7 * n, *dinv = w + 8 * n, *rt = w + 9 * n;
   for (int i = 0; i < n; ++i) x[i] = 0;
@@ -72,7 +155,7 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
     *status_out = OR_CONVERGED;
     return 0;
   }
-  if (precond) {
+  if (precond == 1) {
     for (int i = 0; i < n; ++i) {
       REAL d = 0;
       for (int k = rp[i]; k < rp[i + 1]; ++k)
@@ -80,6 +163,13 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
       dinv[i] = (REAL)1 / d;
     }
   }
+#define PRECOND_APPLY(dst, src)                                                \
+  do {                                                                         \
+    if (precond == 2)                                                          \
+      FN(ilu_apply_)(n, rp, ci, F, fdiag, ilu_sweeps, src, dst, ft);           \
+    else                                                                       \
+      for (int i_ = 0; i_ < n; ++i_) dst[i_] = precond ? dinv[i_] * src[i_] : src[i_]; \
+  } while (0)
   /* r0 = b - A x0 */
   if (x0) {
     for (int i = 0; i < n; ++i) x[i] = x0[i];
@@ -117,7 +207,7 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
         REAL beta = (rho / rho_prev) * (alpha / omega);
         for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
       }
-      for (int i = 0; i < n; ++i) ph[i] = precond ? dinv[i] * p[i] : p[i];
+      PRECOND_APPLY(ph, p);
       FN(spmv_)(n, rp, ci, A, ph, v);
       REAL sigma = FN(dot_)(n, rh, v);
       if (!isfinite((double)sigma)) { ended = OR_NONFINITE; break; }
@@ -131,7 +221,7 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
         ended = OR_CONVERGED;
         break;
       }
-      for (int i = 0; i < n; ++i) sh[i] = precond ? dinv[i] * s[i] : s[i];
+      PRECOND_APPLY(sh, s);
       FN(spmv_)(n, rp, ci, A, sh, t);
       REAL tau = FN(dot_)(n, t, t);
       if (!isfinite((double)tau)) { ended = OR_NONFINITE; break; }
@@ -168,6 +258,26 @@ static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, con
     *status_out = (ended == OR_BREAKDOWN) ? OR_BREAKDOWN : OR_MAXIT;
     return it;
   }
+}
+
+#undef PRECOND_APPLY
+
+static int FN(bicgstab_)(int n, const int* rp, const int* ci, const REAL* A, const REAL* b, const REAL* x0,
+                         double rtol, int maxit, int precond, int ilu_sweeps, int rr, int brs, REAL* x,
+                         double* resid_out, int* status_out, REAL* w) {
+  if (precond != 2)
+    return FN(bicgstab_core_)(n, rp, ci, A, b, x0, rtol, maxit, precond, ilu_sweeps, rr, brs, x, resid_out,
+                              status_out, w, NULL, NULL, NULL);
+  REAL* F = (REAL*)malloc(sizeof(REAL) * (size_t)(rp[n] > 0 ? rp[n] : 1));
+  int* fdiag = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  REAL* ft = (REAL*)malloc(sizeof(REAL) * 2 * (size_t)(n > 0 ? n : 1));
+  FN(ilu0_)(n, rp, ci, A, F, fdiag); /* the pattern's diagonal is checked by the caller */
+  int it = FN(bicgstab_core_)(n, rp, ci, A, b, x0, rtol, maxit, precond, ilu_sweeps, rr, brs, x, resid_out,
+                              status_out, w, F, fdiag, ft);
+  free(F);
+  free(fdiag);
+  free(ft);
+  return it;
 }
 
 #undef FN

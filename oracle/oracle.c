@@ -82,8 +82,8 @@ static void cell_matrix(int n, int nnz, const int* rp, const int* ci, const doub
  * x0: initial guesses [ncells, n], or NULL for zero. */
 void oracle_solve_batch(int64_t ncells, int n, int nnz, const int* rp, const int* ci, const double* values,
                         const double* gamma, int64_t gamma_stride, int kind, const double* b, const double* x0,
-                        double rtol, int maxit, int precond, int rr, int brs, double* x, int32_t* iters,
-                        double* resid, int32_t* status, int nthreads) {
+                        double rtol, int maxit, int precond, int ilu_sweeps, int rr, int brs, double* x,
+                        int32_t* iters, double* resid, int32_t* status, int nthreads) {
   set_threads(nthreads);
 #pragma omp parallel
   {
@@ -93,8 +93,8 @@ void oracle_solve_batch(int64_t ncells, int n, int nnz, const int* rp, const int
     for (int64_t c = 0; c < ncells; ++c) {
       cell_matrix(n, nnz, rp, ci, values, gamma, gamma_stride, kind, c, A);
       int st = 0;
-      iters[c] = bicgstab_d(n, rp, ci, A, b + c * n, x0 ? x0 + c * n : NULL, rtol, maxit, precond, rr, brs,
-                            x + c * n, &resid[c], &st, w);
+      iters[c] = bicgstab_d(n, rp, ci, A, b + c * n, x0 ? x0 + c * n : NULL, rtol, maxit, precond, ilu_sweeps, rr,
+                            brs, x + c * n, &resid[c], &st, w);
       status[c] = st;
     }
     free(A);
@@ -111,11 +111,35 @@ void oracle_solve_batch_f(int64_t ncells, int n, int nnz, const int* rp, const i
   float* w = (float*)malloc(sizeof(float) * 10 * (size_t)(n > 0 ? n : 1));
   for (int64_t c = 0; c < ncells; ++c) {
     int st = 0;
-    iters[c] = bicgstab_f(n, rp, ci, A + c * (int64_t)nnz, b + c * n, NULL, rtol, maxit, precond, rr, brs,
+    iters[c] = bicgstab_f(n, rp, ci, A + c * (int64_t)nnz, b + c * n, NULL, rtol, maxit, precond, 0, rr, brs,
                           x + c * n, &resid[c], &st, w);
     status[c] = st;
   }
   free(w);
+}
+
+/* ILU(0) factors of one matrix on its pattern (see ilu0_d): F [nnz]; returns
+ * 0 or i + 1 if row i has no diagonal entry. */
+int oracle_ilu0(int n, const int* rp, const int* ci, const double* A, double* F) {
+  int* diag = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  int rc = ilu0_d(n, rp, ci, A, F, diag);
+  free(diag);
+  return rc;
+}
+
+/* out = (L U)^-1 p with ILU(0) factors F, sweeps as in ilu_apply_d. */
+void oracle_ilu_apply(int n, const int* rp, const int* ci, const double* F, int sweeps, const double* p,
+                      double* out) {
+  int* diag = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  double* t = (double*)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+  for (int i = 0; i < n; ++i) {
+    diag[i] = -1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) diag[i] = k;
+  }
+  ilu_apply_d(n, rp, ci, F, diag, sweeps, p, out, t);
+  free(diag);
+  free(t);
 }
 
 /* Dense LU with partial pivoting (Doolittle; pivot = largest |a|, lowest row
@@ -225,8 +249,8 @@ void oracle_adjoint_batch(int64_t ncells, int n, int nnz, const int* rp, const i
       for (int q = 0; q < nnz; ++q) AT[q] = A[perm[q]];
       int st = 0;
       double* lam = grad_b + c * n;
-      iters[c] = bicgstab_d(n, trp, tci, AT, g + c * n, NULL, rtol, maxit, precond, rr, brs, lam, &resid[c], &st,
-                            w);
+      iters[c] = bicgstab_d(n, trp, tci, AT, g + c * n, NULL, rtol, maxit, precond, 0, rr, brs, lam, &resid[c],
+                            &st, w);
       status[c] = st;
       const double* xc = x + c * n;
       for (int i = 0; i < n; ++i)
@@ -318,8 +342,8 @@ void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int
           for (int i = 0; i < n; ++i) r32[i] = (float)(r[i] / rn);
           double ires;
           int ist;
-          tot += bicgstab_f(n, rp, ci, A32, r32, NULL, inner_rtol, budget_cell ? maxit - tot : maxit, 0, 0, 1, d32,
-                            &ires, &ist, w32);
+          tot += bicgstab_f(n, rp, ci, A32, r32, NULL, inner_rtol, budget_cell ? maxit - tot : maxit, 0, 0, 0, 1,
+                            d32, &ires, &ist, w32);
           ++nref;
           if (ist == OR_NONFINITE) { st = OR_NONFINITE; break; }
           for (int i = 0; i < n; ++i) xn[i] = xc[i] + rn * ((double)d32[i] / dg[i]);

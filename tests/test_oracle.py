@@ -623,3 +623,125 @@ def test_mixed_budget_per_cell_never_spends_more_than_maxit():
     # per-cell budget solves within 200 iterations, it solves the same way
     assert np.all(st_i[st_c == CONVERGED] == CONVERGED)
     assert (st_i == CONVERGED).sum() >= (st_c == CONVERGED).sum()
+
+
+# ------------------------------------------------------------------ ILU(0) --
+
+def _ilu_dense(rp, ci, F):
+    n = len(rp) - 1
+    M = oracle.to_dense(rp, ci, F)
+    L = np.tril(M, -1) + np.eye(n)
+    U = np.triu(M)
+    return L, U
+
+
+@pytest.mark.parametrize("source", ["random", "mechanism"])
+def test_ilu0_product_equals_a_on_the_pattern(source):
+    """The defining property of ILU(0): (L U)_ij = a_ij wherever (i, j) is in
+    the pattern (L unit lower, U upper, both on A's pattern)."""
+    rng = np.random.default_rng(31)
+    cases = []
+    if source == "random":
+        for _ in range(60):
+            n = int(rng.integers(2, 14))
+            M = random_sparse(n, 0.35, rng)
+            M[np.arange(n), np.arange(n)] = np.abs(M).sum(1) + rng.uniform(0.5, 2, n)
+            cases.append(dense_to_csr(M))
+    else:
+        mech, cells = config_inputs(3, ncells=30)[0]
+        for c in range(30):
+            cases.append((mech.row_ptr, mech.col_idx,
+                          oracle.form_a(mech.row_ptr, mech.col_idx, cells["values"][c], cells["gamma"][c])))
+    for rp, ci, vals in cases:
+        F = oracle.ilu0(rp, ci, vals)
+        L, U = _ilu_dense(rp, ci, F)
+        LU = L @ U
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        got = LU[rows, ci]
+        scale = (np.abs(L) @ np.abs(U))[rows, ci]
+        assert np.all(np.abs(got - vals) <= 64 * np.finfo(float).eps * scale)
+
+
+def test_ilu0_of_a_dense_pattern_is_lu_without_pivoting():
+    """On a full pattern ILU(0) drops nothing: it is Gaussian elimination
+    without pivoting, which for a diagonally dominant matrix is what LAPACK's
+    partially pivoted LU computes (its permutation is the identity)."""
+    rng = np.random.default_rng(32)
+    for n in (3, 6, 11):
+        M = rng.standard_normal((n, n))
+        M[np.arange(n), np.arange(n)] = np.abs(M).sum(1) + 1.0
+        rp, ci, vals = dense_to_csr(M)
+        F = oracle.ilu0(rp, ci, vals)
+        L, U = _ilu_dense(rp, ci, F)
+        Pm, Ls, Us = scipy.linalg.lu(M)
+        assert np.array_equal(Pm, np.eye(n))
+        assert np.allclose(L, Ls, rtol=1e-12, atol=1e-14) and np.allclose(U, Us, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", ["tridiagonal", "lower", "upper_bidiagonal"])
+def test_ilu0_without_fill_is_exact_and_solves_in_one_iteration(shape):
+    """Patterns on which elimination creates no fill: ILU(0) is the exact LU,
+    so the exactly applied preconditioner is A^-1 and preconditioned BiCGStab
+    stops at the first half step with x = A^-1 b."""
+    rng = np.random.default_rng(33)
+    n = 15
+    M = np.diag(rng.uniform(2, 4, n))
+    if shape == "tridiagonal":
+        M += np.diag(rng.uniform(-1, 1, n - 1), 1) + np.diag(rng.uniform(-1, 1, n - 1), -1)
+    elif shape == "lower":
+        M += np.tril(rng.uniform(-1, 1, (n, n)), -1)
+    else:
+        M += np.diag(rng.uniform(-1, 1, n - 1), 1)
+    rp, ci, vals = dense_to_csr(M)
+    F = oracle.ilu0(rp, ci, vals)
+    L, U = _ilu_dense(rp, ci, F)
+    assert np.allclose(L @ U, M, rtol=1e-13, atol=1e-14)
+    b = rng.standard_normal(n)
+    x, it, res, st = oracle.solve_batch(rp, ci, vals[None], [0.0], b[None], precond=2, ilu_sweeps=0,
+                                        kind=A_DIRECT)
+    assert st[0] == CONVERGED and it[0] == 1
+    assert np.allclose(x[0], np.linalg.solve(M, b), rtol=1e-12, atol=1e-14)
+
+
+def test_ilu_sweeps_are_the_truncated_neumann_series_and_exact_at_depth():
+    """s Jacobi sweeps on the unit lower triangle give y = sum_{t<=s} (-L)^t p,
+    on the upper triangle z = sum_{t<=s} (-D^-1 U)^t D^-1 y; at s >= depth - 1
+    both are the exact substitutions (strictly triangular parts are
+    nilpotent)."""
+    mech, cells = config_inputs(1, ncells=3)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    n = mech.n
+    A = oracle.form_a(rp, ci, cells["values"][1], cells["gamma"][1])
+    F = oracle.ilu0(rp, ci, A)
+    L, U = _ilu_dense(rp, ci, F)
+    Ls = L - np.eye(n)
+    d = np.diag(U)
+    Us = np.triu(U, 1)
+    p = np.random.default_rng(34).standard_normal(n)
+    for s in (1, 2, 3):
+        y = sum(np.linalg.matrix_power(-Ls, t) @ p for t in range(s + 1))
+        K = -Us / d[:, None]
+        z = sum(np.linalg.matrix_power(K, t) @ (y / d) for t in range(s + 1))
+        got = oracle.ilu_apply(rp, ci, F, p, sweeps=s)
+        assert np.allclose(got, z, rtol=1e-10, atol=1e-12 * np.abs(z).max())
+    exact = scipy.linalg.solve_triangular(U, scipy.linalg.solve_triangular(L, p, lower=True, unit_diagonal=True))
+    assert np.allclose(oracle.ilu_apply(rp, ci, F, p, sweeps=0), exact, rtol=1e-10, atol=1e-12 * np.abs(exact).max())
+    assert np.allclose(oracle.ilu_apply(rp, ci, F, p, sweeps=n), exact, rtol=1e-10, atol=1e-12 * np.abs(exact).max())
+
+
+def test_ilu_preconditioned_solves_match_lu_with_far_fewer_iterations():
+    mech, cells = config_inputs(3, ncells=300)[0]
+    rp, ci = mech.row_ptr, mech.col_idx
+    args = (rp, ci, cells["values"], cells["gamma"], cells["b"])
+    x, it, res, st = oracle.solve_batch(*args, precond=2, ilu_sweeps=3)
+    _, itj, _, stj = oracle.solve_batch(*args, precond=1)
+    xl, _ = oracle.lu_batch(*args)
+    assert np.mean(st == CONVERGED) >= np.mean(stj == CONVERGED)
+    both = (st == 0) & (stj == 0)
+    assert it[both].mean() < 0.4 * itj[both].mean()
+    for c in np.nonzero(st == CONVERGED)[0][::5]:
+        A = oracle.to_dense(rp, ci, oracle.form_a(rp, ci, cells["values"][c], cells["gamma"][c]))
+        kappa = np.linalg.cond(A)
+        rlu = np.linalg.norm(cells["b"][c] - A @ xl[c]) / np.linalg.norm(cells["b"][c])
+        err = np.linalg.norm(x[c] - xl[c]) / np.linalg.norm(xl[c])
+        assert err <= max(1e-8, 4 * kappa * max(res[c], rlu))
