@@ -62,6 +62,13 @@ extern "C" {
 #define BCS_FP32_REFINE 1 /* FP32 inner BiCGStab, FP64 residual, scaling and update */
 #define BCS_PRECOND_NONE 0
 #define BCS_PRECOND_JACOBI 1 /* right preconditioning with M = diag(A) */
+#define BCS_PRECOND_ILU0 2   /* right preconditioning with M = L U, the incomplete LU
+                                factors of A on A's own pattern (ILU(0)); the paper
+                                names a preconditioner as its solver's most promising
+                                next optimisation (Section 5.2).  The factors are
+                                computed per cell inside the solve; M^-1 is applied by
+                                ilu_sweeps Jacobi sweeps per triangular factor.  FP64,
+                                jit = 1, forward solves (bcs_solve_batch) only */
 #define BCS_J_GAMMA 0        /* values hold J; A = I - gamma*J (pattern must hold the diagonal) */
 #define BCS_A_DIRECT 1       /* values hold A itself; gamma is ignored */
 #define BCS_BUDGET_INNER 0   /* FP32_REFINE: maxit bounds each inner solve */
@@ -114,7 +121,14 @@ typedef struct bcs_options {
                                    cell's inner iterations summed over its inner
                                    solves, as it bounds the FP64 solve's iterations
                                    summed over its restarts)                       */
-  int32_t reserved[2];          /* must be zero                                       */
+  int32_t ilu_sweeps;           /* BCS_PRECOND_ILU0: Jacobi sweeps per triangular
+                                   solve, 1..16 (0 = the library's default, 3): L y = q
+                                   by y <- q, then ilu_sweeps times y <- q - L_s y;
+                                   U z = y by z <- D^-1 y, then ilu_sweeps times
+                                   z <- D^-1 (y - U_s z) (L_s, U_s the strict parts,
+                                   D = diag(U)), the truncated Neumann series of each
+                                   factor.  Must be 0 for other preconditioners    */
+  int32_t reserved[1];          /* must be zero                                       */
 } bcs_options;
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation, except for the
@@ -124,7 +138,7 @@ typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation, except fo
 /* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
  * max_refine 10, refine_budget BCS_BUDGET_INNER, jit 1, autotune 1,
- * cell_order 1, shared_scalars 0. */
+ * cell_order 1, shared_scalars 0, ilu_sweeps 0. */
 void bcs_options_default(bcs_options* opt);
 
 /* Create a plan: the shared sparsity pattern of every cell's Jacobian
@@ -132,8 +146,10 @@ void bcs_options_default(bcs_options* opt);
  * (Section 3.1).  The n x n pattern has nnz entries in CSR form (row_ptr[n+1],
  * col_idx[nnz], HOST int32 arrays) with row_ptr[0] = 0, row_ptr[n] = nnz,
  * non-decreasing row_ptr, strictly increasing columns in [0, n) within each
- * row, and (for BCS_J_GAMMA, Jacobi preconditioning or FP32_REFINE) every
- * diagonal entry; n <= 255.  opt == NULL means defaults.  Allocates the plan's
+ * row, and (for BCS_J_GAMMA, Jacobi or ILU(0) preconditioning or
+ * FP32_REFINE) every diagonal entry; n <= 255.  ILU(0) plans also need their
+ * factor block (nnz + 3 doubles per cell slot) and the factorisation program
+ * to fit a workgroup's LDS at some lane count, else BCS_ERR_UNSUPPORTED.  opt == NULL means defaults.  Allocates the plan's
  * device tables on the current HIP device (the plan must be used on that
  * device) and may compile kernels (hipRTC) and time them on a synthetic batch.
  * On error *out is set to NULL. */
@@ -169,14 +185,22 @@ int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, cons
 #define BCS_SCHED_SPAN 1 /* the longest rows may span row slots 0 and 1 of one lane */
 #define BCS_SCHED_DIAG 2 /* diagonal entries left out; the row sum starts from the diagonal term */
 
+/* Matrices bcs_schedule_describe can describe (its `transpose` argument). */
+#define BCS_PART_A 0       /* A */
+#define BCS_PART_AT 1      /* A^T, as the adjoint solves it */
+#define BCS_PART_LOWER 2   /* strict lower triangle (ILU(0) factor L_s) */
+#define BCS_PART_UPPER 3   /* strict upper triangle (ILU(0) factor U_s) */
+
 /* Describe, on the host (no device needed), the gather schedule the
  * specialised solve kernels use for a pattern: its rows dealt to row slots of
  * `lanes` lanes (16, 32 or 64) by decreasing length, each lane's entries step
  * after step (the sliced-ELL layout of the per-cell SpMV that Section 3.1's
  * solver performs, one row per thread there, several rows per lane here), for
- * A (transpose = 0) or for A^T as the adjoint solves it (transpose = 1), with
- * the schedule shapes allowed by `shapes` (BCS_SCHED_* mask; the diagonal is
- * left out only if every row holds it).  For tests and tuning.
+ * the matrix named by `transpose` (BCS_PART_*: A, A^T, or the strict lower or
+ * upper triangle of A, whose rows the ILU(0) kernel deals by their own
+ * lengths; positions are those of the full pattern), with the schedule
+ * shapes allowed by `shapes` (BCS_SCHED_* mask; the diagonal is left out
+ * only if every row holds it, never for a triangle).  For tests and tuning.
  *   *steps          gather steps per lane
  *   *rows_per_lane  row slots per lane, ceil(n / lanes)
  *   *shape          the BCS_SCHED_* shapes used
@@ -194,6 +218,29 @@ int bcs_plan_autotune(bcs_plan* plan, int64_t ncells, const double* values, cons
 int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,
                           int32_t transpose, int32_t shapes, int32_t* steps, int32_t* rows_per_lane,
                           int32_t* shape, int32_t* seg, int16_t* row, int32_t* pos, uint8_t* col);
+
+/* Describe, on the host, the program by which the ILU(0) kernel factorises
+ * one cell for a pattern (every row holding its diagonal) and lane count
+ * (16, 32 or 64).  The cell's factor block holds the nnz values in CSR order
+ * and three constants at positions nnz (0.0), nnz + 1 (1.0) and nnz + 2
+ * (scratch).  Step st has widths[st] terms and runs one operation per lane:
+ * its words (lanes head words, then widths[st] x lanes term words, lane
+ * minor, steps one after another) give, per lane, head = target | divisor
+ * << 16 and term = p | q << 16, and the operation is
+ *   F[target] = (F[target] - sum over its terms of F[p] F[q]) / F[divisor].
+ * Running the steps in order turns A into its ILU(0) factors (L strictly
+ * below the diagonal, unit diagonal implied; U on and above it): the IKJ
+ * elimination restricted to the pattern (Saad, Iterative Methods for Sparse
+ * Linear Systems, Algorithm 10.4), per entry, the operations of one step
+ * independent of each other.  For tests.
+ *   *nsteps   steps
+ *   widths    [nsteps] (may be NULL)
+ *   *nwords   words (sum over steps of (1 + widths[st]) * lanes)
+ *   words     [nwords] (may be NULL)
+ * Call once with NULL arrays to learn the sizes.  Returns BCS_OK or an error
+ * code (BCS_ERR_UNSUPPORTED if positions do not fit 16 bits). */
+int bcs_ilu_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,
+                     int32_t* nsteps, int32_t* widths, int32_t* nwords, uint32_t* words);
 
 /* Describe the plan's launch configuration (the threads- and cells-per-block
  * choice of Section 3.2's Table 1, here per wavefront): lanes per cell, rows
@@ -250,6 +297,7 @@ int bcs_solve_batch(const bcs_plan* plan, int64_t ncells, const double* values, 
  *                              shared gamma is the sum of these per-cell terms.
  * iters/resid/status describe the transposed solve.  Other arguments as in
  * bcs_solve_batch; x and g are device [ncells, n] FP64. */
+/* (Not available for ILU(0) plans: BCS_ERR_UNSUPPORTED.) */
 int bcs_solve_batch_adjoint(const bcs_plan* plan, int64_t ncells, const double* values,
                             const double* gamma, int64_t gamma_stride, const double* x, const double* g,
                             double rtol, int32_t maxit, int32_t grad_kind, double* grad_b, double* grad_vals,
@@ -267,7 +315,8 @@ size_t bcs_multi_workspace_bytes(int32_t nmech, const bcs_plan* const* plans, co
  * Section 3.2 and the fixed cells-per-block choices of Table 1 replaced by
  * work stealing).  Arrays are per mechanism m (host arrays of device
  * pointers, length nmech); semantics per cell as in bcs_solve_batch with
- * x0 = 0.  All plans must use BCS_FP64 and jit = 1.  nmech <= 8.  The
+ * x0 = 0.  All plans must use BCS_FP64, jit = 1 and a Jacobi or no
+ * preconditioner.  nmech <= 8.  The
  * mechanisms' LDS layouts must fit one workgroup together (64 KiB); a
  * combination that does not is rejected with BCS_ERR_UNSUPPORTED before
  * anything is compiled or launched. */

@@ -6,7 +6,7 @@ marshals torch tensors (device memory) and the current HIP stream.  There is
 no fallback: if the library is missing or fails to load, the import of the
 entry points raises.
 
-    plan = Plan(row_ptr, col_idx, precond="jacobi")          # shared pattern
+    plan = Plan(row_ptr, col_idx, precond="jacobi")          # shared pattern ("ilu0": ILU(0))
     x, iters, resid, status, _ = solve_batch(plan, J, gamma, b)  # per-cell values
     x, status = BatchedSolve.apply(J, gamma, b, plan)            # differentiable
 """
@@ -25,6 +25,13 @@ from ._binding import (  # noqa: F401
     BCS_J_GAMMA,
     BCS_MAXIT,
     BCS_NONFINITE,
+    BCS_PART_A,
+    BCS_PART_AT,
+    BCS_PART_LOWER,
+    BCS_PART_UPPER,
+    BCS_PRECOND_ILU0,
+    BCS_PRECOND_JACOBI,
+    BCS_PRECOND_NONE,
     BCS_SCHED_DIAG,
     BCS_SCHED_SPAN,
     BcsError,
@@ -32,6 +39,7 @@ from ._binding import (  # noqa: F401
     BatchedSolveWarning,
     Plan,
     exported_symbols,
+    ilu_describe,
     lib,
     library_path,
     multi_autotune,

@@ -16,13 +16,14 @@ _HEADER = os.path.join(os.path.dirname(_HERE), "include", "bcs.h")
 BCS_OK = 0
 BCS_CONVERGED, BCS_MAXIT, BCS_BREAKDOWN, BCS_NONFINITE = 0, 1, 2, 3
 BCS_FP64, BCS_FP32_REFINE = 0, 1
-BCS_PRECOND_NONE, BCS_PRECOND_JACOBI = 0, 1
+BCS_PRECOND_NONE, BCS_PRECOND_JACOBI, BCS_PRECOND_ILU0 = 0, 1, 2
 BCS_J_GAMMA, BCS_A_DIRECT = 0, 1
 BCS_SCHED_SPAN, BCS_SCHED_DIAG = 1, 2
+BCS_PART_A, BCS_PART_AT, BCS_PART_LOWER, BCS_PART_UPPER = 0, 1, 2, 3
 BCS_BUDGET_INNER, BCS_BUDGET_CELL = 0, 1
 BCS_GRAD_A, BCS_GRAD_VALUES = 0, 1
 
-_PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI}
+_PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI, "ilu0": BCS_PRECOND_ILU0}
 _PRECISION = {"fp64": BCS_FP64, "fp32_refine": BCS_FP32_REFINE}
 _KIND = {"j_gamma": BCS_J_GAMMA, "a_direct": BCS_A_DIRECT}
 _BUDGET = {"inner": BCS_BUDGET_INNER, "cell": BCS_BUDGET_CELL}
@@ -50,7 +51,8 @@ class _Options(ctypes.Structure):
         ("cell_order", ctypes.c_int32),
         ("shared_scalars", ctypes.c_int32),
         ("refine_budget", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("ilu_sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -99,6 +101,8 @@ def lib():
         L.bcs_multi_autotune.restype = ctypes.c_int
         L.bcs_schedule_describe.argtypes = [I32, I32, P, P, I32, I32, I32, P, P, P, P, P, P, P]
         L.bcs_schedule_describe.restype = ctypes.c_int
+        L.bcs_ilu_describe.argtypes = [I32, I32, P, P, I32, P, P, P, P]
+        L.bcs_ilu_describe.restype = ctypes.c_int
         L.bcs_last_error.argtypes = []
         L.bcs_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -112,11 +116,12 @@ def exported_symbols() -> list:
     return sorted(set(re.findall(r"\b(bcs_[a-z_]+)\s*\(", text)))
 
 
-def schedule_describe(row_ptr, col_idx, lanes: int, transpose: bool = False,
+def schedule_describe(row_ptr, col_idx, lanes: int, transpose=False,
                       shapes: int = BCS_SCHED_SPAN | BCS_SCHED_DIAG) -> dict:
     """The specialised kernels' gather schedule for a pattern (host only; see
     bcs_schedule_describe in include/bcs.h): steps, rows_per_lane, shape, and
-    the arrays seg [rpl], row [rpl, lanes], pos [steps, lanes], col [steps, lanes]."""
+    the arrays seg [rpl], row [rpl, lanes], pos [steps, lanes], col [steps, lanes].
+    transpose: False/True (A, A^T) or a BCS_PART_* value (the ILU(0) triangles)."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     n, nnz = rp.size - 1, ci.size
@@ -131,6 +136,21 @@ def schedule_describe(row_ptr, col_idx, lanes: int, transpose: bool = False,
     _check(lib().bcs_schedule_describe(*args, None, None, None, seg.ctypes.data, row.ctypes.data, pos.ctypes.data,
                                        col.ctypes.data))
     return dict(steps=steps, rows_per_lane=rpl, shape=shape, seg=seg, row=row, pos=pos, col=col)
+
+
+def ilu_describe(row_ptr, col_idx, lanes: int) -> dict:
+    """The ILU(0) kernel's factorisation program for a pattern (host only; see
+    bcs_ilu_describe in include/bcs.h): widths [nsteps] and words [nwords]."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n, nnz = rp.size - 1, ci.size
+    ns, nw = ctypes.c_int32(), ctypes.c_int32()
+    args = (n, nnz, rp.ctypes.data, ci.ctypes.data, int(lanes))
+    _check(lib().bcs_ilu_describe(*args, ctypes.byref(ns), None, ctypes.byref(nw), None))
+    widths = np.zeros(ns.value, np.int32)
+    words = np.zeros(nw.value, np.uint32)
+    _check(lib().bcs_ilu_describe(*args, None, widths.ctypes.data, None, words.ctypes.data))
+    return dict(widths=widths, words=words)
 
 
 def _check(rc: int) -> None:
@@ -171,7 +191,7 @@ class Plan:
                  matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
                  breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10,
                  jit: bool = True, autotune: bool = True, cell_order: bool = True,
-                 shared_scalars: bool = False, refine_budget: str = "inner"):
+                 shared_scalars: bool = False, refine_budget: str = "inner", ilu_sweeps: int = 0):
         L = lib()
         rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
         ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
@@ -193,6 +213,7 @@ class Plan:
         opt.cell_order = int(bool(cell_order))
         opt.shared_scalars = int(bool(shared_scalars))
         opt.refine_budget = _BUDGET[refine_budget]
+        opt.ilu_sweeps = int(ilu_sweeps)
         self.options = opt
         self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
         h = ctypes.c_void_p()

@@ -305,6 +305,14 @@ struct Kernel {
   WgLayout layout;
   bcs::DevSchedule d{};
   void* buf = nullptr;  // device schedule arrays
+  // ILU(0) kernels (bcs_ilu.h): the triangles' schedules, the 16-bit value
+  // position tables and the factorisation program (device copies in ibuf)
+  bool ilu = false;
+  int fs = 0, sweeps = 0, fprog_words = 0;
+  bcs::DevSchedule dL{}, dU{};
+  const uint16_t* ilu_tab = nullptr;
+  const uint32_t* fprog = nullptr;
+  void* ibuf = nullptr;
 
   hipError_t launch(const bcs::KParams& P, int grid, hipStream_t stream) const {
     if (var) return var->fp64(P, grid, stream);
@@ -352,7 +360,9 @@ int upload_schedule(const HostSchedule& S, Kernel* K) {
 
 void free_kernel(Kernel* K) {
   if (K->buf) (void)hipFree(K->buf);
+  if (K->ibuf) (void)hipFree(K->ibuf);
   K->buf = nullptr;
+  K->ibuf = nullptr;
 }
 
 // Transposed pattern of (rp, ci): trp/tci its CSR arrays, tpos[q] the CSR
@@ -389,6 +399,266 @@ bool adjoint_fits(int n, const std::vector<int>& trp, const std::vector<int>& tc
   const int rpl = (n + lanes - 1) / lanes;
   const HostSchedule T = build_schedule_jit(n, trp, tci, tpos, lanes, rpl, sched_allowed(false));
   return T.ksteps > 0 && jit_feasible(T.ksteps, rpl) && layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1));
+}
+
+// ---- ILU(0) preconditioning (kernel body in bcs_ilu.h) ----
+
+// Jacobi sweeps per triangular solve when the options leave the choice to
+// the library.
+constexpr int kIluSweepsDefault = 3;
+
+// The strict lower (part 0) or strict upper (part 1) triangle of a pattern
+// as a CSR pattern of its own; tpos[q] is the position of its entry q in the
+// full pattern.
+void triangle_pattern(int n, const std::vector<int>& rp, const std::vector<int>& ci, int part,
+                      std::vector<int>& trp, std::vector<int>& tci, std::vector<int>& tpos) {
+  trp.assign(n + 1, 0);
+  tci.clear();
+  tpos.clear();
+  for (int i = 0; i < n; ++i) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (part == 0 ? ci[k] < i : ci[k] > i) {
+        tci.push_back(ci[k]);
+        tpos.push_back(k);
+      }
+    trp[i + 1] = (int)tci.size();
+  }
+}
+
+// Gather schedule of a triangle, its rows dealt by their own lengths (the
+// spanning shape allowed; a triangle holds no diagonal), with value
+// positions in the full pattern.  ksteps = -1 if the schedule's own check
+// fails.
+HostSchedule triangle_schedule(int n, const std::vector<int>& rp, const std::vector<int>& ci, int part, int lanes) {
+  std::vector<int> trp, tci, tpos;
+  triangle_pattern(n, rp, ci, part, trp, tci, tpos);
+  std::vector<int> ident(tci.size());
+  for (size_t q = 0; q < ident.size(); ++q) ident[q] = (int)q;
+  const int rpl = (n + lanes - 1) / lanes;
+  HostSchedule S = build_schedule_jit(n, trp, tci, ident, lanes, rpl, sched_allowed(false) & bcs::kSchedSpan);
+  if (S.ksteps < 0) return S;
+  for (int32_t& e : S.ent)
+    if (!(e & bcs::kEntPad)) e = tpos[e & bcs::kEntPosMask] | (e & ~bcs::kEntPosMask);
+  return S;
+}
+
+// The numeric factorisation as a program (format in bcs_ilu.h: FactProg).
+// Entry (i, j) of the pattern becomes a_ij - sum_k l_ik u_kj over the
+// k < min(i, j) with (i, k) and (k, j) in the pattern (increasing k), divided
+// by u_jj when i > j: the IKJ elimination of ILU(0) (Saad, Algorithm 10.4)
+// written per entry.  An entry is an operation if it has terms or lies below
+// the diagonal (upper entries without terms keep a_ij).  Its level is one
+// more than the highest level among its inputs (l_ik, u_kj and the pivot
+// u_jj; unchanged entries have level 0), so that the operations of a level
+// only read final values; CSR order is a topological order of these
+// dependencies.  Each level becomes steps of at most `lanes` operations,
+// sorted by term count so that a step's width (its largest term count) pads
+// little.  Every row must hold its diagonal.  Returns false if a position
+// does not fit 16 bits.
+struct IluProgram {
+  std::vector<int> widths;      // terms per step
+  std::vector<uint32_t> words;  // per step: lanes head words, then widths[st] x lanes term words
+};
+
+bool build_ilu_program(int n, const std::vector<int>& rp, const std::vector<int>& ci, int lanes, IluProgram* out) {
+  const int nnz = rp[n];
+  if (nnz + bcs::kIluSpare > 65536) return false;
+  const uint32_t zero = (uint32_t)(nnz + bcs::kIluZero), unit = (uint32_t)(nnz + bcs::kIluUnit),
+                 junk = (uint32_t)(nnz + bcs::kIluJunk);
+  std::vector<int> at((size_t)n * n, -1), diag(n, -1);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      at[(size_t)i * n + ci[k]] = k;
+      if (ci[k] == i) diag[i] = k;
+    }
+  struct Op {
+    uint32_t head;
+    std::vector<uint32_t> terms;
+  };
+  std::vector<int> level(nnz, 0);
+  std::vector<std::vector<Op>> by_level;
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      Op op;
+      int lv = 0;
+      for (int q = rp[i]; q < rp[i + 1] && ci[q] < std::min(i, j); ++q) {
+        const int u = at[(size_t)ci[q] * n + j];
+        if (u < 0) continue;
+        op.terms.push_back((uint32_t)q | ((uint32_t)u << 16));
+        lv = std::max(lv, std::max(level[q], level[u]));
+      }
+      if (i > j)
+        lv = std::max(lv, level[diag[j]]);
+      else if (op.terms.empty())
+        continue;
+      op.head = (uint32_t)k | ((uint32_t)(i > j ? diag[j] : (int)unit) << 16);
+      level[k] = lv + 1;
+      if ((int)by_level.size() < lv + 1) by_level.resize(lv + 1);
+      by_level[lv].push_back(std::move(op));
+    }
+  out->widths.clear();
+  out->words.clear();
+  for (auto& ops : by_level) {
+    std::stable_sort(ops.begin(), ops.end(),
+                     [](const Op& a, const Op& b) { return a.terms.size() > b.terms.size(); });
+    for (size_t c0 = 0; c0 < ops.size(); c0 += (size_t)lanes) {
+      const size_t c1 = std::min(ops.size(), c0 + (size_t)lanes);
+      const int w = (int)ops[c0].terms.size();
+      out->widths.push_back(w);
+      for (int l = 0; l < lanes; ++l) out->words.push_back(c0 + l < c1 ? ops[c0 + l].head : (junk | unit << 16));
+      for (int q = 0; q < w; ++q)
+        for (int l = 0; l < lanes; ++l) {
+          const bool real = c0 + l < c1 && q < (int)ops[c0 + l].terms.size();
+          out->words.push_back(real ? ops[c0 + l].terms[q] : (zero | zero << 16));
+        }
+    }
+  }
+  return true;
+}
+
+// Workgroup LDS of the ILU(0) kernel, in doubles: one block per cell slot
+// (stride fs: the factor block of nnz values and the three constants while a
+// cell is staged, afterwards the operand block of n values and the zero
+// spare element; 8 mod 32 doubles apart so that a wave's slots start on
+// different banks), then at tbase the 16-bit tables (value positions of A,
+// L_s and U_s, each row's diagonal position and the padding row's) and the
+// factorisation program.  The gathers' 16-bit addresses reach the first
+// 64 KiB, where every operand block must end.
+struct IluLayout {
+  int fs = 0, tbase = 0;
+  size_t bytes = 0, gather_end = 0;
+};
+
+IluLayout ilu_layout(int n, int nnz, int lanes, int ka, int kl, int ku, size_t prog_words) {
+  IluLayout L;
+  const int v = std::max(nnz + bcs::kIluSpare, n + 1);
+  const int v8 = ((v + 7) / 8) * 8;
+  L.fs = ((v8 + 31) / 32) * 32 + 8;
+  const int slots = slots_per_wg(lanes);
+  L.tbase = slots * L.fs;
+  const size_t ntab = (size_t)(ka + kl + ku) * lanes + n + 1;
+  L.bytes = (size_t)L.tbase * 8 + ((ntab + 1) & ~(size_t)1) * 2 + prog_words * 4;
+  L.gather_end = ((size_t)(slots - 1) * L.fs + n + 1) * 8;
+  return L;
+}
+
+// Registers of an ILU(0) layout (values 2 VGPRs a step, addresses one a
+// step, ten register vectors and the sweeps' temporaries): larger layouts
+// would spill.
+bool ilu_feasible(int ka, int kl, int ku, int rpl) { return 3 * (ka + kl + ku) + 26 * rpl <= 300; }
+
+int upload_ilu(const HostSchedule& SL, const HostSchedule& SU, const std::vector<uint16_t>& tab,
+               const IluProgram& prog, Kernel* K) {
+  auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  const size_t o_rl = 0, o_cl = al(o_rl + SL.row.size() * 2), o_ru = al(o_cl + SL.col.size());
+  const size_t o_cu = al(o_ru + SU.row.size() * 2), o_tab = al(o_cu + SU.col.size());
+  const size_t o_prog = al(o_tab + tab.size() * 2), total = al(o_prog + prog.words.size() * 4) + 16;
+  void* buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, total));
+  K->ibuf = buf;
+  char* p = (char*)buf;
+  HIP_TRY(hipMemcpy(p + o_rl, SL.row.data(), SL.row.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + o_cl, SL.col.data(), SL.col.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + o_ru, SU.row.data(), SU.row.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + o_cu, SU.col.data(), SU.col.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p + o_tab, tab.data(), tab.size() * 2, hipMemcpyHostToDevice));
+  if (!prog.words.empty())
+    HIP_TRY(hipMemcpy(p + o_prog, prog.words.data(), prog.words.size() * 4, hipMemcpyHostToDevice));
+  auto dev = [](const HostSchedule& S, const char* row, const char* col) {
+    bcs::DevSchedule d{};
+    d.ent = nullptr;
+    d.row = (const int16_t*)row;
+    d.col = (const uint8_t*)col;
+    d.ksteps = S.ksteps;
+    d.rpl = S.rpl;
+    d.flush[0] = S.flush[0];
+    d.flush[1] = S.flush[1];
+    return d;
+  };
+  K->dL = dev(SL, p + o_rl, p + o_cl);
+  K->dU = dev(SU, p + o_ru, p + o_cu);
+  K->ilu_tab = (const uint16_t*)(p + o_tab);
+  K->fprog = (const uint32_t*)(p + o_prog);
+  K->fprog_words = (int)prog.words.size();
+  return BCS_OK;
+}
+
+// Build the ILU(0) kernel for one lanes-per-cell choice (forward solves;
+// every row holds its diagonal).  Returns BCS_ERR_UNSUPPORTED without a
+// message when the layout does not fit or spills.
+int make_ilu_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, int lanes, int sweeps,
+                    Kernel* out) {
+  const int nnz = rp[n];
+  const int rpl = (n + lanes - 1) / lanes;
+  std::vector<int> pos(nnz);
+  for (int k = 0; k < nnz; ++k) pos[k] = k;
+  const HostSchedule SA = build_schedule_jit(n, rp, ci, pos, lanes, rpl, sched_allowed(false));
+  const HostSchedule SL = triangle_schedule(n, rp, ci, 0, lanes);
+  const HostSchedule SU = triangle_schedule(n, rp, ci, 1, lanes);
+  if (SA.ksteps < 0 || SL.ksteps < 0 || SU.ksteps < 0)
+    return fail(BCS_ERR_UNSUPPORTED, "internal error: ILU(0) schedule check failed (lanes = %d)", lanes);
+  if (!ilu_feasible(SA.ksteps, SL.ksteps, SU.ksteps, rpl)) return BCS_ERR_UNSUPPORTED;
+  IluProgram prog;
+  if (!build_ilu_program(n, rp, ci, lanes, &prog)) return BCS_ERR_UNSUPPORTED;
+  const IluLayout L = ilu_layout(n, nnz, lanes, SA.ksteps, SL.ksteps, SU.ksteps, prog.words.size());
+  if (L.gather_end > 65536 || L.bytes > device_max_lds()) return BCS_ERR_UNSUPPORTED;
+  Kernel K;
+  K.lanes = lanes;
+  K.rpl = rpl;
+  K.ksteps = SA.ksteps;
+  K.seg = SA.seg;
+  K.flags = SA.flags;
+  K.ilu = true;
+  K.sweeps = sweeps;
+  K.fs = L.fs;
+  K.layout.tbase = L.tbase;
+  K.layout.bytes = L.bytes;
+  K.lds = L.bytes;
+  // three schedules' values and addresses live in registers at once: packed
+  // addresses and a shorter gather window keep the kernel within 256 VGPRs
+  const int opt = bcs::kSchedPack | bcs::kSchedWin8;
+  const int flags[3] = {SA.flags | opt, SL.flags | opt, SU.flags | opt};
+  const int* segs[3] = {SA.seg.data(), SL.seg.data(), SU.seg.data()};
+  const int rpls[3] = {rpl, rpl, rpl};
+  char err[512] = {0};
+  const int rc = bcs::jit_ilu_kernel(lanes, flags, segs, rpls, nnz, prog.widths.data(), (int)prog.widths.size(),
+                                     K.lds, &K.jit, err, sizeof(err));
+  if (rc != BCS_OK) return fail(rc, "%s", err);
+  if (K.jit.scratch > 0) return BCS_ERR_UNSUPPORTED;  // spills: another lane count serves the pattern
+  K.max_blocks = K.jit.max_blocks;
+  if (const char* e = std::getenv("BCS_BLOCKS_PER_CU")) {
+    const int o = std::atoi(e);
+    if (o > 0) K.max_blocks = o;
+  }
+  std::vector<uint16_t> tab;
+  auto push = [&](const HostSchedule& S) {
+    for (int32_t e : S.ent) tab.push_back((uint16_t)((e & bcs::kEntPad) ? nnz + bcs::kIluZero : (e & bcs::kEntPosMask)));
+  };
+  push(SA);
+  push(SL);
+  push(SU);
+  for (int i = 0; i < n; ++i) {
+    int d = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) d = k;
+    tab.push_back((uint16_t)d);
+  }
+  tab.push_back((uint16_t)(nnz + bcs::kIluUnit));
+  int r = upload_schedule(SA, &K);
+  if (r == BCS_OK) r = upload_ilu(SL, SU, tab, prog, &K);
+  if (r != BCS_OK) {
+    free_kernel(&K);
+    return r;
+  }
+  if (verbose())
+    std::fprintf(stderr,
+                 "[bcs] kernel ilu0 lanes=%d rpl=%d steps A/L/U=%d/%d/%d shapes=%d/%d/%d factor steps=%zu "
+                 "words=%zu sweeps=%d lds=%zu blocks/CU=%d\n",
+                 lanes, rpl, SA.ksteps, SL.ksteps, SU.ksteps, SA.flags, SL.flags, SU.flags, prog.widths.size(),
+                 prog.words.size(), sweeps, K.lds, K.max_blocks);
+  *out = K;
+  return BCS_OK;
 }
 
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
@@ -616,6 +886,15 @@ int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, hipStream_t strea
   P.wbs = L.wbs;
   P.yoff = L.yoff;
   P.tbase = L.tbase;
+  if (K.ilu) {
+    P.schedL = K.dL;
+    P.schedU = K.dU;
+    P.ilu_tab = K.ilu_tab;
+    P.fprog = K.fprog;
+    P.fprog_words = K.fprog_words;
+    P.sweeps = K.sweeps;
+    P.fs = K.fs;
+  }
   const int grid = grid_for(p, K, P.ncells);
   const hipError_t e = K.launch(P, grid, stream);
   if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve launch: %s", hipGetErrorString(e));
@@ -757,8 +1036,13 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (!row_ptr || !col_idx) return fail(BCS_ERR_ARG, "row_ptr/col_idx is NULL");
   if (o.precision != BCS_FP64 && o.precision != BCS_FP32_REFINE)
     return fail(BCS_ERR_ARG, "unknown precision %d", o.precision);
-  if (o.precond != BCS_PRECOND_NONE && o.precond != BCS_PRECOND_JACOBI)
+  if (o.precond != BCS_PRECOND_NONE && o.precond != BCS_PRECOND_JACOBI && o.precond != BCS_PRECOND_ILU0)
     return fail(BCS_ERR_ARG, "unknown preconditioner %d", o.precond);
+  const bool ilu = o.precond == BCS_PRECOND_ILU0;
+  if (ilu && (o.precision != BCS_FP64 || o.jit != 1 || o.shared_scalars != 0))
+    return fail(BCS_ERR_ARG, "BCS_PRECOND_ILU0 needs FP64, jit = 1 and shared_scalars = 0");
+  if (o.ilu_sweeps < 0 || o.ilu_sweeps > 16 || (!ilu && o.ilu_sweeps != 0))
+    return fail(BCS_ERR_ARG, "ilu_sweeps must be in [0, 16], and 0 unless precond is BCS_PRECOND_ILU0");
   if (o.matrix_kind != BCS_J_GAMMA && o.matrix_kind != BCS_A_DIRECT)
     return fail(BCS_ERR_ARG, "unknown matrix kind %d", o.matrix_kind);
   if (o.lanes_per_cell != 0 && o.lanes_per_cell != 16 && o.lanes_per_cell != 32 && o.lanes_per_cell != 64)
@@ -777,14 +1061,14 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     return fail(BCS_ERR_ARG, "shared_scalars needs FP64, jit = 1 and lanes_per_cell 16, 32 or 64");
   if (o.refine_budget != BCS_BUDGET_INNER && o.refine_budget != BCS_BUDGET_CELL)
     return fail(BCS_ERR_ARG, "refine_budget must be BCS_BUDGET_INNER or BCS_BUDGET_CELL");
-  for (int i = 0; i < 2; ++i)
-    if (o.reserved[i] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
+  if (o.reserved[0] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
 
-  const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI ||
+  const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI || ilu ||
                          o.precision == BCS_FP32_REFINE;
   const int prc = check_pattern(n, nnz, row_ptr, col_idx, need_diag);
   if (prc != BCS_OK) return prc;
 
+  if (ilu && o.ilu_sweeps == 0) o.ilu_sweeps = kIluSweepsDefault;
   bcs_plan* p = new bcs_plan();
   p->n = n;
   p->nnz = nnz;
@@ -843,10 +1127,11 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   const int cand[3] = {16, 32, 64};
   for (int L : cand) {
     if (o.lanes_per_cell != 0 && o.lanes_per_cell != L) continue;
-    if (!adjoint_fits(n, trp, tci, tpos, L)) continue;
+    if (!ilu && !adjoint_fits(n, trp, tci, tpos, L)) continue;
     Kernel K;
     g_err.clear();
-    int r = make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K, o.shared_scalars == 1);
+    int r = ilu ? make_ilu_kernel(n, p->rp, p->ci, L, o.ilu_sweeps, &K)
+                : make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K, o.shared_scalars == 1);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) {
       rc = r;
@@ -875,9 +1160,11 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
   if (rc == BCS_OK) {
     p->fwd = best;
     g_err.clear();
-    rc = make_kernel(n, trp, tci, tpos, best.lanes, 1, jit, 0, false, &p->adj);
-    if (rc == BCS_ERR_UNSUPPORTED && g_err.empty())
-      rc = fail(BCS_ERR_UNSUPPORTED, "no kernel layout holds the transposed pattern");
+    if (!ilu) {  // ILU(0) plans solve forward systems only
+      rc = make_kernel(n, trp, tci, tpos, best.lanes, 1, jit, 0, false, &p->adj);
+      if (rc == BCS_ERR_UNSUPPORTED && g_err.empty())
+        rc = fail(BCS_ERR_UNSUPPORTED, "no kernel layout holds the transposed pattern");
+    }
   } else {
     free_kernel(&best);
   }
@@ -927,12 +1214,14 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   rc = time_launches(p, p->fwd, P, ws.ptr, 2, &best);
   if (rc != BCS_OK) return rc;
   if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
+  const bool ilu = p->opt.precond == BCS_PRECOND_ILU0;
   const int cand[3] = {16, 32, 64};
   for (int L : cand) {
-    if (L == p->fwd.lanes || !adjoint_fits(p->n, trp, tci, tpos, L)) continue;
+    if (L == p->fwd.lanes || (!ilu && !adjoint_fits(p->n, trp, tci, tpos, L))) continue;
     Kernel K;
     g_err.clear();
-    int r = make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K);
+    int r = ilu ? make_ilu_kernel(p->n, p->rp, p->ci, L, p->opt.ilu_sweeps, &K)
+                : make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) return r;
     double t = 0;
@@ -951,7 +1240,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
       free_kernel(&K);
     }
   }
-  if (p->adj.lanes != best_lanes) {
+  if (!ilu && p->adj.lanes != best_lanes) {
     Kernel A;
     g_err.clear();
     rc = make_kernel(p->n, trp, tci, tpos, best_lanes, 1, jit, 0, false, &A);
@@ -980,17 +1269,29 @@ int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const 
   g_err.clear();
   if (n <= 0 || nnz < 1 || !row_ptr || !col_idx) return fail(BCS_ERR_ARG, "bad pattern arguments");
   if (lanes != 16 && lanes != 32 && lanes != 64) return fail(BCS_ERR_ARG, "lanes must be 16, 32 or 64");
-  if (transpose != 0 && transpose != 1) return fail(BCS_ERR_ARG, "transpose must be 0 or 1");
+  if (transpose < BCS_PART_A || transpose > BCS_PART_UPPER) return fail(BCS_ERR_ARG, "unknown matrix part %d", transpose);
   if (shapes < 0 || shapes > (BCS_SCHED_SPAN | BCS_SCHED_DIAG)) return fail(BCS_ERR_ARG, "unknown shapes %d", shapes);
   const int prc = check_pattern(n, nnz, row_ptr, col_idx, false);
   if (prc != BCS_OK) return prc;
   std::vector<int> rp(row_ptr, row_ptr + n + 1), ci(col_idx, col_idx + nnz), pos0(nnz);
   for (int k = 0; k < nnz; ++k) pos0[k] = k;
   std::vector<int> trp, tci, tpos;
-  if (transpose) transpose_pattern(n, rp, ci, trp, tci, tpos);
+  if (transpose == BCS_PART_AT) transpose_pattern(n, rp, ci, trp, tci, tpos);
   const int rpl = (n + lanes - 1) / lanes;
-  const HostSchedule S = transpose ? build_schedule_jit(n, trp, tci, tpos, lanes, rpl, shapes)
-                                   : build_schedule_jit(n, rp, ci, pos0, lanes, rpl, shapes);
+  HostSchedule S;
+  if (transpose == BCS_PART_LOWER || transpose == BCS_PART_UPPER) {
+    std::vector<int> lrp, lci, lpos;
+    triangle_pattern(n, rp, ci, transpose == BCS_PART_LOWER ? 0 : 1, lrp, lci, lpos);
+    std::vector<int> ident(lci.size());
+    for (size_t q = 0; q < ident.size(); ++q) ident[q] = (int)q;
+    S = build_schedule_jit(n, lrp, lci, ident, lanes, rpl, shapes & bcs::kSchedSpan);
+    if (S.ksteps >= 0)
+      for (int32_t& e : S.ent)
+        if (!(e & bcs::kEntPad)) e = lpos[e & bcs::kEntPosMask] | (e & ~bcs::kEntPosMask);
+  } else {
+    S = transpose ? build_schedule_jit(n, trp, tci, tpos, lanes, rpl, shapes)
+                  : build_schedule_jit(n, rp, ci, pos0, lanes, rpl, shapes);
+  }
   if (S.ksteps < 0) return fail(BCS_ERR_UNSUPPORTED, "internal error: schedule check failed (lanes = %d)", lanes);
   if (steps) *steps = S.ksteps;
   if (rows_per_lane) *rows_per_lane = rpl;
@@ -1004,6 +1305,26 @@ int bcs_schedule_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const 
     if (pos) pos[q] = pad ? -1 : (S.ent[q] & bcs::kEntPosMask);
     if (col) col[q] = S.col[q];
   }
+  return BCS_OK;
+}
+
+int bcs_ilu_describe(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t lanes,
+                     int32_t* nsteps, int32_t* widths, int32_t* nwords, uint32_t* words) {
+  g_err.clear();
+  if (n <= 0 || nnz < 1 || !row_ptr || !col_idx) return fail(BCS_ERR_ARG, "bad pattern arguments");
+  if (lanes != 16 && lanes != 32 && lanes != 64) return fail(BCS_ERR_ARG, "lanes must be 16, 32 or 64");
+  const int prc = check_pattern(n, nnz, row_ptr, col_idx, true);
+  if (prc != BCS_OK) return prc;
+  std::vector<int> rp(row_ptr, row_ptr + n + 1), ci(col_idx, col_idx + nnz);
+  IluProgram prog;
+  if (!build_ilu_program(n, rp, ci, lanes, &prog))
+    return fail(BCS_ERR_UNSUPPORTED, "positions of a pattern with %d entries do not fit 16 bits", nnz);
+  if (nsteps) *nsteps = (int32_t)prog.widths.size();
+  if (nwords) *nwords = (int32_t)prog.words.size();
+  if (widths)
+    for (size_t q = 0; q < prog.widths.size(); ++q) widths[q] = prog.widths[q];
+  if (words)
+    for (size_t q = 0; q < prog.words.size(); ++q) words[q] = prog.words[q];
   return BCS_OK;
 }
 
@@ -1066,6 +1387,8 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   if (rc != BCS_OK) return rc;
   if (p->opt.shared_scalars == 1)
     return fail(BCS_ERR_UNSUPPORTED, "the adjoint is not available for shared_scalars plans");
+  if (p->opt.precond == BCS_PRECOND_ILU0)
+    return fail(BCS_ERR_UNSUPPORTED, "the adjoint is not available for ILU(0) plans");
   if (grad_kind != BCS_GRAD_A && grad_kind != BCS_GRAD_VALUES)
     return fail(BCS_ERR_ARG, "grad_kind must be BCS_GRAD_A or BCS_GRAD_VALUES");
   if (grad_gamma && p->opt.matrix_kind != BCS_J_GAMMA)
@@ -1120,9 +1443,12 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     if (rc != BCS_OK) return rc;
     for (int q = 0; q < m; ++q)
       if (plans[q] == p) return fail(BCS_ERR_ARG, "a plan appears twice (mechanisms %d and %d)", q, m);
-    if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var || p->opt.shared_scalars == 1)
+    if (p->opt.precision != BCS_FP64 || p->opt.jit != 1 || p->fwd.var || p->opt.shared_scalars == 1 ||
+        p->opt.precond == BCS_PRECOND_ILU0)
       return fail(BCS_ERR_UNSUPPORTED,
-                  "bcs_solve_multi needs FP64 plans created with jit = 1 and shared_scalars = 0 (mechanism %d)", m);
+                  "bcs_solve_multi needs FP64 plans created with jit = 1, shared_scalars = 0 and a Jacobi or no "
+                  "preconditioner (mechanism %d)",
+                  m);
     ws_off[m] = ws_need;
     ws_need += ws_bytes(ncells[m]);
     if (ncells[m] == 0) continue;

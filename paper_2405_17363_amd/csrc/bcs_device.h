@@ -313,7 +313,7 @@ struct StaticSched {
   static_assert(!SPAN || RPL >= 2, "a spanning row needs two slots");
   static constexpr int KMAX = (SEG + ...);
   // short schedules keep one address per word (no extraction on the hot path)
-  static constexpr int PACK = KMAX <= 48 ? 1 : 2, NW = (KMAX + PACK - 1) / PACK;
+  static constexpr int PACK = (KMAX <= 48 && (FLAGS & kSchedPack) == 0) ? 1 : 2, NW = (KMAX + PACK - 1) / PACK;
   __device__ explicit StaticSched(const DevSchedule&) {}
 
   // slot of step s, and whether s is the last step of its slot
@@ -349,18 +349,22 @@ struct StaticSched {
   // value, whose term starts the row's sum.  sm (SPAN): 1 on a lane whose
   // slots 0 and 1 hold one row (slot 1's sum is added into slot 0 and slot
   // 1, a padding row, ends 0), else 0.
-  template <typename T>
+  // STAGE = false: `in` is already in the operand block (every owned row,
+  // and 0 in the spare element), so the stores are skipped.
+  template <typename T, bool STAGE = true>
   __device__ __forceinline__ void spmv(const T (&a)[KMAX], uint32_t (&ad)[NW], double* xb,
                                        double* /*yb*/, int /*gl*/, const int (&rows)[RPL], const T (&in)[RPL],
                                        T (&out)[RPL], const T (&dg)[RPL], T sm) const {
     opaque_inplace<NW>(ad);
+    if constexpr (STAGE) {
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
-    wave_sync();
+      for (int j = 0; j < RPL; ++j) *(T*)(xb + rows[j]) = in[j];
+      wave_sync();
+    }
     // two accumulators per slot (even / odd steps of the slot) halve the
-    // FMA dependency chain; gathers run kGatherChunk steps ahead of the FMAs
-    // that consume them
-    constexpr int W = kGatherChunk;
+    // FMA dependency chain; gathers run kGatherChunk (kSchedWin8: 8) steps
+    // ahead of the FMAs that consume them
+    constexpr int W = (FLAGS & kSchedWin8) ? 8 : kGatherChunk;
     T acc0 = DIAG ? dg[0] * in[0] : T(0), acc1 = 0;
     T g[W];
 #pragma unroll

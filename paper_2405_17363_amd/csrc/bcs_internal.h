@@ -52,6 +52,12 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
 hipError_t launch_solve_prologue(unsigned long long* queue, const double* gamma, int64_t stride, int64_t ncells,
                                  uint32_t* state, int32_t* order, hipStream_t stream);
 
+// The ILU(0) kernel for one pattern: schedules of A, L_s and U_s (flags,
+// segment lengths, rows per lane each) and the factorisation program's step
+// widths.
+int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,
+                   const int* widths, int nstep, size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
+
 // The multi-mechanism kernel for mechanisms with the given layouts, in order.
 int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,
                      size_t lds_bytes, JitKernel* out, char* err, size_t errlen);

@@ -223,6 +223,23 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
   return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen);
 }
 
+int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,
+                   const int* widths, int nstep, size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
+  std::ostringstream src;
+  src << "// device sources " << kJitSourceHash << "\n"
+      << "#include \"bcs_ilu.h\"\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_solve_ilu0(bcs::KParams P) {\n"
+      << "  bcs::ilu_body<";
+  for (int m = 0; m < 3; ++m) {
+    sched_type(src, lanes, flags[m], seg[m], rpl[m]);
+    src << ", ";
+  }
+  src << "bcs::dev::FactProg<" << nnz;
+  for (int q = 0; q < nstep; ++q) src << ", " << widths[q];
+  src << ">>(P);\n}\n";
+  return load_source(src.str(), "bcs_solve_ilu0", true, lds_bytes, out, err, errlen);
+}
+
 int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,
                      size_t lds_bytes,
                      JitKernel* out, char* err, size_t errlen) {

@@ -8,6 +8,7 @@
 #include <stdint.h>
 #else
 using __hip_internal::int16_t;
+using __hip_internal::uint16_t;
 using __hip_internal::int32_t;
 using __hip_internal::int64_t;
 using __hip_internal::uint32_t;
@@ -67,6 +68,12 @@ constexpr int kWsOrderOffset = kWsStateOffset + kOrderStateWords * 4;
 // diagonal term, taken from the row's own operand value in registers.
 constexpr int kSchedSpan = 1;
 constexpr int kSchedDiag = 2;
+// Register-saving options (not shapes), for kernels that hold several
+// schedules: kSchedPack keeps two 16-bit gather addresses per VGPR even for
+// short schedules (one VALU operation per step, half the registers);
+// kSchedWin8 keeps 8 gathers in flight instead of kGatherChunk.
+constexpr int kSchedPack = 4;
+constexpr int kSchedWin8 = 8;
 constexpr int16_t kRowSpan = -2;
 
 struct DevSchedule {
@@ -122,7 +129,25 @@ struct KParams {
   int32_t bbase, bs, wbs;   // state blocks: start, stride, stride per wave
   int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the state block
   int32_t tbase;            // start of the schedule tables
+  // ILU(0) preconditioning (kernels compiled per pattern only).  The strict
+  // lower and strict upper parts of the factors each have their own
+  // schedule (rows dealt by their own lengths); the factorization program
+  // and the 16-bit value-position tables are copied into LDS at tbase.
+  DevSchedule schedL, schedU;
+  const uint16_t* ilu_tab;  // [KA*L | KL*L | KU*L | n + 1]: positions in the slot's factor block
+  const uint32_t* fprog;    // factorization program (see ilu_factor), fprog_words words
+  int32_t fprog_words;
+  int32_t sweeps;           // Jacobi sweeps per triangular solve
+  int32_t fs;               // slot block stride (doubles): the factor block, later the operand
 };
+
+// ILU(0) factor block of a slot: the nnz values in CSR order, then three
+// constant elements that the schedules and the factorization program use for
+// padding (positions as in the 16-bit tables).
+constexpr int kIluZero = 0;   // offset past nnz: always 0.0
+constexpr int kIluUnit = 1;   // always 1.0 (divisor of ops on the upper part)
+constexpr int kIluJunk = 2;   // target of padding ops
+constexpr int kIluSpare = 3;  // elements after the nnz values
 
 // Arguments of a multi-mechanism launch.
 constexpr int kMaxMech = 8;
