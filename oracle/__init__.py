@@ -14,6 +14,7 @@ Functions (all take/return numpy arrays):
   mixed_batch   FP32 inner BiCGStab + FP64 refinement      -> x, iters, refinements, resid, status
   solve_groups  Block-cells (N): runs of cells solved as one block-diagonal system -> x, iters, resid, status
   form_a        A = I - gamma*J on the pattern
+  assemble      mass-action rates f and Jacobian J per cell   -> f, J
 """
 from __future__ import annotations
 
@@ -74,6 +75,8 @@ def _load():
     lib.oracle_mixed_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _vp, _dbl, _int, _dbl,
                                        _int, _int, _D, _I, _I, _D, _I, _int]
     lib.oracle_mixed_batch.restype = None
+    lib.oracle_assemble.argtypes = [_i64, _int, _int, _I, _I, _D, _i64, _I, _I, _D, _vp, _vp]
+    lib.oracle_assemble.restype = _int
     _F = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
     lib.oracle_solve_batch_f.argtypes = [_i64, _int, _int, _I, _I, _F, _F, _dbl, _int, _int, _int, _int, _F, _I, _D,
                                          _I]
@@ -271,6 +274,31 @@ def mixed_batch(row_ptr, col_idx, values, gamma, b, rtol=1e-10, maxit=200, inner
                                float(inner_rtol), int(max_refine), int(budget == "cell"), x, iters, refin, resid,
                                status, int(nthreads))
     return x, iters, refin, resid, status
+
+
+def assemble(reactants, products, k, row_ptr, col_idx, y):
+    """Mass-action rates f [C, n] and Jacobian J [C, nnz] on the pattern for concentrations y [C, n].
+
+    reactants, products: [R, 2] species indices (-1 = none); k: [R] rate constants shared by every cell, or
+    [C, R] per cell."""
+    reac = np.ascontiguousarray(np.asarray(reactants).reshape(-1, 2), dtype=np.int32)
+    prod = np.ascontiguousarray(np.asarray(products).reshape(-1, 2), dtype=np.int32)
+    R = reac.shape[0]
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n, nnz = rp.shape[0] - 1, ci.shape[0]
+    yy = np.ascontiguousarray(np.atleast_2d(y), dtype=np.float64)
+    C = yy.shape[0]
+    kk = np.ascontiguousarray(k, dtype=np.float64)
+    ks = 0 if kk.ndim == 1 else R
+    if kk.size != (R if ks == 0 else C * R):
+        raise ValueError("k must have shape [R] or [C, R]")
+    f = np.zeros((C, n))
+    J = np.zeros((C, nnz))
+    rc = _load().oracle_assemble(C, n, R, reac, prod, kk.ravel(), ks, rp, ci, yy, f.ctypes.data, J.ctypes.data)
+    if rc:
+        raise ValueError(f"reaction {rc - 1} needs an entry the pattern lacks")
+    return f, J
 
 
 def form_a(row_ptr, col_idx, J, gamma):

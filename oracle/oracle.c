@@ -15,6 +15,8 @@
  *   oracle_adjoint_batch  lambda = A^-T g by BiCGStab on A^T, and the pattern
  *                      gradient dL/dA_ij = -lambda_i x_j
  *   oracle_mixed_batch FP32 inner BiCGStab + FP64 residual and refinement
+ *   oracle_assemble    mass-action rates f and Jacobian J of every cell (the
+ *                      inputs the linear solve needs, Section 2.2)
  * Readings of the paper taken here are listed in bicgstab_body.h and above
  * each function.
  */
@@ -369,4 +371,89 @@ void oracle_mixed_batch(int64_t ncells, int n, int nnz, const int* rp, const int
     }
     free(A); free(A32); free(dg); free(r); free(xn); free(rn_v); free(r32); free(d32); free(w32);
   }
+}
+
+/* Mass-action rates and their Jacobian, per cell (the chemistry of Section
+ * 2.2: the rate of change of each species is a sum over reactions, and the
+ * BDF step needs the Jacobian of that rate function).  Reaction r consumes
+ * reactants reac[2r] and reac[2r+1] (-1 = none) and makes products
+ * prod[2r], prod[2r+1] (-1 = none) at the mass-action rate
+ *   w_r = k_r y_a            (one reactant a)
+ *   w_r = (k_r y_a) y_b      (two reactants a, b; a == b allowed)
+ * with k_r = k[c * k_stride + r] (k_stride 0: one set for every cell).
+ * f_i = sum_r S_ir w_r, S_ir = (times i is a product) - (times i is a
+ * reactant); J_ij = d f_i / d y_j = sum_r S_ir d w_r / d y_j with
+ *   d w / d y_a = k_r               (one reactant)
+ *   d w / d y_a = k_r y_b, d w / d y_b = k_r y_a   (a != b)
+ *   d w / d y_a = 2 (k_r y_a)       (a == b).
+ * Reactions are taken in order and, within one, the species in the order
+ * reactants then products, each species once; J is written on the CSR
+ * pattern (rp, ci).  f or J may be NULL.  Returns 0, or 1 + r if reaction r
+ * needs an entry the pattern lacks (nothing is then guaranteed). */
+int oracle_assemble(int64_t ncells, int n, int R, const int* reac, const int* prod, const double* k,
+                    int64_t k_stride, const int* rp, const int* ci, const double* y, double* f, double* J) {
+  int nnz = rp[n];
+  for (int64_t c = 0; c < ncells; ++c) {
+    const double* yc = y + c * n;
+    if (f)
+      for (int i = 0; i < n; ++i) f[c * n + i] = 0.0;
+    if (J)
+      for (int q = 0; q < nnz; ++q) J[c * nnz + q] = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double kr = k[c * k_stride + r];
+      int a = reac[2 * r], b = reac[2 * r + 1];
+      /* species of the reaction with their net stoichiometry */
+      int sp[4], ns = 0;
+      double st[4];
+      int all[4] = {reac[2 * r], reac[2 * r + 1], prod[2 * r], prod[2 * r + 1]};
+      for (int q = 0; q < 4; ++q) {
+        if (all[q] < 0) continue;
+        double d = q < 2 ? -1.0 : 1.0;
+        int found = -1;
+        for (int u = 0; u < ns; ++u)
+          if (sp[u] == all[q]) found = u;
+        if (found < 0) {
+          sp[ns] = all[q];
+          st[ns] = d;
+          ++ns;
+        } else {
+          st[found] += d;
+        }
+      }
+      double w = kr * yc[a];
+      if (b >= 0) w = w * yc[b];
+      /* derivative of w by each reactant */
+      int dj[2];
+      double dw[2];
+      int nd = 0;
+      if (b < 0) {
+        dj[0] = a;
+        dw[0] = kr;
+        nd = 1;
+      } else if (a == b) {
+        dj[0] = a;
+        dw[0] = 2.0 * (kr * yc[a]);
+        nd = 1;
+      } else {
+        dj[0] = a;
+        dw[0] = kr * yc[b];
+        dj[1] = b;
+        dw[1] = kr * yc[a];
+        nd = 2;
+      }
+      for (int u = 0; u < ns; ++u) {
+        int i = sp[u];
+        if (f) f[c * n + i] = f[c * n + i] + st[u] * w;
+        if (!J) continue;
+        for (int v = 0; v < nd; ++v) {
+          int pos = -1;
+          for (int q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] == dj[v]) pos = q;
+          if (pos < 0) return 1 + r;
+          J[c * nnz + pos] = J[c * nnz + pos] + st[u] * dw[v];
+        }
+      }
+    }
+  }
+  return 0;
 }

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from oracle import BREAKDOWN, CONVERGED, MAXIT, NONFINITE, A_DIRECT, J_GAMMA
-from workload import config_inputs
+from workload import config_inputs, gen_cells, gen_mechanism
 
 RNG = np.random.default_rng(20240527)
 
@@ -745,3 +745,87 @@ def test_ilu_preconditioned_solves_match_lu_with_far_fewer_iterations():
         rlu = np.linalg.norm(cells["b"][c] - A @ xl[c]) / np.linalg.norm(cells["b"][c])
         err = np.linalg.norm(x[c] - xl[c]) / np.linalg.norm(xl[c])
         assert err <= max(1e-8, 4 * kappa * max(res[c], rlu))
+
+
+# ------------------------------------------- mass-action rates and Jacobian ----
+# The oracle's assembly (oracle_assemble) is pinned by a hand-computed
+# example, by the generator's independent Python implementation
+# (workload.rates / workload.jacobian_values), by the mechanism's structural
+# invariants (molecule count conserved: zero column sums of J and zero sum of
+# f; no autocatalysis: J_ii <= 0) and by central differences of f, which are
+# exact up to rounding because f is at most quadratic in y.
+
+def test_assemble_hand_example():
+    # species 0, 1, 2: 0 -> 1 (k = 2); 0 + 1 -> 2 + 2 (k = 3); 2 + 2 -> 0 + 1 (k = 5)
+    reac = [[0, -1], [0, 1], [2, 2]]
+    prod = [[1, -1], [2, 2], [0, 1]]
+    rp = np.array([0, 3, 6, 9], np.int32)
+    ci = np.array([0, 1, 2] * 3, np.int32)
+    y = np.array([[1.0, 2.0, 3.0]])
+    f, J = oracle.assemble(reac, prod, [2.0, 3.0, 5.0], rp, ci, y)
+    # w = 2 * 1, 3 * 1 * 2, 5 * 3 * 3 = 2, 6, 45
+    assert f.tolist() == [[-2 - 6 + 45, 2 - 6 + 45, 2 * 6 - 2 * 45]]
+    # dw0/dy0 = 2; dw1/dy0 = 3 y1 = 6, dw1/dy1 = 3 y0 = 3; dw2/dy2 = 2 * 5 * y2 = 30
+    assert J.reshape(3, 3).tolist() == [[-8, -3, 30], [-4, -3, 30], [12, 6, -60]]
+
+
+@pytest.mark.parametrize("n,R", [(30, 50), (80, 150), (200, 400)])
+def test_assemble_matches_the_generator(n, R):
+    m = gen_mechanism(n, R)
+    y = gen_cells(m, 40, 11)["y"]
+    f, J = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, y)
+    from workload import jacobian_values, rates
+    assert np.array_equal(J, jacobian_values(m, y))
+    fr = rates(m, y)
+    assert np.all(np.abs(f - fr) <= 1e-14 * np.abs(fr) + 1e-300)
+
+
+@pytest.mark.parametrize("n,R", [(30, 50), (80, 150)])
+def test_assemble_invariants(n, R):
+    m = gen_mechanism(n, R)
+    y = gen_cells(m, 40, 12)["y"]
+    f, J = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, y)
+    rows = np.repeat(np.arange(n), np.diff(m.row_ptr))
+    colsum = np.zeros((40, n))
+    colabs = np.zeros((40, n))
+    np.add.at(colsum.T, m.col_idx, J.T)
+    np.add.at(colabs.T, m.col_idx, np.abs(J).T)
+    u = np.finfo(np.float64).eps / 2
+    assert np.all(np.abs(colsum) <= 64 * u * colabs)
+    assert np.all(np.abs(f.sum(1)) <= 1e-12 * np.abs(f).sum(1))
+    assert np.all(J[:, rows == m.col_idx] <= 0)
+
+
+def test_assemble_central_differences_are_exact_up_to_rounding():
+    m = gen_mechanism(30, 50)
+    y = gen_cells(m, 3, 13)["y"]
+    f, J = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, y)
+    Jd = np.stack([oracle.to_dense(m.row_ptr, m.col_idx, J[c]) for c in range(3)])
+    for j in range(m.n):
+        h = 1e-3 * y[:, j]
+        yp, ym = y.copy(), y.copy()
+        yp[:, j] += h
+        ym[:, j] -= h
+        fp, _ = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, yp)
+        fm, _ = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, ym)
+        cd = (fp - fm) / (2 * h[:, None])
+        scale = (np.abs(fp) + np.abs(fm) + np.abs(f)).max(1, keepdims=True) / h[:, None]
+        assert np.all(np.abs(cd - Jd[:, :, j]) <= 1e-12 * scale + 1e-9 * np.abs(Jd[:, :, j]))
+
+
+def test_assemble_per_cell_rate_constants():
+    m = gen_mechanism(30, 50)
+    y = gen_cells(m, 4, 14)["y"]
+    f1, J1 = oracle.assemble(m.reactants, m.products, m.k, m.row_ptr, m.col_idx, y)
+    kc = np.stack([m.k * 2.0 ** c for c in range(4)])  # power-of-two scaling is exact
+    f2, J2 = oracle.assemble(m.reactants, m.products, kc, m.row_ptr, m.col_idx, y)
+    for c in range(4):
+        assert np.array_equal(f2[c], f1[c] * 2.0 ** c) and np.array_equal(J2[c], J1[c] * 2.0 ** c)
+
+
+def test_assemble_rejects_a_pattern_without_the_entries():
+    m = gen_mechanism(30, 50)
+    rp = np.arange(31, dtype=np.int32)  # diagonal only
+    ci = np.arange(30, dtype=np.int32)
+    with pytest.raises(ValueError):
+        oracle.assemble(m.reactants, m.products, m.k, rp, ci, np.ones((1, 30)))
