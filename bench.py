@@ -28,8 +28,11 @@ METRIC = "cell-systems solved/s at rel. residual 1e-10, 100k cells (FP64 vs FP32
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 FP64_VALU_PEAK = 78.6     # MI355X FP64 vector, TFLOP/s
 LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12  # 128 B per clock per CU, 256 CUs, 2.4 GHz: 78.6 TB/s
+FP32_VALU_PEAK = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
+FP32_UNPACKED_PEAK = 78.6  # FP32 vector without packed instructions (what the kernels issue), TFLOP/s
 RTOL = 1e-10
 MAXIT = 200
+FORMS = ("mixed", "adjoint", "multi", "block", "ilu0", "assemble", "small", "peaks")
 
 
 def parse():
@@ -41,14 +44,20 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ncells", type=int, default=100_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refine form")
-    ap.add_argument("--no-forms", action="store_true", help="skip the adjoint and multi-mechanism timings")
+    ap.add_argument("--forms", default="all",
+                    help="comma list of the forms timed beside the headline solve: " + ",".join(FORMS) +
+                         ", or 'all' / 'none'")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--cell-order", type=int, default=1, choices=(0, 1),
                     help="1: cells handed out in the cost order (sorted by gamma on the device each step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer (reference for HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.forms = set(FORMS) if a.forms == "all" else set() if a.forms == "none" else set(a.forms.split(","))
+    unknown = a.forms - set(FORMS)
+    if unknown:
+        ap.error("unknown forms: " + ",".join(sorted(unknown)))
+    return a
 
 
 def algorithmic_bytes_per_cell(n: int, nnz: int) -> int:
@@ -62,6 +71,54 @@ def flops_per_cell(n: int, nnz: int, iters: np.ndarray, status: np.ndarray) -> f
     # true-residual check = about 3 nnz + 7 n + (2 nnz + 3 n) per confirmation
     it = iters.astype(np.float64)
     return float(np.sum(it * (4 * nnz + 24 * n) + (5 * nnz + 10 * n)))
+
+
+def roofline(kernel: str, seconds: float, hbm_bytes: float, flops: float, lds_bytes: float,
+             valu_peak: float = FP64_VALU_PEAK, traffic=None, **extra) -> dict:
+    """Fractions of the three ceilings the solve can exhaust (HBM bytes,
+    vector FLOPs, LDS operand gathers) for one launch's algorithmic work over
+    its measured duration; `bound` is the binding one, the largest fraction."""
+    ach = {"hbm": hbm_bytes / seconds / 1e9, "alu": flops / seconds / 1e12, "lds": lds_bytes / seconds / 1e12}
+    peak = {"hbm": HBM_PEAK_GBS, "alu": valu_peak, "lds": LDS_PEAK_TBS}
+    unit = {"hbm": "GB/s", "alu": "TFLOP/s", "lds": "TB/s"}
+    frac = {k: ach[k] / peak[k] for k in ach}
+    bound = max(frac, key=frac.get)
+    out = {"bound": bound, "achieved": round(ach[bound], 3), "peak": peak[bound], "unit": unit[bound],
+           "frac": round(frac[bound], 4), "traffic": traffic, "kernel": kernel,
+           "avg_launch_ms": round(seconds * 1e3, 4),
+           "hbm_gbs": round(ach["hbm"], 2), "hbm_frac": round(frac["hbm"], 4),
+           "valu_tflops": round(ach["alu"], 3), "valu_peak": valu_peak, "valu_frac": round(frac["alu"], 4),
+           "lds_gather_tbs": round(ach["lds"], 2), "lds_gather_frac": round(frac["lds"], 4),
+           "algorithmic_bytes_per_launch": hbm_bytes, "algorithmic_flops_per_launch": flops,
+           "lds_gather_bytes_per_launch": lds_bytes}
+    out.update(extra)
+    return out
+
+
+def ilu_counts(row_ptr, col_idx):
+    """Entries of the strict lower and upper triangles of the pattern, and the
+    flops of one ILU(0) factorisation on it (IKJ: a division per lower entry,
+    an FMA per update a_ij -= l_ik u_kj with (i, j) in the pattern)."""
+    n = len(row_ptr) - 1
+    rows = [set(col_idx[row_ptr[i]:row_ptr[i + 1]].tolist()) for i in range(n)]
+    zl = sum(1 for i in range(n) for j in rows[i] if j < i)
+    zu = sum(1 for i in range(n) for j in rows[i] if j > i)
+    fl = 0
+    for i in range(n):
+        for k in sorted(j for j in rows[i] if j < i):
+            fl += 1 + 2 * sum(1 for j in rows[k] if j > k and j in rows[i])
+    return zl, zu, fl
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -125,8 +182,6 @@ def main():
     avg_launch_s = float(np.mean(kern_ms)) * 1e-3
     bytes_launch = algorithmic_bytes_per_cell(n, nnz) * C
     flops_launch = flops_per_cell(n, nnz, iters, status)
-    hbm_gbs = bytes_launch / avg_launch_s / 1e9
-    valu_tfs = flops_launch / avg_launch_s / 1e12
     info = plan.info()
 
     # HBM bytes per launch from the committed counter summary, used only while
@@ -141,32 +196,29 @@ def main():
                 and tr.get("lanes_per_cell") == info["lanes_per_cell"]):
             traffic = round(tr["hbm_bytes_per_launch"])
 
-    fracs = {"hbm": hbm_gbs / HBM_PEAK_GBS, "alu": valu_tfs / FP64_VALU_PEAK}
     # on-chip operand gathers: every stored entry gathers one FP64 operand per
     # SpMV (two per iteration, one for staging's column scaling, one for the
     # true residual)
     lds_bytes = float(np.sum(iters.astype(np.float64) * 16 * nnz + 16 * nnz))
-    lds_tbs = lds_bytes / avg_launch_s / 1e12
-    bound = max(fracs, key=fracs.get)
-    roofline = {
-        "bound": bound,
-        "achieved": round(hbm_gbs if bound == "hbm" else valu_tfs, 3),
-        "peak": HBM_PEAK_GBS if bound == "hbm" else FP64_VALU_PEAK,
-        "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
-        "frac": round(fracs[bound], 4),
-        "traffic": traffic,
-        "kernel": "bcs_solve_fp64 (%d lanes/cell, %d rows/lane, %d steps/lane)" % (
+    roofline_obj = roofline(
+        "bcs_solve_fp64 (%d lanes/cell, %d rows/lane, %d steps/lane)" % (
             info["lanes_per_cell"], info["rows_per_lane"], info["steps_per_lane"]),
-        "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-        "hbm_gbs": round(hbm_gbs, 2),
-        "hbm_frac": round(fracs["hbm"], 4),
-        "fp64_tflops": round(valu_tfs, 3),
-        "fp64_frac": round(fracs["alu"], 4),
-        "algorithmic_bytes_per_launch": bytes_launch,
-        "algorithmic_flops_per_launch": flops_launch,
-        "lds_gather_tbs": round(lds_tbs, 2),
-        "lds_gather_frac": round(lds_tbs / LDS_PEAK_TBS, 4),
-    }
+        avg_launch_s, bytes_launch, flops_launch, lds_bytes, traffic=traffic)
+
+    # the same launch after a 1 GiB scratch write (no input left in the L2 or
+    # the Infinity Cache): per-call event times only, not the headline
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    flushed = []
+    for _ in range(min(args.steps, 10)):
+        scratch.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        flushed.append(e0.elapsed_time(e1))
+    del scratch
+    roofline_obj["avg_launch_ms_after_cache_flush"] = round(float(np.mean(flushed)), 4)
 
     # Unsolved cells whose FP64 evaluation floor is above rtol: the relative
     # residual of their dense-LU solution (numpy, FP64) exceeds rtol / 2, so
@@ -212,7 +264,21 @@ def main():
             msolved = int(np.sum((mst == 0) & (mres <= RTOL)))
             both = (mst == 0) & (status == 0)
             err = np.linalg.norm(mx[both] - x[both], axis=1) / np.linalg.norm(x[both], axis=1)
-            return {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4),
+            # FP32 inner iterations (two SpMVs, six reductions, four updates) plus
+            # FP64 work: staging (form A, scale, cast) and per refinement the
+            # residual b - A x, its norm and the update x += ||r|| D^-1 d
+            mi = mit.astype(np.float64)
+            mr = mref.astype(np.float64)
+            f32 = float(np.sum(mi * (4 * nnz + 24 * n)))
+            f64 = float(np.sum(mr * (2 * nnz + 8 * n) + (4 * nnz + 6 * n)))
+            # gathers: 4-byte FP32 operands in the inner solve, 8-byte FP64 in
+            # the residual of every refinement and in staging's scaling
+            mlds = float(np.sum(mi * 8 * nnz + mr * 8 * nnz + 8 * nnz))
+            mroof = roofline("bcs_solve_mixed (%d lanes/cell)" % mplan.info()["lanes_per_cell"], mms * 1e-3,
+                             algorithmic_bytes_per_cell(n, nnz) * C, f32 + f64, mlds, valu_peak=FP32_VALU_PEAK,
+                             fp32_flops_per_launch=f32, fp64_flops_per_launch=f64,
+                             valu_frac_unpacked=round((f32 + f64) / (mms * 1e-3) / 1e12 / FP32_UNPACKED_PEAK, 4))
+            return {"value": round(msolved / (mms * 1e-3), 1), "ms_per_step": round(mms, 4), "roofline": mroof,
                     "refine_budget": budget, "lanes_per_cell": mplan.info()["lanes_per_cell"],
                     "solved_fraction": round(msolved / C, 5), "iters_mean": round(float(mit.mean()), 2),
                     "refinements_mean": round(float(mref.mean()), 3),
@@ -224,7 +290,7 @@ def main():
             return {"error": str(e)}
 
     mixed = mixed_cell = None
-    if not args.no_mixed:
+    if "mixed" in args.forms:
         mixed = mixed_form("inner")
         mixed_cell = mixed_form("cell")
 
@@ -241,7 +307,7 @@ def main():
         return e0.elapsed_time(e1) / steps
 
     adjoint = multi = block_cells = None
-    if not args.no_forms:
+    if "adjoint" in args.forms:
         # adjoint of the same batch: lambda = A^-T g (g ~ N(0,1)), dL/dA on the pattern
         g_host = np.random.default_rng(7).standard_normal((C, n))
         g = torch.as_tensor(g_host, device=dev)
@@ -261,7 +327,15 @@ def main():
                    "unsolved_floor_limited": floor_limited_count(np.nonzero(~((ast == 0) & (ares <= RTOL)))[0],
                                                                  g_host, transpose=True),
                    "algorithmic_bytes_per_cell": 16 * nnz + 24 * n + 32}
+        ait = res_adj["r"][3].cpu().numpy().astype(np.float64)
+        adjoint["roofline"] = roofline(
+            "bcs_solve_adjoint (%d lanes/cell)" % info["lanes_per_cell"], ams * 1e-3,
+            (16 * nnz + 24 * n + 32) * C,
+            # the transposed solve's iterations and staging, then dL/dA = -lambda_i x_j
+            float(np.sum(ait * (4 * nnz + 24 * n) + (5 * nnz + 10 * n) + nnz)),
+            float(np.sum(ait * 16 * nnz + 16 * nnz)))
         del g, xf, res_adj
+    if "multi" in args.forms:
         # three mechanisms (n = 30 / 80 / 200, 12.5k / 25k / 12.5k cells) in one persistent launch,
         # against the same cells solved by one launch per mechanism
         mechs = config_inputs(4)
@@ -288,12 +362,20 @@ def main():
         ems = timed(mstep_each, args.steps)
         mc = sum(int(v.shape[0]) for v in MV)
         msolved = sum(int(np.sum((r[3].cpu().numpy() == 0) & (r[2].cpu().numpy() <= RTOL))) for r in res_m["r"])
+        mbytes = sum(algorithmic_bytes_per_cell(m.n, m.nnz) * int(v.shape[0]) for (m, _), v in zip(mechs, MV))
+        mflops = sum(flops_per_cell(m.n, m.nnz, r[1].cpu().numpy(), r[3].cpu().numpy())
+                     for (m, _), r in zip(mechs, res_m["r"]))
+        mlds = sum(float(np.sum(r[1].cpu().numpy().astype(np.float64) * 16 * m.nnz + 16 * m.nnz))
+                   for (m, _), r in zip(mechs, res_m["r"]))
         multi = {"value": round(msolved / (mms * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(mms, 4),
+                 "roofline": roofline("bcs_solve_multi (%s lanes/cell)" % "/".join(
+                     str(pl.info()["lanes_per_cell"]) for pl in mplans), mms * 1e-3, mbytes, mflops, mlds),
                  "ncells": mc, "solved_fraction": round(msolved / mc, 5),
                  "ms_one_launch_per_mechanism": round(ems, 4),
                  "lanes_per_cell": [pl.info()["lanes_per_cell"] for pl in mplans],
                  "lanes_per_cell_one_launch_per_mechanism": [pl.info()["lanes_per_cell"] for pl in eplans]}
         del MV, MG, MB, res_m
+    if "block" in args.forms:
         # Block-cells (N) of Section 3 against Block-cells (1) on the same batch: the cells of a wave
         # (64 / lanes consecutive cells) solved as one block-diagonal system with shared scalars
         block_cells = []
@@ -326,6 +408,102 @@ def main():
             row["bc1"].pop("_iters")
             block_cells.append(row)
 
+    # ILU(0) right preconditioning (the stronger preconditioner the paper
+    # names as its next optimisation) on the same 100k cells
+    ilu = None
+    if "ilu0" in args.forms:
+        try:
+            iplan = bcs.Plan(mech.row_ptr, mech.col_idx, precond="ilu0", cell_order=bool(args.cell_order))
+            iplan.autotune(values, gamma, b, RTOL, MAXIT)
+            iout = [torch.empty_like(o) for o in out]
+
+            def istep():
+                bcs.solve_batch(iplan, values, gamma, b, RTOL, MAXIT, out=iout, workspace=ws)
+
+            ims = timed(istep, args.steps)
+            ix, iit, ires, ist, _ = [t.cpu().numpy() for t in iout]
+            isolved = int(np.sum((ist == 0) & (ires <= RTOL)))
+            zl, zu, ffl = ilu_counts(mech.row_ptr, mech.col_idx)
+            sw = iplan.options.ilu_sweeps
+            ii = iit.astype(np.float64)
+            # per iteration: two SpMVs with A, two applications of (LU)^-1 by
+            # `sw` sweeps per triangle, six reductions and four updates; per
+            # cell: forming A, the factorisation and the true residual
+            per_it = 4 * nnz + 24 * n + 2 * (sw * (2 * zl + n) + n + sw * (2 * zu + n))
+            iflops = float(np.sum(ii * per_it + ffl + 5 * nnz + 10 * n))
+            ilds = float(np.sum(ii * 8 * (2 * nnz + 2 * sw * (zl + zu)) + 8 * (zl + zu + nnz)))
+            both = (ist == 0) & (status == 0)
+            err = np.linalg.norm(ix[both] - x[both], axis=1) / np.linalg.norm(x[both], axis=1)
+            ilu = {"value": round(isolved / (ims * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(ims, 4),
+                   "solved_fraction": round(isolved / C, 5), "iters_mean": round(float(iit.mean()), 2),
+                   "iters_p99": float(np.percentile(iit, 99)), "iters_max": int(iit.max()), "sweeps": sw,
+                   "lanes_per_cell": iplan.info()["lanes_per_cell"],
+                   "unsolved_floor_limited": floor_limited_count(np.nonzero(~((ist == 0) & (ires <= RTOL)))[0],
+                                                                 cells["b"]),
+                   "rel_diff_vs_jacobi_max": float(err.max()) if err.size else None,
+                   "roofline": roofline("bcs_solve_ilu0 (%d lanes/cell, %d sweeps)" % (
+                       iplan.info()["lanes_per_cell"], sw), ims * 1e-3, bytes_launch, iflops, ilds)}
+            del iplan, iout
+        except bcs.BcsError as e:
+            ilu = {"error": str(e)}
+
+    # mass-action rates and Jacobian of the 100k cells assembled on the device
+    # (the inputs of the solve), an HBM-streaming kernel
+    assemble = None
+    if "assemble" in args.forms:
+        M = bcs.Mechanism(mech.n, mech.reactants, mech.products, mech.row_ptr, mech.col_idx)
+        y = torch.as_tensor(cells["y"], device=dev)
+        kk = torch.as_tensor(mech.k, device=dev)
+        fo = torch.empty((C, n), dtype=torch.float64, device=dev)
+        Jo = torch.empty((C, nnz), dtype=torch.float64, device=dev)
+
+        def asm_step():
+            bcs.assemble(M, y, kk, out=(fo, Jo))
+
+        ams_a = timed(asm_step, args.steps)
+        same_j = bool(torch.equal(Jo, values))
+        abytes = float(C * (8 * n + 8 * n + 8 * nnz) + 8 * mech.R)
+        terms = len(mech.term_pos)
+        assemble = {"ms_per_step": round(ams_a, 4), "cells_per_s": round(C / (ams_a * 1e-3), 1),
+                    "jacobian_equals_generated": same_j,
+                    "roofline": roofline("bcs_assemble", ams_a * 1e-3, abytes,
+                                         float(C * (3 * terms + 2 * mech.R)), 0.0)}
+        del y, kk, fo, Jo, M
+
+    # the small configurations: 100 cells (latency) and 10,000 cells (the
+    # paper's cell count; its 77 MB fit the Infinity Cache)
+    small = {}
+    if "small" in args.forms:
+        for cfg in (1, 2):
+            m1, c1 = config_inputs(cfg)[0]
+            V1, G1, B1 = (torch.as_tensor(c1[k], device=dev) for k in ("values", "gamma", "b"))
+            p1 = bcs.Plan(m1.row_ptr, m1.col_idx, precond="jacobi")
+            p1.autotune(V1, G1, B1, RTOL, MAXIT)
+            o1 = [torch.empty((V1.shape[0], m1.n), dtype=torch.float64, device=dev)] + [
+                torch.empty(V1.shape[0], dtype=dt, device=dev)
+                for dt in (torch.int32, torch.float64, torch.int32, torch.int32)]
+            w1 = p1.workspace(V1.shape[0], dev)
+
+            def s1(p1=p1, V1=V1, G1=G1, B1=B1, o1=o1, w1=w1):
+                bcs.solve_batch(p1, V1, G1, B1, RTOL, MAXIT, out=o1, workspace=w1)
+
+            reps = 200 if cfg == 1 else args.steps
+            t1 = timed(s1, reps)
+            st1, rs1, it1 = o1[3].cpu().numpy(), o1[2].cpu().numpy(), o1[1].cpu().numpy()
+            sv1 = int(np.sum((st1 == 0) & (rs1 <= RTOL)))
+            small["config%d" % cfg] = {
+                "ncells": int(V1.shape[0]), "us_per_call": round(t1 * 1e3, 2),
+                "value": round(sv1 / (t1 * 1e-3), 1), "unit": "cells/s",
+                "solved_fraction": round(sv1 / V1.shape[0], 5), "iters_mean": round(float(it1.mean()), 2),
+                "iters_max": int(it1.max()), "lanes_per_cell": p1.info()["lanes_per_cell"]}
+            del V1, G1, B1, p1, o1, w1
+
+    peaks = None
+    if "peaks" in args.forms:
+        from paper_2405_17363_amd.profiling import measure_peaks
+
+        peaks = measure_peaks()
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -351,7 +529,18 @@ def main():
         csolved = int(np.sum((ci_st == 0) & (ci_res <= RTOL)))
         cpu = {"value": round(csolved / tcpu, 1), "unit": "cells/s", "cores": nthreads, "kind": "oracle",
                "sample": f"first {S} of the {C} cells, FP64 BiCGStab + Jacobi, OpenMP static over cells, "
-                         f"median of {len(times)} runs of {tcpu:.2f} s"}
+                         f"median of {len(times)} runs of {tcpu:.2f} s",
+               "cpu_model": cpu_model()}
+        # one thread, on a prefix sized for about 5 s
+        S1 = max(200, int(S0 * 5.0 / max(pilot * nthreads, 1e-6)))
+        S1 = min(S1, C)
+        t1 = time.perf_counter()
+        _, c1_it, c1_res, c1_st = oracle.solve_batch(mech.row_ptr, mech.col_idx, cells["values"][:S1],
+                                                     cells["gamma"][:S1], cells["b"][:S1], RTOL, MAXIT,
+                                                     precond=1, nthreads=1)
+        t1 = time.perf_counter() - t1
+        cpu["one_thread"] = {"value": round(int(np.sum((c1_st == 0) & (c1_res <= RTOL))) / t1, 1),
+                             "unit": "cells/s", "cores": 1, "sample": f"first {S1} cells, one run of {t1:.2f} s"}
 
     line = {
         "metric": METRIC,
@@ -375,12 +564,16 @@ def main():
         "iters_max": int(iters.max()),
         "status_counts": np.bincount(status, minlength=4).tolist(),
         "unsolved_floor_limited": floor_limited,
-        "roofline": roofline,
+        "roofline": roofline_obj,
         "fp32_refine": mixed,
         "fp32_refine_cell_budget": mixed_cell,
         "adjoint": adjoint,
         "multi_mechanism": multi,
         "block_cells_n": block_cells,
+        "ilu0": ilu,
+        "assemble": assemble,
+        "small_configs": small,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -345,6 +345,46 @@ int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* nce
                        double rtol, int32_t maxit, double* const* x, int32_t* const* iters, double* const* resid,
                        int32_t* const* status, int32_t* lanes_out);
 
+/* ---- Mass-action rates and Jacobian on the device ----
+ * The inputs of the solve for a mechanism of elementary reactions (the
+ * per-cell rate equations of Section 2.1; Section 6 names moving the rest of
+ * the BDF step onto the GPU as the next step).  Reaction r has reactants
+ * reactants[2r] (required) and reactants[2r+1] (-1 = none; equal to the first
+ * for A + A) and products products[2r], products[2r+1] (-1 = none).  It runs
+ * at w_r = k_r y_a (one reactant) or (k_r y_a) y_b (two).  Per cell,
+ *   f_i  = sum_r S_ir w_r                       (S_ir = products - reactants)
+ *   J_ij = sum_r S_ir dw_r/dy_j  on the pattern (CSR order), with
+ *          dw/dy_a = k_r (one reactant); k_r y_b, k_r y_a (a != b); 2 (k_r y_a) (a == b).
+ * Every sum is taken over reactions in increasing order, one rounding per
+ * term (S_ir times the rounded derivative or rate is exact). */
+typedef struct bcs_mechanism bcs_mechanism; /* opaque, immutable */
+
+/* Build a mechanism's gather tables for a pattern (HOST arrays: row_ptr[n+1],
+ * col_idx[nnz] as in bcs_plan_create, reactants/products [nreact, 2] int32)
+ * and copy them to the current device.  n < 65535.  BCS_ERR_PATTERN if the
+ * pattern is malformed or lacks an entry (i, j) that a reaction's J needs
+ * (every species i of the reaction against each of its reactants j);
+ * BCS_ERR_ARG for species out of range.  Validation happens on the host,
+ * before any device call.  On error *out is NULL. */
+int bcs_mechanism_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx, int32_t nreact,
+                         const int32_t* reactants, const int32_t* products, bcs_mechanism** out);
+
+/* Release a mechanism (NULL allowed); no assembly may still be running. */
+void bcs_mechanism_destroy(bcs_mechanism* mech);
+
+/* f and J of every cell on `stream`:
+ *   y [ncells, n]          device FP64 concentrations
+ *   k                      device FP64 rate constants: k_r of cell c at
+ *                          k[c * k_stride + r]; k_stride 0 = one set shared by
+ *                          every cell, else >= nreact
+ *   f [ncells, n]          device FP64 out, or NULL
+ *   J [ncells, nnz]        device FP64 out (the values a J_GAMMA solve takes),
+ *                          or NULL
+ * Allocates nothing.  BCS_ERR_UNSUPPORTED if the mechanism's tables do not
+ * fit a workgroup's LDS (64 KiB, about 9,000 reaction-entry terms). */
+int bcs_assemble(const bcs_mechanism* mech, int64_t ncells, const double* y, const double* k, int64_t k_stride,
+                 double* f, double* J, void* stream);
+
 /* Description of the last error on this thread ("" if none). */
 const char* bcs_last_error(void);
 

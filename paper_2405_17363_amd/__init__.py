@@ -37,7 +37,9 @@ from ._binding import (  # noqa: F401
     BcsError,
     BatchedSolve,
     BatchedSolveWarning,
+    Mechanism,
     Plan,
+    assemble,
     exported_symbols,
     ilu_describe,
     lib,

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes
+import glob
 import os
 import re
 import threading
@@ -103,6 +104,20 @@ def lib():
         L.bcs_schedule_describe.restype = ctypes.c_int
         L.bcs_ilu_describe.argtypes = [I32, I32, P, P, I32, P, P, P, P]
         L.bcs_ilu_describe.restype = ctypes.c_int
+        L.bcs_mechanism_create.argtypes = [I32, I32, P, P, I32, P, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.bcs_mechanism_create.restype = ctypes.c_int
+        L.bcs_mechanism_destroy.argtypes = [P]
+        L.bcs_mechanism_destroy.restype = None
+        L.bcs_assemble.argtypes = [P, I64, P, P, I64, P, P, VP]
+        L.bcs_assemble.restype = ctypes.c_int
+        L.bcs_probe_threads_per_block.argtypes = []
+        L.bcs_probe_threads_per_block.restype = ctypes.c_int
+        L.bcs_probe_copy.argtypes = [P, P, I64, I32, VP]
+        L.bcs_probe_copy.restype = D
+        L.bcs_probe_lds.argtypes = [P, I64, I32, I32, VP]
+        L.bcs_probe_lds.restype = D
+        L.bcs_probe_fma.argtypes = [P, I64, I32, I32, VP]
+        L.bcs_probe_fma.restype = D
         L.bcs_last_error.argtypes = []
         L.bcs_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -110,10 +125,12 @@ def lib():
 
 
 def exported_symbols() -> list:
-    """Function names declared in include/bcs.h."""
-    with open(_HEADER) as f:
-        text = f.read()
-    return sorted(set(re.findall(r"\b(bcs_[a-z_]+)\s*\(", text)))
+    """Function names declared in the headers under include/ (bcs.h, bcs_probe.h)."""
+    names = set()
+    for path in sorted(glob.glob(os.path.join(os.path.dirname(_HEADER), "*.h"))):
+        with open(path) as f:
+            names |= set(re.findall(r"\b(bcs_[a-z_0-9]+)\s*\(", f.read()))
+    return sorted(names)
 
 
 def schedule_describe(row_ptr, col_idx, lanes: int, transpose=False,
@@ -414,6 +431,69 @@ def multi_autotune(plans: Sequence[Plan], values: Sequence, gammas: Sequence, bs
                                     float(rtol), int(maxit), arrs["x"], arrs["iters"], arrs["resid"],
                                     arrs["status"], lanes))
     return list(lanes)
+
+
+class Mechanism:
+    """A mass-action mechanism on a CSR pattern (bcs_mechanism_create): the
+    gather tables of its rates f and Jacobian J, on the current device."""
+
+    def __init__(self, n: int, reactants, products, row_ptr, col_idx):
+        L = lib()
+        rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+        ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
+        re = np.ascontiguousarray(np.asarray(reactants).reshape(-1, 2), dtype=np.int32)
+        pr = np.ascontiguousarray(np.asarray(products).reshape(-1, 2), dtype=np.int32)
+        if re.shape != pr.shape:
+            raise ValueError("reactants and products must both have shape [R, 2]")
+        self.n, self.nnz, self.R = int(n), int(ci.shape[0]), int(re.shape[0])
+        if rp.shape[0] != self.n + 1:
+            raise ValueError("row_ptr must have n + 1 entries")
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.bcs_mechanism_create(self.n, self.nnz, rp.ctypes.data, ci.ctypes.data, self.R, re.ctypes.data,
+                                      pr.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.bcs_mechanism_destroy(h)
+            self._h = None
+
+
+def assemble(mech: Mechanism, y, k, f: bool = True, J: bool = True, out=None):
+    """Mass-action rates and Jacobian of every cell (bcs_assemble): returns
+    (f [C, n] or None, J [C, nnz] or None).  y: [C, n] FP64 device tensor;
+    k: [R] (shared) or [C, R] (per cell) FP64 device tensor; out: optional
+    (f, J) tensors to write into."""
+    torch = _torch()
+    y = _dev(y, torch.float64, "y")
+    C = y.shape[0] if y.dim() == 2 else 0
+    _dev(y, torch.float64, "y", (C, mech.n))
+    k = _dev(k, torch.float64, "k")
+    if k.dim() == 1:
+        _dev(k, torch.float64, "k", (mech.R,))
+        ks = 0
+    else:
+        _dev(k, torch.float64, "k", (C, mech.R))
+        ks = mech.R
+    if out is not None:
+        fo, Jo = out
+    else:
+        fo = torch.empty((C, mech.n), dtype=torch.float64, device=y.device) if f else None
+        Jo = torch.empty((C, mech.nnz), dtype=torch.float64, device=y.device) if J else None
+    if fo is not None:
+        _dev(fo, torch.float64, "f", (C, mech.n))
+    if Jo is not None:
+        _dev(Jo, torch.float64, "J", (C, mech.nnz))
+    _check(lib().bcs_assemble(mech.handle, C, y.data_ptr(), k.data_ptr(), ks,
+                              fo.data_ptr() if fo is not None else None, Jo.data_ptr() if Jo is not None else None,
+                              _stream_handle()))
+    return fo, Jo
 
 
 class BatchedSolveWarning(UserWarning):

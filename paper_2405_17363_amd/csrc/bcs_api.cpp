@@ -1001,6 +1001,11 @@ int time_kernel_synthetic(const bcs_plan* p, const Kernel& K, double* seconds) {
 
 }  // namespace
 
+namespace bcs {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace bcs
+
 extern "C" {
 
 const char* bcs_last_error(void) { return g_err.c_str(); }
@@ -1083,7 +1088,6 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     delete p;
     return fail(BCS_ERR_HIP, "cannot query the compute unit count");
   }
-
   // device tables shared by every kernel of the plan
   std::vector<int16_t> crow(nnz), ccol(nnz);
   std::vector<int> diag(n, 0);  // an absent diagonal (allowed without Jacobi) is never read: 0 keeps it in bounds

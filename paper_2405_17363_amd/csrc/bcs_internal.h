@@ -14,6 +14,11 @@ static_assert(kConverged == BCS_CONVERGED && kMaxit == BCS_MAXIT && kBreakdown =
               "status codes");
 static_assert(kJGamma == BCS_J_GAMMA && kADirect == BCS_A_DIRECT, "matrix kinds");
 
+// The library's thread-local error message (bcs_last_error): set it and
+// return `code`, or clear it.
+int set_error(int code, const char* msg);
+void clear_error();
+
 // Precompiled variants: (lanes per cell, row slots per lane, max steps per
 // lane), with the slot segment boundaries read at run time.
 using LaunchFn = hipError_t (*)(const KParams&, int grid, hipStream_t stream);

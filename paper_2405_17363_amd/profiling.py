@@ -95,6 +95,58 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> d
             "launches": len(fk), "source_hash": source_hash()}
 
 
+def measure_peaks(reps: int = 5) -> dict:
+    """Attained ceilings on the current device (include/bcs_probe.h): HBM
+    stream (a 1 GiB copy), LDS gathers of FP64 words (conflict-free and
+    pseudo-random), FP64 and FP32 vector FMAs.  Each probe is launched once
+    untimed, then `reps` times, each timed with HIP events on the current
+    stream; the best rate is kept."""
+    import ctypes
+
+    import torch
+
+    from ._binding import lib
+
+    L = lib()
+    dev = torch.cuda.current_device()
+    cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    threads = L.bcs_probe_threads_per_block()
+
+    def best(launch):
+        if launch() < 0:
+            raise RuntimeError("probe launch failed")
+        out = 0.0
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            amount = launch()
+            e1.record(stream)
+            e1.synchronize()
+            out = max(out, amount / (e0.elapsed_time(e1) * 1e-3))
+        return out
+
+    n = 1 << 27  # 1 GiB of FP64 each way
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    blocks = cu * 16
+    hbm = best(lambda: L.bcs_probe_copy(a.data_ptr(), b.data_ptr(), n, blocks, sh))
+    del a, b
+    blocks = cu * 8
+    sink = torch.empty(blocks * threads, dtype=torch.float64, device=dev)
+    lds0 = best(lambda: L.bcs_probe_lds(sink.data_ptr(), 2000, 0, blocks, sh))
+    lds1 = best(lambda: L.bcs_probe_lds(sink.data_ptr(), 2000, 1, blocks, sh))
+    f64 = best(lambda: L.bcs_probe_fma(sink.data_ptr(), 5000, 1, blocks, sh))
+    sink32 = torch.empty(blocks * threads, dtype=torch.float32, device=dev)
+    f32 = best(lambda: L.bcs_probe_fma(sink32.data_ptr(), 5000, 0, blocks, sh))
+    torch.cuda.synchronize()
+    return {"hbm_copy_gbs": round(hbm / 1e9, 1), "lds_gather_tbs": round(lds0 / 1e12, 2),
+            "lds_random_gather_tbs": round(lds1 / 1e12, 2), "fp64_fma_tflops": round(f64 / 1e12, 2),
+            "fp32_fma_tflops": round(f32 / 1e12, 2), "compute_units": cu,
+            "how": "include/bcs_probe.h kernels, best of %d event-timed launches each" % reps}
+
+
 def load_traffic(path: str) -> dict:
     with open(path) as f:
         return json.loads("".join(line for line in f if not line.lstrip().startswith("#")))
