@@ -278,6 +278,28 @@ int bcs_solve_batch(const bcs_plan* plan, int64_t ncells, const double* values, 
                     double* x, int32_t* iters, double* resid, int32_t* status, int32_t* refinements,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* Bytes of the library-owned scratch of bcs_solve_batch_noalloc (per GPU). */
+#define BCS_NOALLOC_MAX_BYTES (4u << 20)
+
+/* bcs_solve_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument.  The solve's scratch (work queue, cost-order sort
+ * state and order) lives in a library-owned device array of
+ * BCS_NOALLOC_MAX_BYTES on every GPU the library runs on, held until the
+ * process ends; the call allocates and frees nothing.  Limit:
+ * bcs_workspace_bytes(plan, ncells) <= BCS_NOALLOC_MAX_BYTES, i.e. at most
+ * 1,048,256 cells; a larger batch is rejected with BCS_ERR_UNSUPPORTED
+ * before anything is launched.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (each call clears what must
+ * start at zero itself, by a kernel on `stream`): calls that overlap on one
+ * GPU (different streams or host threads without ordering) race and must be
+ * serialised by the caller.  Arguments, outputs and errors otherwise as in
+ * bcs_solve_batch; results are those of bcs_solve_batch. */
+int bcs_solve_batch_noalloc(const bcs_plan* plan, int64_t ncells, const double* values, const double* gamma,
+                            int64_t gamma_stride, const double* b, const double* x0, double rtol, int32_t maxit,
+                            double* x, int32_t* iters, double* resid, int32_t* status, int32_t* refinements,
+                            void* stream);
+
 /* What the adjoint writes into grad_vals. */
 #define BCS_GRAD_A 0      /* dL/dA on the pattern: -lambda_i x_j at entry (i, j) */
 #define BCS_GRAD_VALUES 1 /* dL/d(values): in BCS_J_GAMMA mode dL/dJ = gamma_c lambda_i x_j

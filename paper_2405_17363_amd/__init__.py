@@ -34,6 +34,8 @@ from ._binding import (  # noqa: F401
     BCS_PRECOND_NONE,
     BCS_SCHED_DIAG,
     BCS_SCHED_SPAN,
+    NOALLOC_MAX_BYTES,
+    NOALLOC_MAX_CELLS,
     BcsError,
     BatchedSolve,
     BatchedSolveWarning,
@@ -48,5 +50,6 @@ from ._binding import (  # noqa: F401
     schedule_describe,
     solve_batch,
     solve_batch_adjoint,
+    solve_batch_noalloc,
     solve_multi,
 )

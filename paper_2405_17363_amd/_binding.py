@@ -23,6 +23,8 @@ BCS_SCHED_SPAN, BCS_SCHED_DIAG = 1, 2
 BCS_PART_A, BCS_PART_AT, BCS_PART_LOWER, BCS_PART_UPPER = 0, 1, 2, 3
 BCS_BUDGET_INNER, BCS_BUDGET_CELL = 0, 1
 BCS_GRAD_A, BCS_GRAD_VALUES = 0, 1
+NOALLOC_MAX_BYTES = 4 << 20  # BCS_NOALLOC_MAX_BYTES
+NOALLOC_MAX_CELLS = (NOALLOC_MAX_BYTES - 1280) // 4
 
 _PRECOND = {"none": BCS_PRECOND_NONE, "jacobi": BCS_PRECOND_JACOBI, "ilu0": BCS_PRECOND_ILU0}
 _PRECISION = {"fp64": BCS_FP64, "fp32_refine": BCS_FP32_REFINE}
@@ -92,6 +94,8 @@ def lib():
         L.bcs_workspace_bytes.restype = SZ
         L.bcs_solve_batch.argtypes = [P, I64, P, P, I64, P, P, D, I32, P, P, P, P, P, P, SZ, VP]
         L.bcs_solve_batch.restype = ctypes.c_int
+        L.bcs_solve_batch_noalloc.argtypes = [P, I64, P, P, I64, P, P, D, I32, P, P, P, P, P, VP]
+        L.bcs_solve_batch_noalloc.restype = ctypes.c_int
         L.bcs_solve_batch_adjoint.argtypes = [P, I64, P, P, I64, P, P, D, I32, I32, P, P, P, P, P, P, P, SZ, VP]
         L.bcs_solve_batch_adjoint.restype = ctypes.c_int
         L.bcs_multi_workspace_bytes.argtypes = [I32, P, P]
@@ -341,6 +345,35 @@ def solve_batch(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 
                                iters.data_ptr(), resid.data_ptr(), status.data_ptr(),
                                refin.data_ptr() if refin is not None else None, ws.data_ptr(), ws.numel(),
                                _stream_handle())
+    _check(rc)
+    return x, iters, resid, status, refin
+
+
+def solve_batch_noalloc(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit: int = 200, out=None, x0=None):
+    """solve_batch without a workspace (bcs_solve_batch_noalloc): the solve's
+    scratch is the library's own device array (at most NOALLOC_MAX_CELLS
+    cells).  Calls that overlap on one GPU race.  With `out` given (x, iters,
+    resid, status, refinements or None) nothing at all is allocated."""
+    torch = _torch()
+    values = _dev(values, torch.float64, "values")
+    ncells = values.shape[0] if values.dim() == 2 else 0
+    _dev(values, torch.float64, "values", (ncells, plan.nnz))
+    _dev(b, torch.float64, "b", (ncells, plan.n))
+    if x0 is not None:
+        _dev(x0, torch.float64, "x0", (ncells, plan.n))
+    g, gs = _gamma_arg(gamma, ncells, values.device)
+    if out is None:
+        x = torch.empty((ncells, plan.n), dtype=torch.float64, device=values.device)
+        iters = torch.empty(ncells, dtype=torch.int32, device=values.device)
+        resid = torch.empty(ncells, dtype=torch.float64, device=values.device)
+        status = torch.empty(ncells, dtype=torch.int32, device=values.device)
+        refin = torch.empty(ncells, dtype=torch.int32, device=values.device)
+    else:
+        x, iters, resid, status, refin = out
+    rc = lib().bcs_solve_batch_noalloc(plan.handle, ncells, values.data_ptr(), g.data_ptr(), gs, b.data_ptr(),
+                                       x0.data_ptr() if x0 is not None else None, float(rtol), int(maxit),
+                                       x.data_ptr(), iters.data_ptr(), resid.data_ptr(), status.data_ptr(),
+                                       refin.data_ptr() if refin is not None else None, _stream_handle())
     _check(rc)
     return x, iters, resid, status, refin
 

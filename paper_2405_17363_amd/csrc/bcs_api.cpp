@@ -779,6 +779,42 @@ struct bcs_plan {
   int16_t* coo_col = nullptr;
 };
 
+// Scratch of bcs_solve_batch_noalloc: the contents of a caller's workspace
+// (work queue, cost-order sort state, the order itself) in a library-owned
+// device array, one copy on every GPU the library runs on, held until the
+// process ends.  In host code the array's name is only a host-side stand-in:
+// host code uses the device address hipGetSymbolAddress returns for each
+// device (scratch_address), never the name itself.
+static __device__ __align__(256) unsigned char scratch[BCS_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Resolve this device's copy of `scratch` (the current device; once per
+// device, at plan creation).
+int scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(BCS_ERR_UNSUPPORTED, "device index %d >= %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[device]) return BCS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(BCS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  g_scratch_addr[device] = ptr;
+  return BCS_OK;
+}
+
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
+}  // namespace
+
 namespace {
 
 void release(bcs_plan* p) {
@@ -1088,6 +1124,14 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     delete p;
     return fail(BCS_ERR_HIP, "cannot query the compute unit count");
   }
+  {
+    const int src = scratch_init(p->device);  // the no-allocation entry point's scratch on this device
+    if (src != BCS_OK) {
+      delete p;
+      return src;
+    }
+  }
+
   // device tables shared by every kernel of the plan
   std::vector<int16_t> crow(nnz), ccol(nnz);
   std::vector<int> diag(n, 0);  // an absent diagonal (allowed without Jacobi) is never read: 0 keeps it in bounds
@@ -1379,6 +1423,25 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   rc = prologue(p, &P, workspace, (hipStream_t)stream);
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd, P, (hipStream_t)stream);
+}
+
+int bcs_solve_batch_noalloc(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
+                            int64_t gamma_stride, const double* b, const double* x0, double rtol, int32_t maxit,
+                            double* x, int32_t* iters, double* resid, int32_t* status, int32_t* refinements,
+                            void* stream) {
+  g_err.clear();
+  int rc = check_common(p, ncells, values, gamma, gamma_stride, rtol, maxit);
+  if (rc != BCS_OK) return rc;
+  if (ncells == 0) return BCS_OK;
+  if (ws_bytes(ncells) > (size_t)BCS_NOALLOC_MAX_BYTES)
+    return fail(BCS_ERR_UNSUPPORTED, "%lld cells need %zu bytes of scratch, more than the %zu bytes of the "
+                "no-allocation entry point (at most %lld cells)", (long long)ncells, ws_bytes(ncells),
+                (size_t)BCS_NOALLOC_MAX_BYTES,
+                (long long)(((size_t)BCS_NOALLOC_MAX_BYTES - bcs::kWsOrderOffset) / sizeof(int32_t)));
+  void* ws = scratch_address(p->device);
+  if (!ws) return fail(BCS_ERR_HIP, "no scratch address for device %d", p->device);
+  return bcs_solve_batch(p, ncells, values, gamma, gamma_stride, b, x0, rtol, maxit, x, iters, resid, status,
+                         refinements, ws, (size_t)BCS_NOALLOC_MAX_BYTES, stream);
 }
 
 int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* values, const double* gamma,
