@@ -424,7 +424,7 @@ def main():
             ix, iit, ires, ist, _ = [t.cpu().numpy() for t in iout]
             isolved = int(np.sum((ist == 0) & (ires <= RTOL)))
             zl, zu, ffl = ilu_counts(mech.row_ptr, mech.col_idx)
-            sw = iplan.options.ilu_sweeps
+            sw = iplan.options.ilu_sweeps or 3  # 0 = the library default, 3 sweeps
             ii = iit.astype(np.float64)
             # per iteration: two SpMVs with A, two applications of (LU)^-1 by
             # `sw` sweeps per triangle, six reductions and four updates; per

@@ -24,6 +24,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Fused multiply-add in the operands' own precision (__builtin_fma is the
+// double version: with float operands it would compute in FP64 and round
+// twice).
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Lane exchange within 16-lane rows.  Every control used here reads a valid
 // lane for every lane, so bound_ctrl never zeroes a lane; it only lets the
 // move write its destination without first copying the source into it.
@@ -285,7 +291,7 @@ struct DynSched {
       for (int i = 0; i < C; ++i) {
         const int s = s0 + i;
         if (s < KMAX) {
-          acc = __builtin_fma(a[s], g[i], acc);
+          acc = fmat(a[s], g[i], acc);
           if (flush_bit(f0, f1, s)) {
             *(T*)ydst = acc;
             ydst += LANES;
@@ -375,9 +381,9 @@ struct StaticSched {
       const T gv = g[s % W];
       if (s + W < KMAX) g[s % W] = lds_load<T>(step_addr<PACK>(ad, s + W));
       if (((s - slot_start(s)) & 1) == 0)
-        acc0 = __builtin_fma(a[s], gv, acc0);
+        acc0 = fmat(a[s], gv, acc0);
       else
-        acc1 = __builtin_fma(a[s], gv, acc1);
+        acc1 = fmat(a[s], gv, acc1);
       if (ends_slot(s)) {
         constexpr int last = RPL - 1;
         const int j = slot_of(s);
@@ -388,7 +394,7 @@ struct StaticSched {
       }
     }
     if constexpr (SPAN) {
-      out[0] = __builtin_fma(sm, out[1], out[0]);
+      out[0] = fmat(sm, out[1], out[0]);
       out[1] = (T(1) - sm) * out[1];
     }
     wave_sync();
@@ -408,7 +414,7 @@ template <int RPL, typename T>
 __device__ __forceinline__ T ldot(const T (&u)[RPL], const T (&v)[RPL]) {
   T s = 0;
 #pragma unroll
-  for (int j = 0; j < RPL; ++j) s = __builtin_fma(u[j], v[j], s);
+  for (int j = 0; j < RPL; ++j) s = fmat(u[j], v[j], s);
   return s;
 }
 

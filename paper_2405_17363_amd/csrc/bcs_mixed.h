@@ -235,8 +235,15 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
         } else {
           alpha = qdiv(rho, sigma);
 #pragma unroll
-          for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];
-          const float sn2 = gsum<LANES>(ldot<RPL>(r, r));
+          for (int j = 0; j < RPL; ++j) r[j] = r[j] - alpha * v[j];  // r now holds s
+          // t = Ahat s is formed before the half-step test so that ||s||^2,
+          // (t, t) and (t, s) are reduced together (one reduction latency
+          // instead of two; each sum is bitwise what its own reduction gives,
+          // and t is discarded on a half-step exit)
+          sch.spmv(a32, ad, xb, yb, gl, rows, r, t, dg32, span32);
+          float red3[3] = {ldot<RPL>(r, r), ldot<RPL>(t, t), ldot<RPL>(t, r)};
+          gsum_n<LANES>(red3);
+          const float sn2 = red3[0];
           if (!finite(sn2)) {
             ended = kNonfinite;
           } else if (sn2 <= itol2) {
@@ -244,10 +251,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
             for (int j = 0; j < RPL; ++j) d[j] = d[j] + alpha * p[j];
             ended = kConverged;
           } else {
-            sch.spmv(a32, ad, xb, yb, gl, rows, r, t, dg32, span32);
-            float red2[2] = {ldot<RPL>(t, t), ldot<RPL>(t, r)};
-            gsum_n<LANES>(red2);
-            const float tt = red2[0], ts = red2[1];
+            const float tt = red3[1], ts = red3[2];
             if (!finite(tt)) {
               ended = kNonfinite;
             } else if (tt == 0.f) {

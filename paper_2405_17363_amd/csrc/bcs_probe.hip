@@ -6,6 +6,7 @@
 // measure what a plain, well-formed kernel attains.  The caller times the
 // launches (HIP events on `stream`) and divides the bytes or flops each
 // launch performs, returned by the functions below, by the time.
+#include "bcs_device.h"
 #include "bcs_internal.h"
 #include "../../include/bcs_probe.h"
 
@@ -29,7 +30,8 @@ __global__ void __launch_bounds__(kProbeThreads) k_copy(const double2* __restric
 // pseudo-random word (a multiplicative hash of its round, slot and lane),
 // like the solve's gathers of random columns.  All addresses stay inside
 // the kLdsDoubles-word array.
-__global__ void __launch_bounds__(kProbeThreads) k_lds(double* out, int64_t rounds, int pattern) {
+template <int PATTERN>
+__global__ void __launch_bounds__(kProbeThreads) k_lds(double* out, int64_t rounds) {
   __shared__ double buf[kLdsDoubles];
   for (int i = threadIdx.x; i < kLdsDoubles; i += kProbeThreads) buf[i] = (double)(i & 7);
   __syncthreads();
@@ -40,8 +42,10 @@ __global__ void __launch_bounds__(kProbeThreads) k_lds(double* out, int64_t roun
   for (int64_t r = 0; r < rounds; ++r) {
 #pragma unroll
     for (int u = 0; u < kProbeUnroll; ++u) {
-      const uint32_t k = ((uint32_t)r * kProbeUnroll + u) * 4u + wv;
-      const uint32_t idx = pattern == 0 ? (k * 64u + lane) : ((k * 64u + lane) * 2654435761u) >> 20;
+      // k runs over the array's 64 blocks of 64 words as r advances (an odd
+      // step, so no load repeats the previous round's and none can be hoisted)
+      const uint32_t k = (uint32_t)r * (kProbeUnroll * 4u + 1u) + u * 4u + wv;
+      const uint32_t idx = PATTERN == 0 ? ((k & 63u) * 64u + lane) : ((k * 64u + lane) * 2654435761u) >> 20;
       acc[u] += buf[idx & (kLdsDoubles - 1)];
     }
   }
@@ -59,7 +63,7 @@ __global__ void __launch_bounds__(kProbeThreads) k_fma(T* out, int64_t rounds, T
   for (int u = 0; u < kProbeUnroll; ++u) v[u] = (T)(threadIdx.x + u);
   for (int64_t r = 0; r < rounds; ++r) {
 #pragma unroll
-    for (int u = 0; u < kProbeUnroll; ++u) v[u] = __builtin_fma(v[u], a, b);
+    for (int u = 0; u < kProbeUnroll; ++u) v[u] = dev::fmat(v[u], a, b);
   }
   T s = 0;
 #pragma unroll
@@ -84,8 +88,10 @@ double bcs_probe_copy(const double* in, double* out, int64_t n, int32_t blocks, 
 
 double bcs_probe_lds(double* out, int64_t rounds, int32_t pattern, int32_t blocks, void* stream) {
   if (!out || rounds < 1 || blocks < 1 || (pattern != 0 && pattern != 1)) return -1.0;
-  hipLaunchKernelGGL(bcs::k_lds, dim3(blocks), dim3(bcs::kProbeThreads), 0, (hipStream_t)stream, out, rounds,
-                     (int)pattern);
+  if (pattern == 0)
+    hipLaunchKernelGGL(bcs::k_lds<0>, dim3(blocks), dim3(bcs::kProbeThreads), 0, (hipStream_t)stream, out, rounds);
+  else
+    hipLaunchKernelGGL(bcs::k_lds<1>, dim3(blocks), dim3(bcs::kProbeThreads), 0, (hipStream_t)stream, out, rounds);
   if (hipGetLastError() != hipSuccess) return -1.0;
   return 8.0 * bcs::kProbeUnroll * (double)rounds * bcs::kProbeThreads * blocks;
 }

@@ -135,6 +135,13 @@ def perturb_ulp(a, seed=1):
     return a * (1 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -52)
 
 
+def perturb_ulp32(a, seed=1):
+    """b perturbed at FP32 rounding level (relative 2^-24 per entry): the
+    control for arithmetic carried out in FP32."""
+    rng = np.random.default_rng(seed)
+    return a * (1 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -24)
+
+
 def iters_close(a, b, sa, sb):
     both = (sa == 0) & (sb == 0)
     if not both.any():

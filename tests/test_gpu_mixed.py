@@ -4,9 +4,14 @@ against the oracle's FP32/FP64 emulation and dense LU.
 Bound for the final x: the same residual-implied bound as FP64
 (tests/parity.py), with resid <= rtol required for converged cells.
 Statuses agree with the oracle's emulation at least as well as the emulation
-agrees with itself when b is perturbed by one ulp per entry, less one point
-(refinement in FP32 is sensitive to rounding near kappa u32 ~ 1); refinement
-counts agree within one on >= 95% of the cells both solve.  Both readings of
+agrees with itself when b is perturbed at FP32 rounding level (relative 2^-24
+per entry), less one point.  The inner solve runs in FP32, where the GPU and
+the emulation differ by FP32 roundings in every operation (fused
+multiply-adds, reciprocal-based quotients and the reduction order on the GPU;
+separate roundings, IEEE division and sequential sums in the emulation); a
+perturbation of one FP64 ulp mostly vanishes in the first cast to FP32 and
+would not exercise that sensitivity.  Refinement counts agree within one on
+>= 95% of the cells both solve.  Both readings of
 the iteration budget are checked: maxit per inner solve (the default) and per
 cell over its inner solves.
 """
@@ -14,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import lu_check, perturb_ulp
+from parity import lu_check, perturb_ulp32
 from workload import config_inputs
 
 torch = pytest.importorskip("torch")
@@ -46,7 +51,7 @@ def check_mixed(mech, cells, out, budget, lu_sample, x0=None):
     x, it, res, st, ref = out
     args = (rp, ci, cells["values"], cells["gamma"])
     xo, ito, refo, reso, sto = oracle.mixed_batch(*args, cells["b"], budget=budget, x0=x0)
-    _, _, refp, _, stp = oracle.mixed_batch(*args, perturb_ulp(cells["b"]), budget=budget, x0=x0)
+    _, _, refp, _, stp = oracle.mixed_batch(*args, perturb_ulp32(cells["b"]), budget=budget, x0=x0)
     agree = float(np.mean(st == sto))
     bar = min(0.99, float(np.mean(stp == sto)) - 0.01)
     print(f"budget {budget}: gpu status {np.bincount(st, minlength=4)}, oracle {np.bincount(sto, minlength=4)}, "
