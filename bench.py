@@ -32,7 +32,7 @@ FP32_VALU_PEAK = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
 FP32_UNPACKED_PEAK = 78.6  # FP32 vector without packed instructions (what the kernels issue), TFLOP/s
 RTOL = 1e-10
 MAXIT = 200
-FORMS = ("mixed", "adjoint", "multi", "block", "ilu0", "assemble", "small", "peaks")
+FORMS = ("mixed", "mixed_cell", "adjoint", "multi", "block", "ilu0", "assemble", "small", "peaks")
 
 
 def parse():
@@ -292,6 +292,7 @@ def main():
     mixed = mixed_cell = None
     if "mixed" in args.forms:
         mixed = mixed_form("inner")
+    if "mixed_cell" in args.forms:
         mixed_cell = mixed_form("cell")
 
     def timed(fn, steps):

@@ -57,8 +57,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    # ORACLE_LIB: a separately built copy of the same source (the sanitizer
+    # tests load an AddressSanitizer / UBSan build this way)
+    path = os.environ.get("ORACLE_LIB") or build()
+    lib = ctypes.CDLL(path)
     _vp = ctypes.c_void_p
     lib.oracle_solve_batch.argtypes = [_i64, _int, _int, _I, _I, _D, _D, _i64, _int, _D, _vp, _dbl, _int, _int,
                                        _int, _int, _int, _D, _I, _D, _I, _int]

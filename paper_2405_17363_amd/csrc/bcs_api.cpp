@@ -253,19 +253,21 @@ struct WgLayout {
 
 int slots_per_wg(int lanes) { return bcs::kWavesPerWg * (64 / lanes); }
 
-// operand block stride and state block size of one slot
-void slot_sizes(int n, int lanes, int rpl, int* xs, int* bs) {
+// operand block stride and state block size of one slot (lean: the slot
+// vectors of kSchedLean kernels ahead of the SpMV result block)
+void slot_sizes(int n, int lanes, int rpl, bool lean, int* xs, int* bs) {
   const int xn = ((n + 1 + 7) / 8) * 8;
   *xs = ((xn + 31) / 32) * 32 + 8;
-  *bs = rpl * lanes;
+  *bs = (lean ? bcs::kSlotVecs + 1 : 1) * rpl * lanes;
 }
 
 size_t table_doubles(int n, int lanes, int ksteps) { return ((size_t)ksteps * lanes + (size_t)n + 1) / 2; }
 
-WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint) {
+WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint, bool lean = false) {
   WgLayout L;
   (void)adjoint;
-  slot_sizes(n, lanes, rpl, &L.xs, &L.bs);
+  slot_sizes(n, lanes, rpl, lean, &L.xs, &L.bs);
+  L.yoff = lean ? bcs::kSlotVecs * rpl * lanes : 0;
   L.wxs = (64 / lanes) * L.xs;
   L.wbs = (64 / lanes) * L.bs;
   L.bbase = bcs::kWavesPerWg * L.wxs;
@@ -298,6 +300,7 @@ struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
   std::vector<int> seg;               // slot segment lengths (specialised kernels)
   int flags = 0;                      // schedule shape (specialised kernels)
+  bool occ = false;                   // built for three waves per SIMD (kSchedLean | kSchedPack)
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -661,6 +664,13 @@ int make_ilu_kernel(int n, const std::vector<int>& rp, const std::vector<int>& c
   return BCS_OK;
 }
 
+// Whether forward FP64 kernels are built for three waves per SIMD first
+// (BCS_OCCUPANCY=0 turns it off, for comparisons).
+bool occupancy_build() {
+  const char* e = std::getenv("BCS_OCCUPANCY");
+  return !(e && std::atoi(e) == 0);
+}
+
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
@@ -677,15 +687,42 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     if (!jit_feasible(S.ksteps, rpl)) return BCS_ERR_UNSUPPORTED;
     K.rpl = rpl;
     K.ksteps = S.ksteps;
-    K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint);
-    if (!layout_fits(K.layout)) return BCS_ERR_UNSUPPORTED;
-    K.lds = K.layout.bytes;
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes, S.flags,
-                                   S.seg.data(), rpl, waves_per_eu, K.lds, &K.jit, err, sizeof(err));
-    if (rc != BCS_OK) return fail(rc, "%s", err);
+    // Forward FP64 kernels are first built for three waves per SIMD: the
+    // rarely used slot vectors in LDS (kSchedLean) and packed gather
+    // addresses; if that build spills registers, the default build (all
+    // vectors in registers, occupancy set by the compiler) is used.
+    bool occ = !mixed && !adjoint && !grouped && waves_per_eu == 0 && occupancy_build();
+    for (;;) {
+      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, occ);
+      if (!layout_fits(K.layout)) {
+        if (occ) {
+          if (verbose())
+            std::fprintf(stderr, "[bcs] lanes=%d: the three-wave layout needs %zu bytes of LDS; default build\n",
+                         lanes, K.layout.bytes);
+          occ = false;
+          continue;
+        }
+        return BCS_ERR_UNSUPPORTED;
+      }
+      K.lds = K.layout.bytes;
+      const int extra = occ ? (bcs::kSchedLean | bcs::kSchedPack) : 0;
+      const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes,
+                                     S.flags | extra, S.seg.data(), rpl, occ ? 3 : waves_per_eu, K.lds, &K.jit, err,
+                                     sizeof(err));
+      if (rc != BCS_OK) return fail(rc, "%s", err);
+      if (occ && K.jit.scratch > 0) {
+        if (verbose())
+          std::fprintf(stderr, "[bcs] lanes=%d: the three-wave build spills %d bytes per lane; default build\n", lanes,
+                       K.jit.scratch);
+        occ = false;
+        continue;
+      }
+      break;
+    }
+    K.occ = occ;
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
     if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
@@ -728,9 +765,10 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     return rc;
   }
   if (verbose())
-    std::fprintf(stderr, "[bcs] kernel %s%s lanes=%d rpl=%d steps=%d shape=%d adjoint=%d lds=%zu blocks/CU=%d\n",
-                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", lanes, K.rpl, K.ksteps, K.flags, adjoint,
-                 K.lds, K.max_blocks);
+    std::fprintf(stderr,
+                 "[bcs] kernel %s%s%s lanes=%d rpl=%d steps=%d shape=%d adjoint=%d lds=%zu blocks/CU=%d\n",
+                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", K.occ ? " occupancy-3" : "", lanes, K.rpl,
+                 K.ksteps, K.flags, adjoint, K.lds, K.max_blocks);
   *out = K;
   return BCS_OK;
 }

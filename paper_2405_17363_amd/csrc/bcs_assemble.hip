@@ -15,11 +15,12 @@
 // position of the pattern, the reactions that contribute to it (reaction,
 // S_ir, the other reactant or none, the factor 2), in increasing reaction
 // order; for every species, the reactions that change it (reaction, S_ir).
-// A workgroup then takes up to four consecutive cells at a time (fewer when
+// A workgroup then takes up to eight consecutive cells at a time (fewer when
 // the staging would not fit the LDS), stages their
-// concentrations (and per-cell rate constants) in LDS with coalesced loads,
-// and writes their J rows and f with consecutive threads on consecutive
-// addresses.  Every sum runs over its terms in increasing reaction order,
+// concentrations (and per-cell rate constants) in LDS with coalesced loads;
+// a thread then takes a position (a species, for f) and, reading its term
+// list once, accumulates it for all the staged cells, so consecutive threads
+// write consecutive addresses of every cell's row.  Every sum runs over its terms in increasing reaction order,
 // each term's product S_ir * (k_r ...) exact (S_ir is a small integer), so
 // the results are bitwise those of summing reaction by reaction.
 #include <algorithm>
@@ -50,7 +51,7 @@ namespace bcs {
 namespace {
 
 constexpr int kAsmThreads = 256;
-constexpr int kAsmCellsMax = 4;    // most cells a workgroup stages at a time
+constexpr int kAsmCellsMax = 8;    // most cells a workgroup stages at a time
 constexpr int kNoSpecies = 0xffff;  // "no other reactant" in a J term
 
 // J term: word 0 = reaction; word 1 = other reactant (16 bits, kNoSpecies =
@@ -114,37 +115,50 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble(AsmParams P) {
         ws[i] = w;
       }
       __syncthreads();
-      // the cells' f rows are contiguous: nc * n doubles
-      for (int e = threadIdx.x; e < nc * n; e += kAsmThreads) {
-        const int cc = e / n, i = e - cc * n;
-        double acc = 0.0;
+      // species i of every staged cell: one pass over i's terms
+      for (int i = threadIdx.x; i < n; i += kAsmThreads) {
+        double acc[kAsmCellsMax];
+#pragma unroll
+        for (int cc = 0; cc < kAsmCellsMax; ++cc) acc[cc] = 0.0;
         for (int t = fofs[i]; t < fofs[i + 1]; ++t) {
           const int r = fterm[2 * t];
           const double s = (double)(fterm[2 * t + 1] - 128);
-          acc = __builtin_fma(s, ws[cc * R + r], acc);  // s * w is exact
+#pragma unroll
+          for (int cc = 0; cc < kAsmCellsMax; ++cc)
+            if (cc < nc) acc[cc] = __builtin_fma(s, ws[cc * R + r], acc[cc]);  // s * w is exact
         }
-        P.f[c0 * n + e] = acc;
+#pragma unroll
+        for (int cc = 0; cc < kAsmCellsMax; ++cc)
+          if (cc < nc) P.f[(c0 + cc) * n + i] = acc[cc];
       }
     }
     if (P.J) {
-      for (int cc = 0; cc < nc; ++cc) {
-        const double* yc = ys + cc * n;
-        const double* kc = ks + (kcell ? cc * R : 0);
-        double* Jc = P.J + (c0 + cc) * nnz;
-        for (int q = threadIdx.x; q < nnz; q += kAsmThreads) {
-          double acc = 0.0;
-          for (int t = jofs[q]; t < jofs[q + 1]; ++t) {
-            const int r = jterm[2 * t];
-            const uint32_t w1 = (uint32_t)jterm[2 * t + 1];
-            const int other = (int)(w1 & 0xffffu);
-            const double s = (double)((int)((w1 >> 16) & 0xffu) - 128);
-            double d = kc[r];
-            if (other != kNoSpecies) d = d * yc[other];
-            if (w1 >> 24) d = d * 2.0;               // 2 (k y_a): exact doubling
-            acc = __builtin_fma(s, d, acc);          // s * d is exact
-          }
-          Jc[q] = acc;
+      // position q of every staged cell: one pass over q's terms, the term
+      // words read once for all the cells; consecutive threads write
+      // consecutive positions of each cell's row
+      for (int q = threadIdx.x; q < nnz; q += kAsmThreads) {
+        double acc[kAsmCellsMax];
+#pragma unroll
+        for (int cc = 0; cc < kAsmCellsMax; ++cc) acc[cc] = 0.0;
+        for (int t = jofs[q]; t < jofs[q + 1]; ++t) {
+          const int r = jterm[2 * t];
+          const uint32_t w1 = (uint32_t)jterm[2 * t + 1];
+          const int other = (int)(w1 & 0xffffu);
+          const double s = (double)((int)((w1 >> 16) & 0xffu) - 128);
+          const bool dbl = (w1 >> 24) != 0;
+          const double ksh = ks[r];  // the shared rate constant (unused with per-cell ones)
+#pragma unroll
+          for (int cc = 0; cc < kAsmCellsMax; ++cc)
+            if (cc < nc) {
+              double d = kcell ? ks[cc * R + r] : ksh;
+              if (other != kNoSpecies) d = d * ys[cc * n + other];
+              if (dbl) d = d * 2.0;                     // 2 (k y_a): exact doubling
+              acc[cc] = __builtin_fma(s, d, acc[cc]);   // s * d is exact
+            }
         }
+#pragma unroll
+        for (int cc = 0; cc < kAsmCellsMax; ++cc)
+          if (cc < nc) P.J[(c0 + cc) * nnz + q] = acc[cc];
       }
     }
   }

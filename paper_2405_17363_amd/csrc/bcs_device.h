@@ -438,6 +438,13 @@ __device__ __forceinline__ float qdiv(float a, float b) {
   return __builtin_fmaf(__builtin_fmaf(-b, q, a), r, q);
 }
 
+// A quiet NaN materialised where it is used (from a scalar register), so
+// that the constant is not kept live in vector registers across the solve
+// loop for the rare non-finite exit.
+__device__ __forceinline__ double qnan() {
+  return __builtin_bit_cast(double, opaque<uint64_t>(0x7ff8000000000000ull));
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 

@@ -77,10 +77,36 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
   double a[KMAX];
   // Krylov state of this lane's rows.  With Jacobi the matrix is staged
-  // column-scaled (Ahat = A D^-1, right preconditioning), so xv holds
-  // xhat = D x and x = D^-1 xhat is formed when the cell finishes.
-  double xv[RPL], r[RPL], rh[RPL], p[RPL], v[RPL], t[RPL];
-  double bb[RPL], dinv[RPL];  // b and diag(A)^-1 of the owned rows
+  // column-scaled (Ahat = A D^-1, right preconditioning), so the iterate
+  // holds xhat = D x and x = D^-1 xhat is formed when the cell finishes.
+  // r, p, v and t, which every step of the iteration reads, stay in
+  // registers.  Kernels built with kSchedLean keep the iterate and the
+  // shadow residual (read or updated once or twice per iteration) and b and
+  // diag(A)^-1 (read when a cell ends or restarts) in the slot's state block
+  // in LDS instead, each lane's own words (no other lane reads them, so they
+  // need no synchronisation); with packed addresses that brings the n = 80
+  // kernel at 32 lanes within the registers of three waves per SIMD.
+  double r[RPL], p[RPL], v[RPL], t[RPL];
+  constexpr bool LEAN = (S::FLAGS & kSchedLean) != 0;
+  constexpr int RR = LEAN ? 1 : RPL;
+  double xv_r[RR], rh_r[RR], bb_r[RR], dinv_r[RR];  // the same vectors in registers (not LEAN)
+  double* const sv = lds + P.bbase + wv * P.wbs + grp * P.bs + gl;  // LEAN: [kSlotVecs][RPL][LANES]
+  auto XV = [&](int j) -> double& {
+    if constexpr (LEAN) return sv[(kSlotX * RPL + j) * LANES]; else return xv_r[j];
+  };
+  auto RH = [&](int j) -> double& {
+    if constexpr (LEAN) return sv[(kSlotRhat * RPL + j) * LANES]; else return rh_r[j];
+  };
+  auto BB = [&](int j) -> double& {
+    if constexpr (LEAN) return sv[(kSlotB * RPL + j) * LANES]; else return bb_r[j];
+  };
+  auto DINV = [&](int j) -> double& {
+    if constexpr (LEAN) return sv[(kSlotDinv * RPL + j) * LANES]; else return dinv_r[j];
+  };
+  auto load_vec = [&](auto& ref, double (&out)[RPL]) {
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) out[j] = ref(j);
+  };
   // Schedules without diagonal entries: the staged (column-scaled) diagonal
   // value of each owned row, 0 for padding rows.
   double dgv[RPL];
@@ -107,9 +133,11 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       active = false;
       return;
     }
+    double xv[RPL];
+    load_vec(XV, xv);
     if (P.precond) {
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) xv[j] = dinv[j] * xv[j];
+      for (int j = 0; j < RPL; ++j) xv[j] = DINV(j) * xv[j];
     }
     if (warm) {
       const double* x0c = P.x0 + cell * n;
@@ -156,7 +184,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   auto restart = [&]() {
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
-      rh[j] = r[j];
+      RH(j) = r[j];
       p[j] = 0;
       v[j] = 0;
     }
@@ -197,9 +225,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           const bool real = rows[j] < n;
           const double bj = bc[real ? rows[j] : 0];
           dv[j] = vals[diag_lds[real ? rows[j] : 0]];
-          bb[j] = real ? bj : 0.0;
-          r[j] = bb[j];
-          xv[j] = 0;
+          r[j] = real ? bj : 0.0;
+          BB(j) = r[j];
+          XV(j) = 0;
         }
         // A = I - gamma J on the schedule's entries (a padding step keeps the
         // finite value it loaded: it multiplies the zero spare element)
@@ -234,16 +262,17 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           for (int j = 0; j < RPL; ++j) x0v[j] = (rows[j] < n) ? x0c[rows[j]] : 0.0;
           sch.spmv(a, ad, xb, yb, gl, rows, x0v, t, dgv, span);
 #pragma unroll
-          for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
+          for (int j = 0; j < RPL; ++j) t[j] = r[j] - t[j];
         }
         if (P.precond) {
           // column scaling by diag(A)^-1, gathered through the LDS slice
 #pragma unroll
           for (int j = 0; j < RPL; ++j) {
             const double d = (P.kind == kJGamma) ? 1.0 - g * dv[j] : dv[j];
-            dinv[j] = (rows[j] < n) ? 1.0 / d : 0.0;
-            xb[rows[j]] = dinv[j];
-            if constexpr ((S::FLAGS & kSchedDiag) != 0) dgv[j] *= dinv[j];
+            const double di = (rows[j] < n) ? 1.0 / d : 0.0;
+            DINV(j) = di;
+            xb[rows[j]] = di;
+            if constexpr ((S::FLAGS & kSchedDiag) != 0) dgv[j] *= di;
           }
           wave_sync();
           uint32_t ado[NW];
@@ -257,7 +286,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
             for (int s = 0; s < KMAX; ++s) a[s] = 0;
 #pragma unroll
-            for (int j = 0; j < RPL; ++j) bb[j] = r[j] = dinv[j] = dgv[j] = 0;
+            for (int j = 0; j < RPL; ++j) BB(j) = r[j] = DINV(j) = dgv[j] = 0;
           }
         }
         double bn2 = gsum<LANES>(ldot<RPL>(r, r));
@@ -271,7 +300,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         warm = use_x0 && finite(bn) && bn != 0.0;
         if (warm) {
 #pragma unroll
-          for (int j = 0; j < RPL; ++j) bb[j] = r[j] = t[j];
+          for (int j = 0; j < RPL; ++j) BB(j) = r[j] = t[j];
           rr2 = gsum<LANES>(ldot<RPL>(r, r));
         }
         it = 0;
@@ -280,7 +309,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         rho = rr2;  // (rhat, r) with rhat = r = r0
         active = true;
         if (!finite(bn)) {
-          finish(kNonfinite, __builtin_nan(""));
+          finish(kNonfinite, qnan());
         } else if (bn == 0.0) {
           finish(kConverged, 0.0);
         } else if (rr2 <= tol2) {
@@ -308,7 +337,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
       for (int j = 0; j < RPL; ++j) p[j] = r[j] + beta * (p[j] - omega * v[j]);
       sch.spmv(a, ad, xb, yb, gl, rows, p, v, dgv, span);
-      const double sigma = gsum<RL>(ldot<RPL>(rh, v));
+      double rhv[RPL];
+      load_vec(RH, rhv);
+      const double sigma = gsum<RL>(ldot<RPL>(rhv, v));
       if (!finite(sigma)) {
         ended = kNonfinite;
       } else if (sigma == 0.0) {
@@ -328,7 +359,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           ended = kNonfinite;
         } else if (sn2 <= tol2) {
 #pragma unroll
-          for (int j = 0; j < RPL; ++j) xv[j] = xv[j] + alpha * p[j];
+          for (int j = 0; j < RPL; ++j) XV(j) = XV(j) + alpha * p[j];
           ended = kConverged;
         } else if (!finite(tt)) {
           ended = kNonfinite;
@@ -338,7 +369,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           omega = qdiv(ts, tt);
 #pragma unroll
           for (int j = 0; j < RPL; ++j) {
-            xv[j] = xv[j] + alpha * p[j] + omega * r[j];
+            XV(j) = XV(j) + alpha * p[j] + omega * r[j];
             r[j] = r[j] - omega * t[j];
           }
           // ||r||^2 of r = s - omega t with omega = (t, s) / (t, t) is
@@ -346,7 +377,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
           // negative value from cancellation passes the test below; the true
           // residual then decides.)
           const double rn2 = sn2 - omega * ts;
-          const double rho_next = gsum<RL>(ldot<RPL>(rh, r));
+          double rhr[RPL];
+          load_vec(RH, rhr);
+          const double rho_next = gsum<RL>(ldot<RPL>(rhr, r));
           if (!finite(rn2)) {
             ended = kNonfinite;
           } else if (rn2 <= tol2) {
@@ -363,9 +396,13 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
     if (ended < 0 && it >= P.maxit) ended = kMaxit;
     if (ended >= 0) {
       // The true residual of the current iterate decides (t is free here).
-      sch.spmv(a, ad, xb, yb, gl, rows, xv, t, dgv, span);
+      {
+        double xv[RPL];
+        load_vec(XV, xv);
+        sch.spmv(a, ad, xb, yb, gl, rows, xv, t, dgv, span);
+      }
 #pragma unroll
-      for (int j = 0; j < RPL; ++j) t[j] = bb[j] - t[j];
+      for (int j = 0; j < RPL; ++j) t[j] = BB(j) - t[j];
       const double tt2c = gsum<LANES>(ldot<RPL>(t, t));
       const double tt2 = GRP ? cross_cells<LANES>(tt2c) : tt2c;
       const double res = __builtin_sqrt(tt2) / bn;

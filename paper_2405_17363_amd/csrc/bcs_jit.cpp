@@ -162,6 +162,7 @@ int load_source(const std::string& source, const char* name, bool ilp, size_t ld
     const std::string dir = cache_dir();
     const std::string path = dir + "/" + fname;
     std::vector<char> code;
+    if (std::getenv("BCS_VERBOSE")) std::fprintf(stderr, "[bcs] jit %s %s\n", name, path.c_str());
     if (!read_file(path, &code)) {
       std::string log;
       if (compile(source, base_arch, ilp, &code, &log) != 0) {

@@ -47,6 +47,16 @@ constexpr int32_t kEntPosMask = kEntPad - 1;
 // itself (4 bytes per cell).  A clear kernel on the solve's stream zeroes the
 // queue and the sort state before every solve.
 constexpr int kQueueWords = 32;
+
+// Per-lane vectors of a cell slot kept in its LDS state block by kernels
+// built with kSchedLean (lane-major: vector k, row slot j, lane l at
+// (k * RPL + j) * LANES + l), ahead of the SpMV result block: the iterate,
+// the shadow residual, b and diag(A)^-1.
+constexpr int kSlotX = 0;
+constexpr int kSlotRhat = 1;
+constexpr int kSlotB = 2;
+constexpr int kSlotDinv = 3;
+constexpr int kSlotVecs = 4;
 constexpr int kWsQueueBytes = kQueueWords * 8;
 
 // Cost order of the cells: a counting sort of the cells by a bucket of
@@ -74,6 +84,10 @@ constexpr int kSchedDiag = 2;
 // kSchedWin8 keeps 8 gathers in flight instead of kGatherChunk.
 constexpr int kSchedPack = 4;
 constexpr int kSchedWin8 = 8;
+// kSchedLean: the FP64 body keeps the vectors of kSlotVecs in the slot's LDS
+// state block instead of registers (the layout then gives every slot
+// kSlotVecs + 1 blocks of RPL x LANES doubles).
+constexpr int kSchedLean = 16;
 constexpr int16_t kRowSpan = -2;
 
 struct DevSchedule {

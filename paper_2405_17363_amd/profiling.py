@@ -2,6 +2,7 @@
 
     python -m paper_2405_17363_amd.profiling stats  --trace DIR [--kernel NAME] [--last N]
     python -m paper_2405_17363_amd.profiling traffic --fetch DIR --write DIR --ncells C --lanes L --out FILE
+    python -m paper_2405_17363_amd.profiling counters --pmc DIR [--pmc DIR ...] --kernel NAME [--last N]
 
 The traffic summary is a text file: '#' lines describe how it was made, the
 rest is one JSON object (read back with ``load_traffic``).
@@ -46,17 +47,26 @@ def _csv(dirname: str, suffix: str):
         return list(csv.DictReader(f))
 
 
-def kernel_stats(trace_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0) -> dict:
+def _is(name: str, kernel: str) -> bool:
+    """`name` (as rocprofv3 prints it) is `kernel`: the same name, or a
+    demangled C++ name whose function is `kernel`."""
+    return name == kernel or ("::" + kernel + "(") in name or name.startswith(kernel + "(")
+
+
+def kernel_stats(trace_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0, drop_last: int = 0) -> dict:
     """rocprofv3's statistics for `kernel`; with last > 0 also the mean
-    duration of its last `last` dispatches (the timed ones after a warm-up)."""
+    duration of its last `last` dispatches (the timed ones after a warm-up),
+    leaving out the final `drop_last` dispatches (launches made after the
+    timed ones, such as the cache-flushed calls of bench.py)."""
     for r in _csv(trace_dir, "kernel_stats.csv"):
-        if r["Name"] == kernel:
+        if _is(r["Name"], kernel):
             out = {"kernel": kernel, "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
                    "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
             if last > 0:
                 d = [(int(t["Start_Timestamp"]), int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
-                     for t in _csv(trace_dir, "kernel_trace.csv") if t["Kernel_Name"] == kernel]
-                d = [ns for _, ns in sorted(d)][-last:]
+                     for t in _csv(trace_dir, "kernel_trace.csv") if _is(t["Kernel_Name"], kernel)]
+                d = [ns for _, ns in sorted(d)]
+                d = d[:len(d) - drop_last][-last:]
                 out["last"] = len(d)
                 out["last_avg_ns"] = sum(d) / len(d)
             return out
@@ -74,6 +84,23 @@ def per_dispatch(pmc_dir: str, counter: str) -> list:
     return [(k[1], k[2], v) for k, v in sorted(acc.items())]
 
 
+def counters(pmc_dirs, kernel: str, last: int = 0) -> dict:
+    """Mean per dispatch of every counter in the `--pmc` runs `pmc_dirs` for
+    `kernel` (each dispatch's value summed over instances), over its last
+    `last` dispatches (all if 0)."""
+    out = {}
+    for d in pmc_dirs:
+        names = sorted({r["Counter_Name"] for r in _csv(d, "counter_collection.csv")})
+        for c in names:
+            v = [val for name, g, val in per_dispatch(d, c) if _is(name, kernel)]
+            if last > 0:
+                v = v[-last:]
+            if v:
+                out[c] = sum(v) / len(v)
+                out.setdefault("_dispatches", len(v))
+    return out
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> dict:
     f = per_dispatch(fetch_dir, "FETCH_SIZE")
     w = per_dispatch(write_dir, "WRITE_SIZE")
@@ -84,8 +111,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> d
         raise RuntimeError("calibration copy not found in the counter runs")
     kf = COPY_BYTES / copy_f
     kw = COPY_BYTES / copy_w
-    fk = [v for name, g, v in f if name == kernel]
-    wk = [v for name, g, v in w if name == kernel]
+    fk = [v for name, g, v in f if _is(name, kernel)]
+    wk = [v for name, g, v in w if _is(name, kernel)]
     if not fk or not wk:
         raise RuntimeError(f"{kernel} not found in the counter runs")
     fetch = kf * sum(fk) / len(fk)
@@ -159,6 +186,7 @@ def main(argv=None) -> int:
     s.add_argument("--trace", required=True)
     s.add_argument("--kernel", default="bcs_solve_fp64")
     s.add_argument("--last", type=int, default=0, help="also average the last N dispatches")
+    s.add_argument("--drop-last", type=int, default=0, help="leave out the final N dispatches")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -167,9 +195,16 @@ def main(argv=None) -> int:
     t.add_argument("--lanes", type=int, required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--note", action="append", default=[], help="header line for the summary (repeatable)")
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", action="append", required=True, help="a --pmc run's output directory (repeatable)")
+    c.add_argument("--kernel", default="bcs_solve_fp64")
+    c.add_argument("--last", type=int, default=0)
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        print(json.dumps(counters(a.pmc, a.kernel, a.last)))
+        return 0
     if a.cmd == "stats":
-        print(json.dumps(kernel_stats(a.trace, a.kernel, a.last)))
+        print(json.dumps(kernel_stats(a.trace, a.kernel, a.last, a.drop_last)))
         return 0
     res = traffic(a.fetch, a.write, a.kernel)
     res.update({"ncells": a.ncells, "lanes_per_cell": a.lanes})
