@@ -504,6 +504,11 @@ def main():
         from paper_2405_17363_amd.profiling import measure_peaks
 
         peaks = measure_peaks()
+        # the headline's use of each resource against what the probes attain
+        roofline_obj["of_attained"] = {
+            "hbm": round(roofline_obj["hbm_gbs"] / peaks["hbm_copy_gbs"], 4),
+            "alu": round(roofline_obj["valu_tflops"] / peaks["fp64_fma_tflops"], 4),
+            "lds": round(roofline_obj["lds_gather_tbs"] / peaks["lds_random_gather_tbs"], 4)}
 
     cpu = None
     if not args.no_cpu:

@@ -135,7 +135,8 @@ typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation, except fo
                                      kernels that bcs_plan_autotune /
                                      bcs_multi_autotune choose */
 
-/* Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
+/* Solver options of a plan (the kernel configuration choices of Section 3.2
+ * and the solver of Section 3.1).  Fill `opt` with the defaults: FP64, Jacobi, J_GAMMA, lanes chosen by the
  * library, residual replacement on, 1 breakdown restart, inner_rtol 1e-4,
  * max_refine 10, refine_budget BCS_BUDGET_INNER, jit 1, autotune 1,
  * cell_order 1, shared_scalars 0, ilu_sweeps 0. */
@@ -156,7 +157,8 @@ void bcs_options_default(bcs_options* opt);
 int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                     const bcs_options* opt, bcs_plan** out);
 
-/* Release a plan and its device tables (NULL is allowed).  The caller must
+/* Release a plan (the shared pattern of Section 2.2 and its kernels) and its
+ * device tables (NULL is allowed).  The caller must
  * ensure no solve using it is still running. */
 void bcs_plan_destroy(bcs_plan* plan);
 
@@ -407,7 +409,10 @@ void bcs_mechanism_destroy(bcs_mechanism* mech);
 int bcs_assemble(const bcs_mechanism* mech, int64_t ncells, const double* y, const double* k, int64_t k_stride,
                  double* f, double* J, void* stream);
 
-/* Description of the last error on this thread ("" if none). */
+/* Description of the last error on this thread ("" if none).  Errors are
+ * argument, pattern or runtime failures of a call, reported synchronously;
+ * the numerical outcome of each cell's solve (Section 3.1's per-cell
+ * convergence) is never an error but its status. */
 const char* bcs_last_error(void);
 
 #ifdef __cplusplus

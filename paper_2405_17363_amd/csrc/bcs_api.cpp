@@ -300,7 +300,8 @@ struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
   std::vector<int> seg;               // slot segment lengths (specialised kernels)
   int flags = 0;                      // schedule shape (specialised kernels)
-  bool occ = false;                   // built for three waves per SIMD (kSchedLean | kSchedPack)
+  bool occ = false;                   // built for three waves per SIMD
+  int occ_flags = 0;                  // its extra schedule flags (kSchedLean | kSchedPack [| kSchedWin8])
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -695,6 +696,10 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     // addresses; if that build spills registers, the default build (all
     // vectors in registers, occupancy set by the compiler) is used.
     bool occ = !mixed && !adjoint && !grouped && waves_per_eu == 0 && occupancy_build();
+    // the three-wave builds tried in turn: packed addresses, then also a
+    // gather window of 8 (fewer registers in flight)
+    const int occ_opts[2] = {bcs::kSchedLean | bcs::kSchedPack, bcs::kSchedLean | bcs::kSchedPack | bcs::kSchedWin8};
+    int occ_try = 0;
     for (;;) {
       K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, occ);
       if (!layout_fits(K.layout)) {
@@ -708,21 +713,22 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
         return BCS_ERR_UNSUPPORTED;
       }
       K.lds = K.layout.bytes;
-      const int extra = occ ? (bcs::kSchedLean | bcs::kSchedPack) : 0;
+      const int extra = occ ? occ_opts[occ_try] : 0;
       const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes,
                                      S.flags | extra, S.seg.data(), rpl, occ ? 3 : waves_per_eu, K.lds, &K.jit, err,
                                      sizeof(err));
       if (rc != BCS_OK) return fail(rc, "%s", err);
       if (occ && K.jit.scratch > 0) {
         if (verbose())
-          std::fprintf(stderr, "[bcs] lanes=%d: the three-wave build spills %d bytes per lane; default build\n", lanes,
+          std::fprintf(stderr, "[bcs] lanes=%d: three-wave build %d spills %d bytes per lane\n", lanes, occ_try,
                        K.jit.scratch);
-        occ = false;
+        if (++occ_try == 2) occ = false;
         continue;
       }
       break;
     }
     K.occ = occ;
+    K.occ_flags = occ ? occ_opts[occ_try] : 0;
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
     if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
@@ -766,9 +772,9 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   }
   if (verbose())
     std::fprintf(stderr,
-                 "[bcs] kernel %s%s%s lanes=%d rpl=%d steps=%d shape=%d adjoint=%d lds=%zu blocks/CU=%d\n",
+                 "[bcs] kernel %s%s%s lanes=%d rpl=%d steps=%d shape=%d extra=%d adjoint=%d lds=%zu blocks/CU=%d\n",
                  use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", K.occ ? " occupancy-3" : "", lanes, K.rpl,
-                 K.ksteps, K.flags, adjoint, K.lds, K.max_blocks);
+                 K.ksteps, K.flags, K.occ_flags, adjoint, K.lds, K.max_blocks);
   *out = K;
   return BCS_OK;
 }

@@ -101,7 +101,10 @@ def counters(pmc_dirs, kernel: str, last: int = 0) -> dict:
     return out
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> dict:
+def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0) -> dict:
+    """HBM bytes per launch of `kernel` (mean over its last `last` dispatches,
+    all if 0) from a FETCH_SIZE and a WRITE_SIZE run of `bench.py
+    --copy-calibration`."""
     f = per_dispatch(fetch_dir, "FETCH_SIZE")
     w = per_dispatch(write_dir, "WRITE_SIZE")
     # the calibration copy is the copy kernel with the largest write
@@ -113,6 +116,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64") -> d
     kw = COPY_BYTES / copy_w
     fk = [v for name, g, v in f if _is(name, kernel)]
     wk = [v for name, g, v in w if _is(name, kernel)]
+    if last > 0:
+        fk, wk = fk[-last:], wk[-last:]
     if not fk or not wk:
         raise RuntimeError(f"{kernel} not found in the counter runs")
     fetch = kf * sum(fk) / len(fk)
@@ -194,6 +199,7 @@ def main(argv=None) -> int:
     t.add_argument("--ncells", type=int, required=True)
     t.add_argument("--lanes", type=int, required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--last", type=int, default=0, help="average the last N dispatches only")
     t.add_argument("--note", action="append", default=[], help="header line for the summary (repeatable)")
     c = sub.add_parser("counters")
     c.add_argument("--pmc", action="append", required=True, help="a --pmc run's output directory (repeatable)")
@@ -206,7 +212,7 @@ def main(argv=None) -> int:
     if a.cmd == "stats":
         print(json.dumps(kernel_stats(a.trace, a.kernel, a.last, a.drop_last)))
         return 0
-    res = traffic(a.fetch, a.write, a.kernel)
+    res = traffic(a.fetch, a.write, a.kernel, a.last)
     res.update({"ncells": a.ncells, "lanes_per_cell": a.lanes})
     with open(a.out, "w") as f:
         for line in a.note:
