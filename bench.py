@@ -32,7 +32,7 @@ FP32_VALU_PEAK = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
 FP32_UNPACKED_PEAK = 78.6  # FP32 vector without packed instructions (what the kernels issue), TFLOP/s
 RTOL = 1e-10
 MAXIT = 200
-FORMS = ("mixed", "mixed_cell", "adjoint", "multi", "block", "ilu0", "assemble", "small", "peaks")
+FORMS = ("mixed", "mixed_cell", "adjoint", "multi", "block", "ilu0", "assemble", "mech", "small", "peaks")
 
 
 def parse():
@@ -471,6 +471,45 @@ def main():
                                          float(C * (3 * terms + 2 * mech.R)), 0.0)}
         del y, kk, fo, Jo, M
 
+    # the Newton systems solved from the cells' concentrations, J assembled
+    # inside the solve kernel, against assembling J first and solving it
+    mech_solve = None
+    if "mech" in args.forms:
+        try:
+            M = bcs.Mechanism(mech.n, mech.reactants, mech.products, mech.row_ptr, mech.col_idx)
+            mplan = bcs.Plan.from_mechanism(M)
+            mplan.autotune(values, gamma, b, RTOL, MAXIT)
+            y = torch.as_tensor(cells["y"], device=dev)
+            kk = torch.as_tensor(mech.k, device=dev)
+            Jo = torch.empty((C, nnz), dtype=torch.float64, device=dev)
+            mout = [torch.empty_like(o) for o in out[:4]]
+
+            def fused():
+                bcs.solve_batch_mech(mplan, y, kk, gamma, b, RTOL, MAXIT, out=mout, workspace=ws)
+
+            def two_step():
+                bcs.assemble(M, y, kk, f=False, out=(None, Jo))
+                bcs.solve_batch(mplan, Jo, gamma, b, RTOL, MAXIT, out=out, workspace=ws)
+
+            tf = timed(fused, args.steps)
+            t2 = timed(two_step, args.steps)
+            mst, mres = mout[3].cpu().numpy(), mout[2].cpu().numpy()
+            msolved = int(np.sum((mst == 0) & (mres <= RTOL)))
+            same = all(bool(torch.equal(a, c)) for a, c in zip(mout, out[:4]))
+            mit = mout[1].cpu().numpy().astype(np.float64)
+            mech_solve = {
+                "value": round(msolved / (tf * 1e-3), 1), "unit": "cells/s", "ms_per_step": round(tf, 4),
+                "ms_assemble_then_solve": round(t2, 4), "solved_fraction": round(msolved / C, 5),
+                "bitwise_equal_to_assemble_then_solve": same, "lanes_per_cell": mplan.info()["lanes_per_cell"],
+                # HBM: y instead of J (8 n instead of 8 nnz bytes read per cell)
+                "roofline": roofline("bcs_solve_fp64_mech", tf * 1e-3, float(C * (8 * n + 16 * n + 24)),
+                                     float(np.sum(mit * (4 * nnz + 24 * n) + (5 * nnz + 10 * n)) +
+                                           C * 3 * len(mech.term_pos)),
+                                     float(np.sum(mit * 16 * nnz + 16 * nnz)))}
+            del mplan, y, kk, Jo, mout, M
+        except bcs.BcsError as e:
+            mech_solve = {"error": str(e)}
+
     # the small configurations: 100 cells (latency) and 10,000 cells (the
     # paper's cell count; its 77 MB fit the Infinity Cache)
     small = {}
@@ -578,6 +617,7 @@ def main():
         "block_cells_n": block_cells,
         "ilu0": ilu,
         "assemble": assemble,
+        "mech_solve": mech_solve,
         "small_configs": small,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,

@@ -409,6 +409,30 @@ void bcs_mechanism_destroy(bcs_mechanism* mech);
 int bcs_assemble(const bcs_mechanism* mech, int64_t ncells, const double* y, const double* k, int64_t k_stride,
                  double* f, double* J, void* stream);
 
+/* A plan for the mechanism's pattern whose forward solves take the cells'
+ * concentrations instead of their Jacobian values: each cell's J is
+ * assembled inside the solve kernel while the cell is staged (the sums and
+ * roundings of bcs_assemble), so J never travels through device memory (the
+ * paper's next step, the rest of the BDF step inside the Block-cells kernel,
+ * Section 6).  The mechanism must outlive the plan.  Options as in
+ * bcs_plan_create, limited to FP64, no or Jacobi preconditioning, J_GAMMA,
+ * jit = 1, shared_scalars = 0 (else BCS_ERR_UNSUPPORTED).  The plan also
+ * serves bcs_solve_batch, the adjoint and the tuners like any other;
+ * bcs_plan_autotune keeps its mechanism kernel at the chosen lanes. */
+int bcs_plan_create_mech(const bcs_mechanism* mech, const bcs_options* opt, bcs_plan** out);
+
+/* Solve (I - gamma_c J(y_c)) x_c = b_c for every cell, J assembled from the
+ * concentrations y [ncells, n] (device FP64) and the rate constants k (device
+ * FP64, k_r of cell c at k[c * k_stride + r]; k_stride 0 = one shared set,
+ * else >= nreact), with a plan from bcs_plan_create_mech.  Results are
+ * bitwise those of bcs_assemble followed by bcs_solve_batch with the same
+ * plan; other arguments, outputs and errors as in bcs_solve_batch (no
+ * refinements output). */
+int bcs_solve_batch_mech(const bcs_plan* plan, int64_t ncells, const double* y, const double* k, int64_t k_stride,
+                         const double* gamma, int64_t gamma_stride, const double* b, const double* x0, double rtol,
+                         int32_t maxit, double* x, int32_t* iters, double* resid, int32_t* status, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
 /* Description of the last error on this thread ("" if none).  Errors are
  * argument, pattern or runtime failures of a call, reported synchronously;
  * the numerical outcome of each cell's solve (Section 3.1's per-cell

@@ -50,6 +50,7 @@ from ._binding import (  # noqa: F401
     schedule_describe,
     solve_batch,
     solve_batch_adjoint,
+    solve_batch_mech,
     solve_batch_noalloc,
     solve_multi,
 )

@@ -122,6 +122,10 @@ def lib():
         L.bcs_probe_lds.restype = D
         L.bcs_probe_fma.argtypes = [P, I64, I32, I32, VP]
         L.bcs_probe_fma.restype = D
+        L.bcs_plan_create_mech.argtypes = [P, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]
+        L.bcs_plan_create_mech.restype = ctypes.c_int
+        L.bcs_solve_batch_mech.argtypes = [P, I64, P, P, I64, P, I64, P, P, D, I32, P, P, P, P, P, SZ, VP]
+        L.bcs_solve_batch_mech.restype = ctypes.c_int
         L.bcs_last_error.argtypes = []
         L.bcs_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -243,6 +247,34 @@ class Plan:
         self._h = None
         _check(rc)
         self._h = h
+
+    @classmethod
+    def from_mechanism(cls, mech: "Mechanism", precond: str = "jacobi", lanes_per_cell: int = 0,
+                       autotune: bool = True, cell_order: bool = True, residual_replacement: bool = True,
+                       breakdown_restarts: int = 1):
+        """A plan for the mechanism's pattern whose solve_batch_mech assembles
+        each cell's J inside the solve (bcs_plan_create_mech).  The plan keeps
+        a reference to the mechanism."""
+        L = lib()
+        self = cls.__new__(cls)
+        self.n, self.nnz = mech.n, mech.nnz
+        self.row_ptr, self.col_idx = mech.row_ptr, mech.col_idx
+        opt = _Options()
+        L.bcs_options_default(ctypes.byref(opt))
+        opt.precond = _PRECOND[precond]
+        opt.lanes_per_cell = int(lanes_per_cell)
+        opt.autotune = int(bool(autotune))
+        opt.cell_order = int(bool(cell_order))
+        opt.residual_replacement = int(bool(residual_replacement))
+        opt.breakdown_restarts = int(breakdown_restarts)
+        self.options = opt
+        self.precision, self.precond, self.matrix_kind = "fp64", precond, "j_gamma"
+        self.mechanism = mech
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.bcs_plan_create_mech(mech.handle, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        return self
 
     @property
     def handle(self):
@@ -378,6 +410,45 @@ def solve_batch_noalloc(plan: Plan, values, gamma, b, rtol: float = 1e-10, maxit
     return x, iters, resid, status, refin
 
 
+def solve_batch_mech(plan: Plan, y, k, gamma, b, rtol: float = 1e-10, maxit: int = 200, out=None, x0=None,
+                     workspace=None):
+    """Solve every cell's Newton system with J assembled from its
+    concentrations inside the solve (bcs_solve_batch_mech); plan from
+    Plan.from_mechanism.  y: [C, n]; k: [R] (shared) or [C, R]; returns (x,
+    iters, resid, status)."""
+    torch = _torch()
+    mech = getattr(plan, "mechanism", None)
+    if mech is None:
+        raise ValueError("the plan was not made by Plan.from_mechanism")
+    y = _dev(y, torch.float64, "y")
+    ncells = y.shape[0] if y.dim() == 2 else 0
+    _dev(y, torch.float64, "y", (ncells, plan.n))
+    _dev(b, torch.float64, "b", (ncells, plan.n))
+    k = _dev(k, torch.float64, "k")
+    if k.dim() == 1:
+        _dev(k, torch.float64, "k", (mech.R,))
+        ks = 0
+    else:
+        _dev(k, torch.float64, "k", (ncells, mech.R))
+        ks = mech.R
+    if x0 is not None:
+        _dev(x0, torch.float64, "x0", (ncells, plan.n))
+    g, gs = _gamma_arg(gamma, ncells, y.device)
+    ws = _check_ws(workspace, plan.workspace_bytes(ncells), y.device)
+    if out is None:
+        x = torch.empty((ncells, plan.n), dtype=torch.float64, device=y.device)
+        iters = torch.empty(ncells, dtype=torch.int32, device=y.device)
+        resid = torch.empty(ncells, dtype=torch.float64, device=y.device)
+        status = torch.empty(ncells, dtype=torch.int32, device=y.device)
+    else:
+        x, iters, resid, status = out[:4]
+    _check(lib().bcs_solve_batch_mech(plan.handle, ncells, y.data_ptr(), k.data_ptr(), ks, g.data_ptr(), gs,
+                                      b.data_ptr(), x0.data_ptr() if x0 is not None else None, float(rtol),
+                                      int(maxit), x.data_ptr(), iters.data_ptr(), resid.data_ptr(),
+                                      status.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle()))
+    return x, iters, resid, status
+
+
 def solve_batch_adjoint(plan: Plan, values, gamma, x, g, rtol: float = 1e-10, maxit: int = 200,
                         grad_kind: str = "A", grad_gamma: bool = False, workspace=None):
     """Adjoint solve: returns (grad_b = lambda, grad_vals, grad_gamma, iters, resid, status).
@@ -479,6 +550,7 @@ class Mechanism:
         if re.shape != pr.shape:
             raise ValueError("reactants and products must both have shape [R, 2]")
         self.n, self.nnz, self.R = int(n), int(ci.shape[0]), int(re.shape[0])
+        self.row_ptr, self.col_idx = rp, ci
         if rp.shape[0] != self.n + 1:
             raise ValueError("row_ptr must have n + 1 entries")
         h = ctypes.c_void_p()

@@ -300,8 +300,10 @@ struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
   std::vector<int> seg;               // slot segment lengths (specialised kernels)
   int flags = 0;                      // schedule shape (specialised kernels)
-  bool occ = false;                   // built for three waves per SIMD
-  int occ_flags = 0;                  // its extra schedule flags (kSchedLean | kSchedPack [| kSchedWin8])
+  int mtbase = 0;                     // MECH kernels: LDS offset (doubles) of the mechanism tables
+  bool occ = false;                   // built with extra schedule flags for more waves per SIMD
+  int occ_flags = 0;                  // those flags (kSchedLean | kSchedPack [| kSchedWin8])
+  int waves = 0;                      // waves per SIMD the build asked for (0 = the compiler's choice)
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -676,7 +678,7 @@ bool occupancy_build() {
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
                 int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out,
-                bool grouped = false) {
+                bool grouped = false, const bcs_mechanism* mech = nullptr) {
   const int rpl = (n + lanes - 1) / lanes;
   Kernel K;
   K.lanes = lanes;
@@ -691,44 +693,64 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    // Forward FP64 kernels are first built for three waves per SIMD: the
-    // rarely used slot vectors in LDS (kSchedLean) and packed gather
-    // addresses; if that build spills registers, the default build (all
-    // vectors in registers, occupancy set by the compiler) is used.
-    bool occ = !mixed && !adjoint && !grouped && waves_per_eu == 0 && occupancy_build();
-    // the three-wave builds tried in turn: packed addresses, then also a
-    // gather window of 8 (fewer registers in flight)
-    const int occ_opts[2] = {bcs::kSchedLean | bcs::kSchedPack, bcs::kSchedLean | bcs::kSchedPack | bcs::kSchedWin8};
-    int occ_try = 0;
-    for (;;) {
-      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, occ);
+    // Builds tried in turn, the first that compiles without spilling is kept.
+    // Forward FP64 kernels: three waves per SIMD with the rarely used slot
+    // vectors in LDS (kSchedLean) and packed gather addresses, then the same
+    // with a gather window of 8, then the default build (all vectors in
+    // registers, occupancy set by the compiler).  The mixed form: two waves
+    // per SIMD, then the default build.
+    struct Attempt {
+      int extra, waves;
+    };
+    std::vector<Attempt> tries;
+    const bool tuned = waves_per_eu == 0 && occupancy_build();
+    if (tuned && !mixed && !adjoint && !grouped) {
+      tries.push_back({bcs::kSchedLean | bcs::kSchedPack, 3});
+      tries.push_back({bcs::kSchedLean | bcs::kSchedPack | bcs::kSchedWin8, 3});
+    } else if (tuned && mixed) {
+      tries.push_back({0, 2});
+    }
+    tries.push_back({0, waves_per_eu});
+    size_t at = 0;
+    for (;; ++at) {
+      const Attempt& A = tries[at];
+      const bool last = at + 1 == tries.size();
+      const bool lean = (A.extra & bcs::kSchedLean) != 0;
+      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, lean);
       if (!layout_fits(K.layout)) {
-        if (occ) {
-          if (verbose())
-            std::fprintf(stderr, "[bcs] lanes=%d: the three-wave layout needs %zu bytes of LDS; default build\n",
-                         lanes, K.layout.bytes);
-          occ = false;
-          continue;
-        }
-        return BCS_ERR_UNSUPPORTED;
+        if (last) return BCS_ERR_UNSUPPORTED;
+        if (verbose())
+          std::fprintf(stderr, "[bcs] lanes=%d: build %zu needs %zu bytes of LDS; next build\n", lanes, at,
+                       K.layout.bytes);
+        continue;
       }
       K.lds = K.layout.bytes;
-      const int extra = occ ? occ_opts[occ_try] : 0;
+      if (mech) {
+        // after the schedule tables: room for the shared rate constants and
+        // the mechanism's J gather lists
+        K.mtbase = (int)(K.layout.tbase + table_doubles(n, lanes, S.ksteps));
+        const size_t words = (size_t)mech->nnz + 1 + 2 * (size_t)mech->nj;
+        K.lds = ((size_t)K.mtbase + mech->R + (words + 1) / 2) * sizeof(double);
+        if (K.lds > device_max_lds()) {
+          if (last) return BCS_ERR_UNSUPPORTED;
+          continue;
+        }
+      }
       const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes,
-                                     S.flags | extra, S.seg.data(), rpl, occ ? 3 : waves_per_eu, K.lds, &K.jit, err,
-                                     sizeof(err));
+                                     S.flags | A.extra, S.seg.data(), rpl, A.waves, K.lds, &K.jit, err, sizeof(err),
+                                     mech != nullptr);
       if (rc != BCS_OK) return fail(rc, "%s", err);
-      if (occ && K.jit.scratch > 0) {
+      if (!last && K.jit.scratch > 0) {
         if (verbose())
-          std::fprintf(stderr, "[bcs] lanes=%d: three-wave build %d spills %d bytes per lane\n", lanes, occ_try,
+          std::fprintf(stderr, "[bcs] lanes=%d: build %zu spills %d bytes per lane; next build\n", lanes, at,
                        K.jit.scratch);
-        if (++occ_try == 2) occ = false;
         continue;
       }
       break;
     }
-    K.occ = occ;
-    K.occ_flags = occ ? occ_opts[occ_try] : 0;
+    K.occ = !tries[at].extra ? false : true;
+    K.occ_flags = tries[at].extra;
+    K.waves = tries[at].waves;
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
     if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
@@ -772,9 +794,10 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   }
   if (verbose())
     std::fprintf(stderr,
-                 "[bcs] kernel %s%s%s lanes=%d rpl=%d steps=%d shape=%d extra=%d adjoint=%d lds=%zu blocks/CU=%d\n",
-                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", K.occ ? " occupancy-3" : "", lanes, K.rpl,
-                 K.ksteps, K.flags, K.occ_flags, adjoint, K.lds, K.max_blocks);
+                 "[bcs] kernel %s%s lanes=%d rpl=%d steps=%d shape=%d extra=%d waves=%d adjoint=%d lds=%zu "
+                 "blocks/CU=%d\n",
+                 use_jit ? "jit" : "precompiled", mixed ? " mixed" : "", lanes, K.rpl, K.ksteps, K.flags, K.occ_flags,
+                 K.waves, adjoint, K.lds, K.max_blocks);
   *out = K;
   return BCS_OK;
 }
@@ -818,6 +841,8 @@ struct bcs_plan {
   bcs_options opt{};
   std::vector<int> rp, ci;
   Kernel fwd, adj;
+  const bcs_mechanism* mech = nullptr;  // plans made by bcs_plan_create_mech
+  Kernel fwd_mech;                      // their forward kernel that assembles J while staging
   int32_t* diag_pos = nullptr;
   int16_t* coo_row = nullptr;
   int16_t* coo_col = nullptr;
@@ -867,6 +892,7 @@ void release(bcs_plan* p) {
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
   free_kernel(&p->fwd);
   free_kernel(&p->adj);
+  free_kernel(&p->fwd_mech);
   if (p->diag_pos) (void)hipFree(p->diag_pos);
   if (p->coo_row) (void)hipFree(p->coo_row);
   if (cur != p->device) (void)hipSetDevice(cur);
@@ -966,6 +992,7 @@ int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, hipStream_t strea
   P.wbs = L.wbs;
   P.yoff = L.yoff;
   P.tbase = L.tbase;
+  P.mtbase = K.mtbase;
   if (K.ilu) {
     P.schedL = K.dL;
     P.schedU = K.dU;
@@ -1077,6 +1104,27 @@ int time_kernel_synthetic(const bcs_plan* p, const Kernel& K, double* seconds) {
   if (rc == BCS_OK) rc = time_launches(p, K, P, ws.ptr, 2, seconds);
   cleanup();
   return rc;
+}
+
+}  // namespace
+
+namespace {
+
+// A mechanism plan's forward kernel that assembles J while staging, built for
+// the lane count of the plan's forward kernel (again whenever a tuner changes it).
+int sync_mech(bcs_plan* p) {
+  if (!p->mech || (p->fwd_mech.buf && p->fwd_mech.lanes == p->fwd.lanes)) return BCS_OK;
+  std::vector<int> pos(p->nnz);
+  for (int k = 0; k < p->nnz; ++k) pos[k] = k;
+  Kernel K;
+  g_err.clear();
+  const int rc = make_kernel(p->n, p->rp, p->ci, pos, p->fwd.lanes, 0, true, 0, false, &K, false, p->mech);
+  if (rc != BCS_OK)
+    return g_err.empty() ? fail(rc, "no layout holds the mechanism kernel at %d lanes per cell (LDS)", p->fwd.lanes)
+                         : rc;
+  free_kernel(&p->fwd_mech);
+  p->fwd_mech = K;
+  return BCS_OK;
 }
 
 }  // namespace
@@ -1340,6 +1388,8 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
     free_kernel(&p->adj);
     p->adj = A;
   }
+  rc = sync_mech(p);
+  if (rc != BCS_OK) return rc;
   if (lanes_out) *lanes_out = best_lanes;
   return BCS_OK;
 }
@@ -1766,9 +1816,71 @@ int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* nce
       free_kernel(&p->adj);
       p->adj = A;
     }
+    const int r = sync_mech(p);
+    if (r != BCS_OK) return r;
     if (lanes_out) lanes_out[m] = p->fwd.lanes;
   }
   return BCS_OK;
+}
+
+int bcs_plan_create_mech(const bcs_mechanism* mech, const bcs_options* opt, bcs_plan** out) {
+  g_err.clear();
+  if (!out) return fail(BCS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!mech) return fail(BCS_ERR_ARG, "mechanism is NULL");
+  bcs_options o;
+  bcs_options_default(&o);
+  if (opt) o = *opt;
+  if (o.precision != BCS_FP64 || (o.precond != BCS_PRECOND_NONE && o.precond != BCS_PRECOND_JACOBI) ||
+      o.matrix_kind != BCS_J_GAMMA || o.jit != 1 || o.shared_scalars != 0)
+    return fail(BCS_ERR_UNSUPPORTED, "a mechanism plan needs FP64, no or Jacobi preconditioning, J_GAMMA, jit = 1 "
+                "and shared_scalars = 0");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != mech->device)
+    return fail(BCS_ERR_ARG, "the mechanism belongs to device %d", mech->device);
+  bcs_plan* p = nullptr;
+  int rc = bcs_plan_create(mech->n, mech->nnz, mech->rp.data(), mech->ci.data(), &o, &p);
+  if (rc != BCS_OK) return rc;
+  p->mech = mech;
+  rc = sync_mech(p);
+  if (rc != BCS_OK) {
+    release(p);
+    return rc;
+  }
+  *out = p;
+  return BCS_OK;
+}
+
+int bcs_solve_batch_mech(const bcs_plan* p, int64_t ncells, const double* y, const double* k, int64_t k_stride,
+                         const double* gamma, int64_t gamma_stride, const double* b, const double* x0, double rtol,
+                         int32_t maxit, double* x, int32_t* iters, double* resid, int32_t* status, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_common(p, ncells, y, gamma, gamma_stride, rtol, maxit);
+  if (rc != BCS_OK) return rc;
+  if (!p->mech || !p->fwd_mech.buf) return fail(BCS_ERR_UNSUPPORTED, "the plan was not made from a mechanism");
+  if (k_stride != 0 && k_stride < p->mech->R) return fail(BCS_ERR_ARG, "k_stride must be 0 or at least nreact");
+  if (ncells == 0) return BCS_OK;
+  if (!k || !b || !x || !iters || !resid || !status) return fail(BCS_ERR_ARG, "k/b/x/iters/resid/status is NULL");
+  rc = check_workspace(p, ncells, workspace, workspace_bytes);
+  if (rc != BCS_OK) return rc;
+  bcs::KParams P = base_params(p, ncells, y, gamma, gamma_stride, rtol, maxit);
+  P.b = b;
+  P.x0 = x0;
+  P.x = x;
+  P.iters = iters;
+  P.resid = resid;
+  P.status = status;
+  P.refinements = nullptr;
+  P.y = y;
+  P.kr = k;
+  P.k_stride = k_stride;
+  P.mtab = p->mech->jofs;  // offsets, then the terms
+  P.mtab_words = p->mech->nnz + 1 + 2 * p->mech->nj;
+  P.mk = k_stride == 0 ? p->mech->R : 0;
+  rc = prologue(p, &P, workspace, (hipStream_t)stream);
+  if (rc != BCS_OK) return rc;
+  return launch(p, p->fwd_mech, P, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -31,28 +31,11 @@
 
 #include "bcs_internal.h"
 
-struct bcs_mechanism {
-  int n = 0, nnz = 0, R = 0;
-  int device = 0;
-  int num_cu = 0;
-  int nj = 0, nf = 0;       // J and f terms
-  // device tables (one allocation): jofs [nnz + 1], jterm [nj] (2 words each),
-  // fofs [n + 1], fterm [nf] (2 words each), reac [2 R]
-  int32_t* buf = nullptr;
-  int32_t* jofs = nullptr;
-  int32_t* jterm = nullptr;
-  int32_t* fofs = nullptr;
-  int32_t* fterm = nullptr;
-  int32_t* reac = nullptr;
-  size_t table_words = 0;
-};
-
 namespace bcs {
 namespace {
 
 constexpr int kAsmThreads = 256;
 constexpr int kAsmCellsMax = 8;    // most cells a workgroup stages at a time
-constexpr int kNoSpecies = 0xffff;  // "no other reactant" in a J term
 
 // J term: word 0 = reaction; word 1 = other reactant (16 bits, kNoSpecies =
 // none) | (S_ir + 128) << 16 | factor-2 flag << 24.
@@ -280,6 +263,8 @@ int bcs_mechanism_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const i
 
   bcs_mechanism* m = new bcs_mechanism();
   m->n = n, m->nnz = nnz, m->R = nreact, m->nj = nj, m->nf = nf;
+  m->rp.assign(row_ptr, row_ptr + n + 1);
+  m->ci.assign(col_idx, col_idx + nnz);
   m->table_words = tab.size();
   if (hipGetDevice(&m->device) != hipSuccess ||
       hipDeviceGetAttribute(&m->num_cu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess) {

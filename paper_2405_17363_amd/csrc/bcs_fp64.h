@@ -41,7 +41,11 @@ namespace bcs {
 // slot past the last cell is padding with all-zero data.  Each cell reports
 // the run's iterations, its own true residual and CONVERGED only if that
 // residual is within rtol.
-template <class S, int ADJ = -1, bool GRP = false>
+// MECH: the cell's J is assembled while it is staged, from its
+// concentrations and the mechanism's gather lists (P.y, P.kr, P.mtab), in
+// the order and rounding of the assembly kernel, instead of being read from
+// P.values.
+template <class S, int ADJ = -1, bool GRP = false, bool MECH = false>
 __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, const int32_t* ent_lds,
                                          const int32_t* diag_lds) {
   using namespace dev;
@@ -216,15 +220,48 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         const double* vals = P.values + cell * nnz;
         const double g = (P.kind == kJGamma) ? P.gamma[cell * P.gamma_stride] : 0.0;
         gam = g;
-#pragma unroll
-        for (int s = 0; s < KMAX; ++s) a[s] = vals[ent_lds[s * LANES + gl] & kEntPosMask];
         const double* bc = P.b + cell * n;
         double dv[RPL];
+        if constexpr (MECH) {
+          // J of this cell at the schedule's positions: its concentrations
+          // through the operand block (rows 0 .. n-1; the spare element n
+          // keeps its zero), each position's terms in reaction order
+          const double* yc = P.y + cell * n;
+          for (int i = gl; i < n; i += LANES) xb[i] = yc[i];
+          wave_sync();
+          const double* ksh = lds + P.mtbase;
+          const int32_t* jofs = (const int32_t*)(lds + P.mtbase + P.mk);
+          const int32_t* jterm = jofs + nnz + 1;
+          const double* kc = P.k_stride ? P.kr + cell * P.k_stride : ksh;
+          auto jval = [&](int q) {
+            double acc = 0.0;
+            for (int t = jofs[q]; t < jofs[q + 1]; ++t) {
+              const int rr = jterm[2 * t];
+              const uint32_t w1 = (uint32_t)jterm[2 * t + 1];
+              const int other = (int)(w1 & 0xffffu);
+              const double sf = (double)((int)((w1 >> 16) & 0xffu) - 128);
+              double d = kc[rr];
+              if (other != kNoSpecies) d = d * xb[other];
+              if (w1 >> 24) d = d * 2.0;
+              acc = fmat(sf, d, acc);
+            }
+            return acc;
+          };
+#pragma unroll
+          for (int s = 0; s < KMAX; ++s) a[s] = jval(ent_lds[s * LANES + gl] & kEntPosMask);
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) dv[j] = jval(diag_lds[rows[j] < n ? rows[j] : 0]);
+          wave_sync();
+        } else {
+#pragma unroll
+          for (int s = 0; s < KMAX; ++s) a[s] = vals[ent_lds[s * LANES + gl] & kEntPosMask];
+#pragma unroll
+          for (int j = 0; j < RPL; ++j) dv[j] = vals[diag_lds[rows[j] < n ? rows[j] : 0]];
+        }
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           const bool real = rows[j] < n;
           const double bj = bc[real ? rows[j] : 0];
-          dv[j] = vals[diag_lds[real ? rows[j] : 0]];
           r[j] = real ? bj : 0.0;
           BB(j) = r[j];
           XV(j) = 0;
@@ -433,7 +470,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
 }
 
-template <class S, int ADJ = -1, bool GRP = false>
+template <class S, int ADJ = -1, bool GRP = false, bool MECH = false>
 __device__ __forceinline__ void fp64_body(const KParams& P) {
   extern __shared__ double lds[];
   // The schedule's value positions and the rows' diagonal positions, shared
@@ -442,9 +479,15 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   int32_t* diag_lds = ent_lds + S::KMAX * S::LANES;
   for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
   for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
+  if constexpr (MECH) {
+    // the shared rate constants and the mechanism's gather lists
+    for (int i = threadIdx.x; i < P.mk; i += kWgThreads) lds[P.mtbase + i] = P.kr[i];
+    int32_t* mt = (int32_t*)(lds + P.mtbase + P.mk);
+    for (int i = threadIdx.x; i < P.mtab_words; i += kWgThreads) mt[i] = P.mtab[i];
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  fp64_run<S, ADJ, GRP>(P, lds, wv, ent_lds, diag_lds);
+  fp64_run<S, ADJ, GRP, MECH>(P, lds, wv, ent_lds, diag_lds);
 }
 
 // Several mechanisms in one persistent launch.  Every wave drains the

@@ -7,6 +7,29 @@
 #include "../../include/bcs.h"
 #include "bcs_kdefs.h"
 
+#ifdef __cplusplus
+#include <vector>
+#endif
+
+// A mass-action mechanism on a pattern (bcs_mechanism_create): host copies of
+// the pattern and the device gather tables of its rates and Jacobian.
+struct bcs_mechanism {
+  int n = 0, nnz = 0, R = 0;
+  int device = 0;
+  int num_cu = 0;
+  int nj = 0, nf = 0;  // J and f terms
+  std::vector<int> rp, ci;
+  // device tables (one allocation): jofs [nnz + 1], jterm [nj] (2 words each),
+  // fofs [n + 1], fterm [nf] (2 words each), reac [2 R]
+  int32_t* buf = nullptr;
+  int32_t* jofs = nullptr;
+  int32_t* jterm = nullptr;
+  int32_t* fofs = nullptr;
+  int32_t* fterm = nullptr;
+  int32_t* reac = nullptr;
+  size_t table_words = 0;
+};
+
 namespace bcs {
 
 static_assert(kConverged == BCS_CONVERGED && kMaxit == BCS_MAXIT && kBreakdown == BCS_BREAKDOWN &&
@@ -48,7 +71,7 @@ struct JitKernel {
 // the FP64 forward body with one wave's cells solved as one system.  Returns
 // BCS_OK or an error code with the message in `err`.
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
-               int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
+               int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen, bool mech = false);
 
 // Prologue of every solve (bcs_order.hip), on `stream`: zero the work queue
 // (kQueueWords words) and, when `order` is not null, fill order[0, ncells)

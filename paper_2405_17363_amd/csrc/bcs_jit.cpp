@@ -207,7 +207,7 @@ void sched_type(std::ostringstream& src, int lanes, int flags, const int* seg, i
 
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
                int waves_per_eu,
-               size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
+               size_t lds_bytes, JitKernel* out, char* err, size_t errlen, bool mech) {
   std::ostringstream src;
   src << "// device sources " << kJitSourceHash << "\n"  // no compiler cache may reuse code across header versions
       << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
@@ -215,11 +215,12 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
   if (waves_per_eu > 0) src << ", " << waves_per_eu;
   // kernel names tell the forms apart in profiles
   const bool fp64 = std::string(body) == "fp64_body";
-  const char* name = fp64 ? (adjoint ? "bcs_solve_adjoint" : (grouped ? "bcs_solve_fp64_grouped" : "bcs_solve_fp64"))
+  const char* name = fp64 ? (adjoint ? "bcs_solve_adjoint"
+                                     : (grouped ? "bcs_solve_fp64_grouped" : (mech ? "bcs_solve_fp64_mech" : "bcs_solve_fp64")))
                           : "bcs_solve_mixed";
   src << ") " << name << "(bcs::KParams P) {\n  bcs::" << body << "<";
   sched_type(src, lanes, flags, seg, rpl);
-  if (fp64) src << ", " << (adjoint ? 1 : 0) << ", " << (grouped ? "true" : "false");
+  if (fp64) src << ", " << (adjoint ? 1 : 0) << ", " << (grouped ? "true" : "false") << ", " << (mech ? "true" : "false");
   src << ">(P);\n}\n";
   return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen);
 }

@@ -89,6 +89,8 @@ constexpr int kSchedWin8 = 8;
 // kSlotVecs + 1 blocks of RPL x LANES doubles).
 constexpr int kSchedLean = 16;
 constexpr int16_t kRowSpan = -2;
+// A J term word 1: the other reactant (16 bits; kNoSpecies = none) | (S + 128) << 16 | factor 2 << 24.
+constexpr int kNoSpecies = 0xffff;
 
 struct DevSchedule {
   const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
@@ -153,6 +155,17 @@ struct KParams {
   int32_t fprog_words;
   int32_t sweeps;           // Jacobi sweeps per triangular solve
   int32_t fs;               // slot block stride (doubles): the factor block, later the operand
+  // Solves from a mechanism (kernels compiled with MECH): J is assembled per
+  // cell from the concentrations y [ncells, n] and rate constants (k[c *
+  // k_stride + r]) while the cell is staged, by the mechanism's gather lists
+  // (per CSR position: offsets [nnz + 1], then two words per term), copied
+  // into LDS at mtbase (doubles) after the shared rate constants (mk doubles).
+  const double* y;
+  const double* kr;
+  int64_t k_stride;
+  const int32_t* mtab;
+  int32_t mtab_words;
+  int32_t mtbase, mk;
 };
 
 // ILU(0) factor block of a slot: the nnz values in CSR order, then three

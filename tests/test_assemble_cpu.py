@@ -50,3 +50,10 @@ def test_species_out_of_range_are_rejected(reac, prod, what):
 def test_malformed_pattern_is_rejected():
     rc, msg, h = _create(2, [0, 2, 3], [1, 0, 1], [[0, -1]], [[1, -1]])
     assert rc == -2 and "increasing" in msg
+
+
+def test_mechanism_plan_needs_a_mechanism():
+    L = bcs.lib()
+    h = ctypes.c_void_p()
+    assert L.bcs_plan_create_mech(None, None, ctypes.byref(h)) == -1
+    assert "mechanism" in L.bcs_last_error().decode() and not h.value
