@@ -433,6 +433,15 @@ int bcs_solve_batch_mech(const bcs_plan* plan, int64_t ncells, const double* y, 
                          int32_t maxit, double* x, int32_t* iters, double* resid, int32_t* status, void* workspace,
                          size_t workspace_bytes, void* stream);
 
+/* Debug aid for the persistent work queue (Section 3.2's remainder handling
+ * replaced by work stealing): while `counts` (a device int32 array of at
+ * least ncells zeros) is set, every forward, adjoint, mixed or ILU(0) solve
+ * issued from this host thread with one mechanism increments counts[c] each
+ * time it writes cell c's outputs, so a caller can check that every cell is
+ * handed out exactly once.  NULL turns it off (the default).  Not for
+ * bcs_solve_multi.  Adds one atomic per cell. */
+void bcs_debug_count_visits(int32_t* counts);
+
 /* Description of the last error on this thread ("" if none).  Errors are
  * argument, pattern or runtime failures of a call, reported synchronously;
  * the numerical outcome of each cell's solve (Section 3.1's per-cell

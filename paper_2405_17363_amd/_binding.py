@@ -126,6 +126,8 @@ def lib():
         L.bcs_plan_create_mech.restype = ctypes.c_int
         L.bcs_solve_batch_mech.argtypes = [P, I64, P, P, I64, P, I64, P, P, D, I32, P, P, P, P, P, SZ, VP]
         L.bcs_solve_batch_mech.restype = ctypes.c_int
+        L.bcs_debug_count_visits.argtypes = [P]
+        L.bcs_debug_count_visits.restype = None
         L.bcs_last_error.argtypes = []
         L.bcs_last_error.restype = ctypes.c_char_p
         _lib = L

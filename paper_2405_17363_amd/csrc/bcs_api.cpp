@@ -20,6 +20,7 @@
 namespace {
 
 thread_local std::string g_err;
+thread_local int32_t* g_visits = nullptr;  // bcs_debug_count_visits
 
 int fail(int code, const char* fmt, ...) {
   char buf[640];
@@ -676,9 +677,12 @@ bool occupancy_build() {
 
 // Build the kernel for one matrix (A or A^T) and one lanes-per-cell choice.
 // Returns BCS_ERR_UNSUPPORTED (without message) when nothing fits.
+// force_occ (forward FP64 kernels): 0 = the build chain below; 1 or 2 = only
+// the first or second three-wave build, kept even if it spills (for the data
+// autotuner, which times it against the others).
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
                 int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out,
-                bool grouped = false, const bcs_mechanism* mech = nullptr) {
+                bool grouped = false, const bcs_mechanism* mech = nullptr, int force_occ = 0) {
   const int rpl = (n + lanes - 1) / lanes;
   Kernel K;
   K.lanes = lanes;
@@ -704,13 +708,19 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     };
     std::vector<Attempt> tries;
     const bool tuned = waves_per_eu == 0 && occupancy_build();
-    if (tuned && !mixed && !adjoint && !grouped) {
-      tries.push_back({bcs::kSchedLean | bcs::kSchedPack, 3});
-      tries.push_back({bcs::kSchedLean | bcs::kSchedPack | bcs::kSchedWin8, 3});
-    } else if (tuned && mixed) {
-      tries.push_back({0, 2});
+    const Attempt occ_builds[2] = {{bcs::kSchedLean | bcs::kSchedPack, 3},
+                                   {bcs::kSchedLean | bcs::kSchedPack | bcs::kSchedWin8, 3}};
+    if (force_occ > 0 && !mixed && !adjoint && !grouped) {
+      tries.push_back(occ_builds[force_occ - 1]);
+    } else {
+      if (tuned && !mixed && !adjoint && !grouped) {
+        tries.push_back(occ_builds[0]);
+        tries.push_back(occ_builds[1]);
+      } else if (tuned && mixed) {
+        tries.push_back({0, 2});
+      }
+      tries.push_back({0, waves_per_eu});
     }
-    tries.push_back({0, waves_per_eu});
     size_t at = 0;
     for (;; ++at) {
       const Attempt& A = tries[at];
@@ -753,7 +763,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.waves = tries[at].waves;
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
-    if (K.jit.scratch > 0 && !adjoint && !mixed) return BCS_ERR_UNSUPPORTED;
+    if (K.jit.scratch > 0 && !adjoint && !mixed && force_occ == 0) return BCS_ERR_UNSUPPORTED;
     K.max_blocks = K.jit.max_blocks;
     K.seg = S.seg;
     K.flags = S.flags;
@@ -910,6 +920,7 @@ bcs::KParams base_params(const bcs_plan* p, int64_t ncells, const double* values
   P.gamma_stride = gamma_stride;
   P.rtol = rtol;
   P.maxit = maxit;
+  P.visits = g_visits;
   P.precond = p->opt.precond;
   P.kind = p->opt.matrix_kind;
   P.rr = p->opt.residual_replacement;
@@ -1090,6 +1101,7 @@ int time_kernel_synthetic(const bcs_plan* p, const Kernel& K, double* seconds) {
     return fail(BCS_ERR_HIP, "autotune setup: %s", hipGetErrorString(e));
   }
   bcs::KParams P = base_params(p, C, dv, dg, 0, 1e-10, 200);
+  P.visits = nullptr;
   P.kind = bcs::kADirect;
   P.b = db;
   P.xin = dx;
@@ -1356,28 +1368,43 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
   const bool ilu = p->opt.precond == BCS_PRECOND_ILU0;
   const int cand[3] = {16, 32, 64};
+  // Candidates: every lane count's kernel from the build chain, and for
+  // forward FP64 plans also the three-wave builds the chain dropped because
+  // they spill (a few spilled registers can cost less than a wave per SIMD).
+  const bool fp64_fwd = !ilu && p->opt.precision == BCS_FP64 && p->opt.shared_scalars == 0 && jit &&
+                        occupancy_build();
   for (int L : cand) {
-    if (L == p->fwd.lanes || (!ilu && !adjoint_fits(p->n, trp, tci, tpos, L))) continue;
-    Kernel K;
-    g_err.clear();
-    int r = ilu ? make_ilu_kernel(p->n, p->rp, p->ci, L, p->opt.ilu_sweeps, &K)
-                : make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K);
-    if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
-    if (r != BCS_OK) return r;
-    double t = 0;
-    r = time_launches(p, K, P, ws.ptr, 2, &t);
-    if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", L, t * 1e6);
-    if (r != BCS_OK) {
-      free_kernel(&K);
-      return r;
-    }
-    if (t < best) {
-      best = t;
-      best_lanes = L;
-      free_kernel(&p->fwd);
-      p->fwd = K;
-    } else {
-      free_kernel(&K);
+    if (!ilu && !adjoint_fits(p->n, trp, tci, tpos, L)) continue;
+    for (int force = 0; force <= (fp64_fwd ? 2 : 0); ++force) {
+      if (L == p->fwd.lanes && force == 0) continue;  // the plan's own kernel was timed first
+      Kernel K;
+      g_err.clear();
+      int r = ilu ? make_ilu_kernel(p->n, p->rp, p->ci, L, p->opt.ilu_sweeps, &K)
+                  : make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K,
+                                false, nullptr, force);
+      if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
+      if (r != BCS_OK) return r;
+      if (force > 0 && K.jit.scratch == 0) {  // the chain keeps such a build itself
+        free_kernel(&K);
+        continue;
+      }
+      double t = 0;
+      r = time_launches(p, K, P, ws.ptr, 2, &t);
+      if (verbose())
+        std::fprintf(stderr, "[bcs] autotune (data) lanes=%d build=%d spill=%d: %.1f us\n", L, force,
+                     K.jit.scratch, t * 1e6);
+      if (r != BCS_OK) {
+        free_kernel(&K);
+        return r;
+      }
+      if (t < best) {
+        best = t;
+        best_lanes = L;
+        free_kernel(&p->fwd);
+        p->fwd = K;
+      } else {
+        free_kernel(&K);
+      }
     }
   }
   if (!ilu && p->adj.lanes != best_lanes) {
@@ -1678,6 +1705,7 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     const int m = order[q];
     const bcs_plan* p = plans[m];
     bcs::KParams P = base_params(p, ncells[m], values[m], gamma[m], gamma_stride[m], rtol, maxit);
+    P.visits = nullptr;  // cell indices repeat across mechanisms
     P.b = b[m];
     P.x = x[m];
     P.iters = iters[m];
@@ -1822,6 +1850,8 @@ int bcs_multi_autotune(int32_t nmech, bcs_plan* const* plans, const int64_t* nce
   }
   return BCS_OK;
 }
+
+void bcs_debug_count_visits(int32_t* counts) { g_visits = counts; }
 
 int bcs_plan_create_mech(const bcs_mechanism* mech, const bcs_options* opt, bcs_plan** out) {
   g_err.clear();

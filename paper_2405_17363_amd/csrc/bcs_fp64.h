@@ -180,6 +180,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = 0;
+      if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
     }
     active = false;
   };

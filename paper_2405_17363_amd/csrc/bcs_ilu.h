@@ -184,6 +184,7 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = 0;
+      if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
     }
     active = false;
   };

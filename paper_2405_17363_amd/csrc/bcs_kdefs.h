@@ -166,6 +166,10 @@ struct KParams {
   const int32_t* mtab;
   int32_t mtab_words;
   int32_t mtbase, mk;
+  // Debug (bcs_debug_count_visits): every time a cell's outputs are written,
+  // visits[cell] is incremented, so a test can check that the work queue
+  // hands every cell out exactly once.  Null in normal use.
+  int32_t* visits;
 };
 
 // ILU(0) factor block of a slot: the nnz values in CSR order, then three

@@ -87,6 +87,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = nref;
+      if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
     }
     active = false;
   };

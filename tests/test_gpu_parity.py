@@ -507,3 +507,42 @@ def test_warm_start_matches_the_oracle_and_saves_iterations():
     bcs.solve_batch(plan, V, G, B, RTOL, 200, out=out, x0=xin)
     torch.cuda.synchronize()
     assert np.array_equal(xin.cpu().numpy(), x)
+
+
+@pytest.mark.parametrize("form", ["fp64", "adjoint", "mixed", "ilu0"])
+def test_work_queue_hands_every_cell_out_exactly_once(form):
+    """Debug counter (bcs_debug_count_visits): on the 100k-cell workload, in
+    the cost order, every cell's outputs are written exactly once, and the
+    outputs (pre-filled with sentinels) are all written."""
+    mech, cells = config_inputs(3)[0]
+    C = cells["b"].shape[0]
+    kw = {"fp64": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"}, "ilu0": {"precond": "ilu0"}}[form]
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, **kw)
+    V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
+    counts = torch.zeros(C, dtype=torch.int32, device="cuda")
+    L = bcs.lib()
+    if form == "adjoint":
+        x, _, _, _, _ = bcs.solve_batch(plan, V, G, B, RTOL, 200)
+        torch.cuda.synchronize()
+        L.bcs_debug_count_visits(counts.data_ptr())
+        try:
+            _, _, _, it, res, st = bcs.solve_batch_adjoint(plan, V, G, x, B, RTOL, 200)
+            torch.cuda.synchronize()
+        finally:
+            L.bcs_debug_count_visits(None)
+    else:
+        out = (torch.full((C, mech.n), np.nan, dtype=torch.float64, device="cuda"),
+               torch.full((C,), -7, dtype=torch.int32, device="cuda"),
+               torch.full((C,), np.nan, dtype=torch.float64, device="cuda"),
+               torch.full((C,), -7, dtype=torch.int32, device="cuda"),
+               torch.full((C,), -7, dtype=torch.int32, device="cuda"))
+        L.bcs_debug_count_visits(counts.data_ptr())
+        try:
+            _, it, res, st, _ = bcs.solve_batch(plan, V, G, B, RTOL, 200, out=out)
+            torch.cuda.synchronize()
+        finally:
+            L.bcs_debug_count_visits(None)
+    c = counts.cpu().numpy()
+    assert np.all(c == 1), (np.bincount(c), np.nonzero(c != 1)[0][:10])
+    st = st.cpu().numpy()
+    assert np.all((st >= 0) & (st <= 3)) and np.all(it.cpu().numpy() >= 0)
