@@ -301,7 +301,10 @@ struct Kernel {
   int lanes = 0, rpl = 0, ksteps = 0, adjoint = 0;
   std::vector<int> seg;               // slot segment lengths (specialised kernels)
   int flags = 0;                      // schedule shape (specialised kernels)
-  int mtbase = 0;                     // MECH kernels: LDS offset (doubles) of the mechanism tables
+  int mtbase = 0;                     // kernels that assemble J: LDS offset (doubles) of the rate constants,
+  std::vector<int> mterms;            // the J term program's shape (terms per position),
+  int mwords = 0;                     // its size in 32-bit words
+  void* mbuf = nullptr;               // and its device copy
   bool occ = false;                   // built with extra schedule flags for more waves per SIMD
   int occ_flags = 0;                  // those flags (kSchedLean | kSchedPack [| kSchedWin8])
   int waves = 0;                      // waves per SIMD the build asked for (0 = the compiler's choice)
@@ -368,8 +371,73 @@ int upload_schedule(const HostSchedule& S, Kernel* K) {
 void free_kernel(Kernel* K) {
   if (K->buf) (void)hipFree(K->buf);
   if (K->ibuf) (void)hipFree(K->ibuf);
+  if (K->mbuf) (void)hipFree(K->mbuf);
   K->buf = nullptr;
   K->ibuf = nullptr;
+  K->mbuf = nullptr;
+}
+
+// J term program of a kernel that assembles J while staging a cell (the
+// mechanism's J gather lists rearranged for the kernel's schedule).  Lane l
+// evaluates P = ksteps + rpl positions: the value position of each of its
+// schedule steps, then the diagonal position of each of its rows (of row 0
+// for a padding row, as the staging code reads them).  Position p has
+// terms[p] terms on every lane, the largest count among the lanes; entry
+// (p, t, l) is the word pair (start(p) + t) * lanes + l: the LDS byte address
+// of the term's rate constant (the rate constants sit at mtbase doubles,
+// followed by a zero that padding terms read) | factor 2 in bit 0 | the byte
+// offset of the y factor in the cell's operand block (the other reactant, or
+// element n + 1, which holds 1, for a first-order term and for padding) <<
+// 16, then the high word of S as a double (0 for padding).  False if the
+// rate constants lie beyond 16-bit LDS addresses.
+bool mech_program(const HostSchedule& S, int n, int lanes, int rpl, const std::vector<int>& rp,
+                  const std::vector<int>& ci, const bcs_mechanism& m, int mtbase, std::vector<int>* terms,
+                  std::vector<int32_t>* prog) {
+  if ((size_t)(mtbase + m.R + 1) * sizeof(double) > 65536) return false;
+  std::vector<int> diag(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) diag[i] = k;
+  const int np = S.ksteps + rpl;
+  std::vector<int> posq((size_t)np * lanes);  // position of (p, l)
+  for (int l = 0; l < lanes; ++l) {
+    for (int st = 0; st < S.ksteps; ++st) posq[(size_t)st * lanes + l] = S.ent[(size_t)st * lanes + l] & bcs::kEntPosMask;
+    for (int j = 0; j < rpl; ++j) {
+      const int rj = S.row[(size_t)j * lanes + l];
+      const int row = rj >= 0 ? rj : n;
+      posq[(size_t)(S.ksteps + j) * lanes + l] = diag[row < n ? row : 0] & bcs::kEntPosMask;
+    }
+  }
+  const int32_t* jofs = m.htab.data() + m.jofs_at;
+  const int32_t* jterm = m.htab.data() + m.jterm_at;
+  terms->assign(np, 0);
+  for (int p = 0; p < np; ++p)
+    for (int l = 0; l < lanes; ++l) {
+      const int q = posq[(size_t)p * lanes + l];
+      (*terms)[p] = std::max((*terms)[p], jofs[q + 1] - jofs[q]);
+    }
+  prog->clear();
+  const uint32_t one = (uint32_t)(n + 1) * 8u;
+  for (int p = 0; p < np; ++p)
+    for (int t = 0; t < (*terms)[p]; ++t)
+      for (int l = 0; l < lanes; ++l) {
+        const int q = posq[(size_t)p * lanes + l];
+        const int k = jofs[q] + t;
+        uint32_t w0 = (uint32_t)(mtbase + m.R) * 8u | one << 16;  // k = 0, y factor 1
+        double sf = 0.0;
+        if (k < jofs[q + 1]) {
+          const uint32_t w1 = (uint32_t)jterm[2 * k + 1];
+          const uint32_t other = w1 & 0xffffu;
+          w0 = (uint32_t)(mtbase + jterm[2 * k]) * 8u | (w1 >> 24 ? 1u : 0u) |
+               (other == (uint32_t)bcs::kNoSpecies ? one : other * 8u) << 16;
+          sf = (double)((int)((w1 >> 16) & 0xffu) - 128);
+        }
+        uint64_t sbits;
+        std::memcpy(&sbits, &sf, sizeof(sbits));
+        prog->push_back((int32_t)w0);
+        prog->push_back((int32_t)(uint32_t)(sbits >> 32));  // the low word of a small integer is 0
+      }
+  return true;
 }
 
 // Transposed pattern of (rp, ci): trp/tci its CSR arrays, tpos[q] the CSR
@@ -688,6 +756,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   K.lanes = lanes;
   K.adjoint = adjoint;
   HostSchedule S;
+  std::vector<int32_t> mprog;  // J term program (kernels that assemble J)
   if (use_jit) {
     S = build_schedule_jit(n, rp, ci, pos, lanes, rpl, sched_allowed(mixed));
     if (S.ksteps < 0) return fail(BCS_ERR_UNSUPPORTED, "internal error: schedule check failed (lanes = %d)", lanes);
@@ -737,18 +806,19 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       K.lds = K.layout.bytes;
       if (mech) {
         // after the schedule tables: room for the shared rate constants and
-        // the mechanism's J gather lists
+        // the kernel's J term program
         K.mtbase = (int)(K.layout.tbase + table_doubles(n, lanes, S.ksteps));
-        const size_t words = (size_t)mech->nnz + 1 + 2 * (size_t)mech->nj;
-        K.lds = ((size_t)K.mtbase + mech->R + (words + 1) / 2) * sizeof(double);
-        if (K.lds > device_max_lds()) {
+        const bool fits = mech_program(S, n, lanes, rpl, rp, ci, *mech, K.mtbase, &K.mterms, &mprog);
+        K.mwords = (int)mprog.size();
+        K.lds = ((size_t)K.mtbase + mech->R + 1 + mprog.size() / 2) * sizeof(double);
+        if (!fits || K.lds > device_max_lds()) {
           if (last) return BCS_ERR_UNSUPPORTED;
           continue;
         }
       }
       const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes,
                                      S.flags | A.extra, S.seg.data(), rpl, A.waves, K.lds, &K.jit, err, sizeof(err),
-                                     mech != nullptr);
+                                     mech ? &K.mterms : nullptr);
       if (rc != BCS_OK) return fail(rc, "%s", err);
       if (!last && K.jit.scratch > 0) {
         if (verbose())
@@ -801,6 +871,14 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
   if (rc != BCS_OK) {
     free_kernel(&K);
     return rc;
+  }
+  if (!mprog.empty()) {
+    hipError_t e = hipMalloc(&K.mbuf, mprog.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(K.mbuf, mprog.data(), mprog.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_kernel(&K);
+      return fail(BCS_ERR_HIP, "J term program: %s", hipGetErrorString(e));
+    }
   }
   if (verbose())
     std::fprintf(stderr,
@@ -1905,9 +1983,10 @@ int bcs_solve_batch_mech(const bcs_plan* p, int64_t ncells, const double* y, con
   P.y = y;
   P.kr = k;
   P.k_stride = k_stride;
-  P.mtab = p->mech->jofs;  // offsets, then the terms
-  P.mtab_words = p->mech->nnz + 1 + 2 * p->mech->nj;
+  P.mtab = (const int32_t*)p->fwd_mech.mbuf;
+  P.mtab_words = p->fwd_mech.mwords;
   P.mk = k_stride == 0 ? p->mech->R : 0;
+  P.mr = p->mech->R;
   rc = prologue(p, &P, workspace, (hipStream_t)stream);
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd_mech, P, (hipStream_t)stream);

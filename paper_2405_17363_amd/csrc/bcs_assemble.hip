@@ -266,6 +266,9 @@ int bcs_mechanism_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const i
   m->rp.assign(row_ptr, row_ptr + n + 1);
   m->ci.assign(col_idx, col_idx + nnz);
   m->table_words = tab.size();
+  m->htab = tab;
+  m->jofs_at = jofs;
+  m->jterm_at = jterm;
   if (hipGetDevice(&m->device) != hipSuccess ||
       hipDeviceGetAttribute(&m->num_cu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess) {
     delete m;

@@ -200,6 +200,9 @@ __device__ __forceinline__ bool flush_bit(uint64_t f0, uint64_t f1, int s) {
 
 constexpr int kGatherChunk = 16;
 
+// J terms evaluated together when a kernel assembles J while staging a cell.
+constexpr int kJTermChunk = 8;
+
 // Cells a slot takes per claim when the cells come in a cost order.
 constexpr int kClaimGroup = 2;
 
@@ -447,6 +450,54 @@ __device__ __forceinline__ double qnan() {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
+
+// Shape of the J term program of a kernel that assembles J while staging a
+// cell: the lane's KMAX schedule positions, then its RPL rows' diagonal
+// positions, and for each of these P positions the number of terms T[p]
+// every lane evaluates (the largest term count among the lanes; shorter
+// lists are padded with terms that add nothing).  The program itself, two
+// words per (position, term, lane), is data (KParams::mtab); its shape is
+// compiled in so that every term's LDS address is a constant offset.
+template <int... T>
+struct MechTerms {
+  static constexpr bool kOn = true;
+  static constexpr int kP = sizeof...(T);
+  static constexpr int count(int p) {
+    constexpr int t[] = {T...};
+    return t[p];
+  }
+  static constexpr int start(int p) {
+    constexpr int t[] = {T...};
+    int s = 0;
+    for (int i = 0; i < p; ++i) s += t[i];
+    return s;
+  }
+  static constexpr int total() { return (0 + ... + T); }
+  // position of term u of the lane's program (terms numbered across positions)
+  static constexpr int pos_of(int u) {
+    constexpr int t[] = {T...};
+    int p = 0;
+    while (u >= t[p]) u -= t[p++];
+    return p;
+  }
+};
+struct NoMechTerms {
+  static constexpr bool kOn = false;
+  static constexpr int kP = 0;
+};
+
+// Calls f(Pos<I>{}) for I = I0 .. N-1, each with its index as a constant.
+template <int V>
+struct Pos {
+  static constexpr int value = V;
+};
+template <int I, int N, class F>
+__device__ __forceinline__ void for_pos(F&& f) {
+  if constexpr (I < N) {
+    f(Pos<I>{});
+    for_pos<I + 1, N>(f);
+  }
+}
 
 }  // namespace dev
 }  // namespace bcs

@@ -41,15 +41,17 @@ namespace bcs {
 // slot past the last cell is padding with all-zero data.  Each cell reports
 // the run's iterations, its own true residual and CONVERGED only if that
 // residual is within rtol.
-// MECH: the cell's J is assembled while it is staged, from its
-// concentrations and the mechanism's gather lists (P.y, P.kr, P.mtab), in
+// MT (a dev::MechTerms): the cell's J is assembled while it is staged, from
+// its concentrations and the kernel's J term program (P.y, P.kr, P.mtab), in
 // the order and rounding of the assembly kernel, instead of being read from
 // P.values.
-template <class S, int ADJ = -1, bool GRP = false, bool MECH = false>
+template <class S, int ADJ = -1, bool GRP = false, class MT = dev::NoMechTerms>
 __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, const int32_t* ent_lds,
                                          const int32_t* diag_lds) {
   using namespace dev;
   static_assert(!GRP || ADJ == 0, "shared scalars: forward solves only");
+  constexpr bool MECH = MT::kOn;
+  static_assert(!MECH || MT::kP == S::KMAX + S::RPL, "J term program: one entry per schedule step and row");
   const bool adjoint = ADJ < 0 ? (P.adjoint != 0) : (ADJ == 1);
   constexpr int LANES = S::LANES, RPL = S::RPL, KMAX = S::KMAX;
   constexpr int RL = GRP ? 64 : LANES;  // lanes an inner product spans
@@ -71,6 +73,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   // Padding rows only ever store 0 there, and padding steps of the schedule
   // gather it, so it starts at 0 and a padding step adds value * 0.
   if (gl == 0) xb[n] = 0.0;
+  if constexpr (MECH) {
+    if (gl == 0) xb[n + 1] = 1.0;  // y factor of the first-order J terms
+  }
   wave_sync();
   int rows[RPL];
 #pragma unroll
@@ -223,35 +228,91 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         gam = g;
         const double* bc = P.b + cell * n;
         double dv[RPL];
+        double bl[RPL];  // b of the owned rows, loaded early when J is assembled here
         if constexpr (MECH) {
-          // J of this cell at the schedule's positions: its concentrations
-          // through the operand block (rows 0 .. n-1; the spare element n
-          // keeps its zero), each position's terms in reaction order
+          // J of this cell at the schedule's positions and at its rows'
+          // diagonals: the concentrations go through the operand block (rows
+          // 0 .. n-1; the spare element n keeps its zero), then every lane
+          // runs its J term program, each position's terms in reaction order
+          // (padding terms have no reaction and add nothing)
           const double* yc = P.y + cell * n;
-          for (int i = gl; i < n; i += LANES) xb[i] = yc[i];
+          {
+            // b and y: all loads in flight at once (RPL x LANES >= n)
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) bl[j] = bc[rows[j] < n ? rows[j] : 0];
+            double yl[RPL];
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) yl[j] = gl + j * LANES < n ? yc[gl + j * LANES] : 0.0;
+#pragma unroll
+            for (int j = 0; j < RPL; ++j)
+              if (gl + j * LANES < n) xb[gl + j * LANES] = yl[j];
+          }
           wave_sync();
-          const double* ksh = lds + P.mtbase;
-          const int32_t* jofs = (const int32_t*)(lds + P.mtbase + P.mk);
-          const int32_t* jterm = jofs + nnz + 1;
-          const double* kc = P.k_stride ? P.kr + cell * P.k_stride : ksh;
-          auto jval = [&](int q) {
-            double acc = 0.0;
-            for (int t = jofs[q]; t < jofs[q + 1]; ++t) {
-              const int rr = jterm[2 * t];
-              const uint32_t w1 = (uint32_t)jterm[2 * t + 1];
-              const int other = (int)(w1 & 0xffffu);
-              const double sf = (double)((int)((w1 >> 16) & 0xffu) - 128);
-              double d = kc[rr];
-              if (other != kNoSpecies) d = d * xb[other];
-              if (w1 >> 24) d = d * 2.0;
-              acc = fmat(sf, d, acc);
-            }
-            return acc;
+          const uint2* prog = (const uint2*)(lds + P.mtbase + P.mr + 1) + gl;
+          const uint32_t xaddr = lds_addr(xb);
+          // Rate constants from LDS (shared; a padding term reads the zero
+          // after them) or from the cell's row in memory: two copies of the
+          // program, each with its address space.  A term takes no branch:
+          // the y factor of a first-order term is the 1 at xb[n + 1], the
+          // factor 2 an exact ldexp by 1 or 0.  k y rounds once and S d is
+          // exact in the FMA, as in the assembly kernel, so the sums are
+          // bitwise its sums.
+          auto jprog = [&](auto mode) {
+            constexpr bool SHARED = decltype(mode)::value == 0;
+            const double* kc = P.kr + cell * P.k_stride;
+            const uint32_t kb = (uint32_t)P.mtbase * 8u;
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q) a[q] = 0.0;
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) dv[j] = 0.0;
+            // kJTermChunk terms at a time: their operands, then their
+            // arithmetic, so that the loads of a chunk are in flight
+            // together; the next chunk's program words are read meanwhile
+            constexpr int U = MT::total();
+            uint2 wn[kJTermChunk];
+#pragma unroll
+            for (int g = 0; g < kJTermChunk; ++g)
+              if (g < U) wn[g] = prog[g * LANES];
+            for_pos<0, (U + kJTermChunk - 1) / kJTermChunk>([&](auto chunk) {
+              constexpr int u0 = decltype(chunk)::value * kJTermChunk;
+              constexpr int G = U - u0 < kJTermChunk ? U - u0 : kJTermChunk;
+              constexpr int u1 = u0 + kJTermChunk;
+              uint2 w[G];
+              double kv[G], yv[G];
+#pragma unroll
+              for (int g = 0; g < G; ++g) w[g] = wn[g];
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const uint32_t ka = w[g].x & 0xfff8u;
+                if constexpr (SHARED) {
+                  kv[g] = lds_load<double>(ka);
+                } else {
+                  const uint32_t r = (ka - kb) >> 3;
+                  const bool real = r < (uint32_t)P.mr;
+                  const double v = kc[real ? r : 0];
+                  kv[g] = real ? v : 0.0;
+                }
+                yv[g] = lds_load<double>(xaddr + (w[g].x >> 16));
+              }
+#pragma unroll
+              for (int g = 0; g < kJTermChunk; ++g)
+                if (u1 + g < U) wn[g] = prog[(u1 + g) * LANES];
+              for_pos<0, G>([&](auto gg) {
+                constexpr int g = decltype(gg)::value;
+                constexpr int q = MT::pos_of(u0 + g);
+                const double sf = __builtin_bit_cast(double, (uint64_t)w[g].y << 32);
+                const double d = __builtin_amdgcn_ldexp(kv[g] * yv[g], (int)(w[g].x & 1u));
+                if constexpr (q < KMAX)
+                  a[q] = fmat(sf, d, a[q]);
+                else
+                  dv[q - KMAX] = fmat(sf, d, dv[q - KMAX]);
+              });
+            });
           };
-#pragma unroll
-          for (int s = 0; s < KMAX; ++s) a[s] = jval(ent_lds[s * LANES + gl] & kEntPosMask);
-#pragma unroll
-          for (int j = 0; j < RPL; ++j) dv[j] = jval(diag_lds[rows[j] < n ? rows[j] : 0]);
+          if (P.k_stride)
+            jprog(Pos<1>{});
+          else
+            jprog(Pos<0>{});
           wave_sync();
         } else {
 #pragma unroll
@@ -262,7 +323,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           const bool real = rows[j] < n;
-          const double bj = bc[real ? rows[j] : 0];
+          const double bj = MECH ? bl[j] : bc[real ? rows[j] : 0];
           r[j] = real ? bj : 0.0;
           BB(j) = r[j];
           XV(j) = 0;
@@ -471,8 +532,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
 
 }
 
-template <class S, int ADJ = -1, bool GRP = false, bool MECH = false>
+template <class S, int ADJ = -1, bool GRP = false, class MT = dev::NoMechTerms>
 __device__ __forceinline__ void fp64_body(const KParams& P) {
+  constexpr bool MECH = MT::kOn;
   extern __shared__ double lds[];
   // The schedule's value positions and the rows' diagonal positions, shared
   // by every cell slot of the workgroup, copied once into LDS.
@@ -481,14 +543,15 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
   for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
   if constexpr (MECH) {
-    // the shared rate constants and the mechanism's gather lists
+    // the shared rate constants, a zero, and the kernel's J term program
     for (int i = threadIdx.x; i < P.mk; i += kWgThreads) lds[P.mtbase + i] = P.kr[i];
-    int32_t* mt = (int32_t*)(lds + P.mtbase + P.mk);
+    if (threadIdx.x == 0) lds[P.mtbase + P.mr] = 0.0;
+    int32_t* mt = (int32_t*)(lds + P.mtbase + P.mr + 1);
     for (int i = threadIdx.x; i < P.mtab_words; i += kWgThreads) mt[i] = P.mtab[i];
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  fp64_run<S, ADJ, GRP, MECH>(P, lds, wv, ent_lds, diag_lds);
+  fp64_run<S, ADJ, GRP, MT>(P, lds, wv, ent_lds, diag_lds);
 }
 
 // Several mechanisms in one persistent launch.  Every wave drains the

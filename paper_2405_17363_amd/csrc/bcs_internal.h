@@ -19,6 +19,8 @@ struct bcs_mechanism {
   int num_cu = 0;
   int nj = 0, nf = 0;  // J and f terms
   std::vector<int> rp, ci;
+  std::vector<int32_t> htab;  // host copy of the device tables (same word offsets)
+  int jofs_at = 0, jterm_at = 0;  // word offsets of jofs and jterm in htab
   // device tables (one allocation): jofs [nnz + 1], jterm [nj] (2 words each),
   // fofs [n + 1], fterm [nf] (2 words each), reac [2 R]
   int32_t* buf = nullptr;
@@ -71,7 +73,8 @@ struct JitKernel {
 // the FP64 forward body with one wave's cells solved as one system.  Returns
 // BCS_OK or an error code with the message in `err`.
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
-               int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen, bool mech = false);
+               int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen,
+               const std::vector<int>* mech_terms = nullptr);
 
 // Prologue of every solve (bcs_order.hip), on `stream`: zero the work queue
 // (kQueueWords words) and, when `order` is not null, fill order[0, ncells)

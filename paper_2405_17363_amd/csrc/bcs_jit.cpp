@@ -207,7 +207,8 @@ void sched_type(std::ostringstream& src, int lanes, int flags, const int* seg, i
 
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
                int waves_per_eu,
-               size_t lds_bytes, JitKernel* out, char* err, size_t errlen, bool mech) {
+               size_t lds_bytes, JitKernel* out, char* err, size_t errlen, const std::vector<int>* mech_terms) {
+  const bool mech = mech_terms != nullptr;
   std::ostringstream src;
   src << "// device sources " << kJitSourceHash << "\n"  // no compiler cache may reuse code across header versions
       << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
@@ -220,7 +221,16 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
                           : "bcs_solve_mixed";
   src << ") " << name << "(bcs::KParams P) {\n  bcs::" << body << "<";
   sched_type(src, lanes, flags, seg, rpl);
-  if (fp64) src << ", " << (adjoint ? 1 : 0) << ", " << (grouped ? "true" : "false") << ", " << (mech ? "true" : "false");
+  if (fp64) {
+    src << ", " << (adjoint ? 1 : 0) << ", " << (grouped ? "true" : "false") << ", ";
+    if (mech) {
+      src << "bcs::dev::MechTerms<";
+      for (size_t q = 0; q < mech_terms->size(); ++q) src << (q ? ", " : "") << (*mech_terms)[q];
+      src << ">";
+    } else {
+      src << "bcs::dev::NoMechTerms";
+    }
+  }
   src << ">(P);\n}\n";
   return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen);
 }

@@ -92,6 +92,7 @@ constexpr int16_t kRowSpan = -2;
 // A J term word 1: the other reactant (16 bits; kNoSpecies = none) | (S + 128) << 16 | factor 2 << 24.
 constexpr int kNoSpecies = 0xffff;
 
+
 struct DevSchedule {
   const int32_t* ent;   // [ksteps * lanes] value position | kEntDiag, or kEntPad
   const uint8_t* col;   // [ksteps * lanes] gathered vector index (row of the other operand)
@@ -155,17 +156,21 @@ struct KParams {
   int32_t fprog_words;
   int32_t sweeps;           // Jacobi sweeps per triangular solve
   int32_t fs;               // slot block stride (doubles): the factor block, later the operand
-  // Solves from a mechanism (kernels compiled with MECH): J is assembled per
-  // cell from the concentrations y [ncells, n] and rate constants (k[c *
-  // k_stride + r]) while the cell is staged, by the mechanism's gather lists
-  // (per CSR position: offsets [nnz + 1], then two words per term), copied
-  // into LDS at mtbase (doubles) after the shared rate constants (mk doubles).
+  // Solves from a mechanism (kernels compiled with a dev::MechTerms): J is
+  // assembled per cell from the concentrations y [ncells, n] and rate
+  // constants (k[c * k_stride + r]) while the cell is staged, by the kernel's
+  // J term program.  LDS from mtbase (doubles): the mr rate constants (copied
+  // when shared: mk = mr, else mk = 0), a zero, then the program, two words
+  // per (position, term, lane): the LDS byte address of the term's rate
+  // constant (of the zero for a padding term; a multiple of 8) | factor 2 (bit
+  // 0) | the byte offset of its y factor in the operand block << 16; then the
+  // high word of S as a double (S is a small integer: the low word is 0).
   const double* y;
   const double* kr;
   int64_t k_stride;
   const int32_t* mtab;
   int32_t mtab_words;
-  int32_t mtbase, mk;
+  int32_t mtbase, mk, mr;
   // Debug (bcs_debug_count_visits): every time a cell's outputs are written,
   // visits[cell] is incremented, so a test can check that the work queue
   // hands every cell out exactly once.  Null in normal use.

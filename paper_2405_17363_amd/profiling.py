@@ -84,15 +84,16 @@ def per_dispatch(pmc_dir: str, counter: str) -> list:
     return [(k[1], k[2], v) for k, v in sorted(acc.items())]
 
 
-def counters(pmc_dirs, kernel: str, last: int = 0) -> dict:
+def counters(pmc_dirs, kernel: str, last: int = 0, drop_last: int = 0) -> dict:
     """Mean per dispatch of every counter in the `--pmc` runs `pmc_dirs` for
     `kernel` (each dispatch's value summed over instances), over its last
-    `last` dispatches (all if 0)."""
+    `last` dispatches (all if 0) once the final `drop_last` are left out."""
     out = {}
     for d in pmc_dirs:
         names = sorted({r["Counter_Name"] for r in _csv(d, "counter_collection.csv")})
         for c in names:
             v = [val for name, g, val in per_dispatch(d, c) if _is(name, kernel)]
+            v = v[:len(v) - drop_last]
             if last > 0:
                 v = v[-last:]
             if v:
@@ -101,10 +102,11 @@ def counters(pmc_dirs, kernel: str, last: int = 0) -> dict:
     return out
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0) -> dict:
+def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64", last: int = 0,
+            drop_last: int = 0) -> dict:
     """HBM bytes per launch of `kernel` (mean over its last `last` dispatches,
-    all if 0) from a FETCH_SIZE and a WRITE_SIZE run of `bench.py
-    --copy-calibration`."""
+    all if 0, once the final `drop_last` are left out) from a FETCH_SIZE and
+    a WRITE_SIZE run of `bench.py --copy-calibration`."""
     f = per_dispatch(fetch_dir, "FETCH_SIZE")
     w = per_dispatch(write_dir, "WRITE_SIZE")
     # the calibration copy is the copy kernel with the largest write
@@ -116,6 +118,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str = "bcs_solve_fp64", last
     kw = COPY_BYTES / copy_w
     fk = [v for name, g, v in f if _is(name, kernel)]
     wk = [v for name, g, v in w if _is(name, kernel)]
+    fk, wk = fk[:len(fk) - drop_last], wk[:len(wk) - drop_last]
     if last > 0:
         fk, wk = fk[-last:], wk[-last:]
     if not fk or not wk:
@@ -200,19 +203,21 @@ def main(argv=None) -> int:
     t.add_argument("--lanes", type=int, required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--last", type=int, default=0, help="average the last N dispatches only")
+    t.add_argument("--drop-last", type=int, default=0, help="leave out the final N dispatches")
     t.add_argument("--note", action="append", default=[], help="header line for the summary (repeatable)")
     c = sub.add_parser("counters")
     c.add_argument("--pmc", action="append", required=True, help="a --pmc run's output directory (repeatable)")
     c.add_argument("--kernel", default="bcs_solve_fp64")
     c.add_argument("--last", type=int, default=0)
+    c.add_argument("--drop-last", type=int, default=0, help="leave out the final N dispatches")
     a = ap.parse_args(argv)
     if a.cmd == "counters":
-        print(json.dumps(counters(a.pmc, a.kernel, a.last)))
+        print(json.dumps(counters(a.pmc, a.kernel, a.last, a.drop_last)))
         return 0
     if a.cmd == "stats":
         print(json.dumps(kernel_stats(a.trace, a.kernel, a.last, a.drop_last)))
         return 0
-    res = traffic(a.fetch, a.write, a.kernel, a.last)
+    res = traffic(a.fetch, a.write, a.kernel, a.last, a.drop_last)
     res.update({"ncells": a.ncells, "lanes_per_cell": a.lanes})
     with open(a.out, "w") as f:
         for line in a.note:
