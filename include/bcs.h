@@ -440,8 +440,10 @@ int bcs_solve_batch_mech(const bcs_plan* plan, int64_t ncells, const double* y, 
  * least ncells zeros) is set, every forward, adjoint, mixed or ILU(0) solve
  * issued from this host thread with one mechanism increments counts[c] each
  * time it writes cell c's outputs, so a caller can check that every cell is
- * handed out exactly once.  NULL turns it off (the default).  Not for
- * bcs_solve_multi.  Adds one atomic per cell. */
+ * handed out exactly once.  NULL turns it off (the default).  Only kernels
+ * compiled per pattern while the environment variable BCS_DEBUG_VISITS is
+ * set (to anything but "0") at plan creation hold the counter, which costs
+ * registers; other kernels ignore it.  Not for bcs_solve_multi. */
 void bcs_debug_count_visits(int32_t* counts);
 
 /* Description of the last error on this thread ("" if none).  Errors are

@@ -185,7 +185,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = 0;
+#ifdef BCS_COUNT_VISITS
       if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
+#endif
     }
     active = false;
   };

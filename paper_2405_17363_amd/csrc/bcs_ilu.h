@@ -184,7 +184,9 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = 0;
+#ifdef BCS_COUNT_VISITS
       if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
+#endif
     }
     active = false;
   };

@@ -163,6 +163,12 @@ int load_source(const std::string& source, const char* name, bool ilp, size_t ld
     const std::string path = dir + "/" + fname;
     std::vector<char> code;
     if (std::getenv("BCS_VERBOSE")) std::fprintf(stderr, "[bcs] jit %s %s\n", name, path.c_str());
+    if (const char* dump = std::getenv("BCS_JIT_DUMP")) {
+      // debug aid: the kernel's source beside its cache name, to rebuild it offline
+      mkdirs(dump);
+      std::vector<char> text(source.begin(), source.end());
+      write_file_atomic(std::string(dump) + "/" + fname + ".hip", text);
+    }
     if (!read_file(path, &code)) {
       std::string log;
       if (compile(source, base_arch, ilp, &code, &log) != 0) {
@@ -197,6 +203,17 @@ int load_source(const std::string& source, const char* name, bool ilp, size_t ld
   return BCS_OK;
 }
 
+// First lines of every kernel source: the device-source version (no
+// compiler cache may reuse code across header versions) and, with
+// BCS_DEBUG_VISITS set (not "0") in the environment, the per-cell output
+// counter of bcs_debug_count_visits, which costs registers and is left out
+// otherwise.
+void preamble(std::ostringstream& src) {
+  src << "// device sources " << kJitSourceHash << "\n";
+  const char* v = std::getenv("BCS_DEBUG_VISITS");
+  if (v && std::string(v) != "0") src << "#define BCS_COUNT_VISITS 1\n";
+}
+
 void sched_type(std::ostringstream& src, int lanes, int flags, const int* seg, int rpl) {
   src << "bcs::dev::StaticSched<" << lanes << ", " << flags;
   for (int j = 0; j < rpl; ++j) src << ", " << seg[j];
@@ -210,8 +227,8 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
                size_t lds_bytes, JitKernel* out, char* err, size_t errlen, const std::vector<int>* mech_terms) {
   const bool mech = mech_terms != nullptr;
   std::ostringstream src;
-  src << "// device sources " << kJitSourceHash << "\n"  // no compiler cache may reuse code across header versions
-      << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
+  preamble(src);
+  src << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
   if (waves_per_eu > 0) src << ", " << waves_per_eu;
   // kernel names tell the forms apart in profiles
@@ -238,8 +255,8 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
 int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,
                    const int* widths, int nstep, size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
   std::ostringstream src;
-  src << "// device sources " << kJitSourceHash << "\n"
-      << "#include \"bcs_ilu.h\"\n"
+  preamble(src);
+  src << "#include \"bcs_ilu.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_solve_ilu0(bcs::KParams P) {\n"
       << "  bcs::ilu_body<";
   for (int m = 0; m < 3; ++m) {
@@ -256,8 +273,8 @@ int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* c
                      size_t lds_bytes,
                      JitKernel* out, char* err, size_t errlen) {
   std::ostringstream src;
-  src << "// device sources " << kJitSourceHash << "\n"
-      << "#include \"bcs_fp64.h\"\n"
+  preamble(src);
+  src << "#include \"bcs_fp64.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_solve_multi(bcs::MultiParams P) {\n"
       << "  bcs::multi_body<";
   for (int m = 0; m < nmech; ++m) {

@@ -171,7 +171,8 @@ struct KParams {
   const int32_t* mtab;
   int32_t mtab_words;
   int32_t mtbase, mk, mr;
-  // Debug (bcs_debug_count_visits): every time a cell's outputs are written,
+  // Debug (bcs_debug_count_visits; kernels compiled with BCS_COUNT_VISITS
+  // defined): every time a cell's outputs are written,
   // visits[cell] is incremented, so a test can check that the work queue
   // hands every cell out exactly once.  Null in normal use.
   int32_t* visits;

@@ -87,7 +87,9 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
       P.resid[cell] = res;
       P.status[cell] = st;
       if (P.refinements) P.refinements[cell] = nref;
+#ifdef BCS_COUNT_VISITS
       if (P.visits) atomicAdd(P.visits + cell, 1);  // debug: outputs written per cell
+#endif
     }
     active = false;
   };

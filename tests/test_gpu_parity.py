@@ -510,10 +510,12 @@ def test_warm_start_matches_the_oracle_and_saves_iterations():
 
 
 @pytest.mark.parametrize("form", ["fp64", "adjoint", "mixed", "ilu0"])
-def test_work_queue_hands_every_cell_out_exactly_once(form):
-    """Debug counter (bcs_debug_count_visits): on the 100k-cell workload, in
-    the cost order, every cell's outputs are written exactly once, and the
-    outputs (pre-filled with sentinels) are all written."""
+def test_work_queue_hands_every_cell_out_exactly_once(form, monkeypatch):
+    """Debug counter (bcs_debug_count_visits, compiled in with
+    BCS_DEBUG_VISITS): on the 100k-cell workload, in the cost order, every
+    cell's outputs are written exactly once, and the outputs (pre-filled
+    with sentinels) are all written."""
+    monkeypatch.setenv("BCS_DEBUG_VISITS", "1")
     mech, cells = config_inputs(3)[0]
     C = cells["b"].shape[0]
     kw = {"fp64": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"}, "ilu0": {"precond": "ilu0"}}[form]
