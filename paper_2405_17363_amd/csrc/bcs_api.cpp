@@ -264,15 +264,16 @@ void slot_sizes(int n, int lanes, int rpl, bool lean, int* xs, int* bs) {
 
 size_t table_doubles(int n, int lanes, int ksteps) { return ((size_t)ksteps * lanes + (size_t)n + 1) / 2; }
 
-WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint, bool lean = false) {
+WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint, bool lean = false,
+                   int wpw = bcs::kWavesPerWg) {
   WgLayout L;
   (void)adjoint;
   slot_sizes(n, lanes, rpl, lean, &L.xs, &L.bs);
   L.yoff = lean ? bcs::kSlotVecs * rpl * lanes : 0;
   L.wxs = (64 / lanes) * L.xs;
   L.wbs = (64 / lanes) * L.bs;
-  L.bbase = bcs::kWavesPerWg * L.wxs;
-  L.tbase = L.bbase + bcs::kWavesPerWg * L.wbs;
+  L.bbase = wpw * L.wxs;
+  L.tbase = L.bbase + wpw * L.wbs;
   L.operand_bytes = (size_t)L.bbase * sizeof(double);
   L.bytes = ((size_t)L.tbase + table_doubles(n, lanes, ksteps)) * sizeof(double);
   return L;
@@ -308,6 +309,7 @@ struct Kernel {
   bool occ = false;                   // built with extra schedule flags for more waves per SIMD
   int occ_flags = 0;                  // those flags (kSchedLean | kSchedPack [| kSchedWin8])
   int waves = 0;                      // waves per SIMD the build asked for (0 = the compiler's choice)
+  int wpw = bcs::kWavesPerWg;         // waves per workgroup
   const bcs::Variant* var = nullptr;  // precompiled variant, or
   bcs::JitKernel jit;                 // specialised kernel
   int max_blocks = 1;                 // resident workgroups per CU
@@ -328,7 +330,7 @@ struct Kernel {
     if (var) return var->fp64(P, grid, stream);
     bcs::KParams copy = P;
     void* args[] = {&copy};
-    return hipModuleLaunchKernel(jit.fn, grid, 1, 1, bcs::kWgThreads, 1, 1, (unsigned)lds, stream, args, nullptr);
+    return hipModuleLaunchKernel(jit.fn, grid, 1, 1, 64 * wpw, 1, 1, (unsigned)lds, stream, args, nullptr);
   }
 };
 
@@ -750,7 +752,8 @@ bool occupancy_build() {
 // autotuner, which times it against the others).
 int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& pos,
                 int lanes, int adjoint, bool use_jit, int waves_per_eu, bool mixed, Kernel* out,
-                bool grouped = false, const bcs_mechanism* mech = nullptr, int force_occ = 0) {
+                bool grouped = false, const bcs_mechanism* mech = nullptr, int force_occ = 0,
+                int wpw = bcs::kWavesPerWg) {
   const int rpl = (n + lanes - 1) / lanes;
   Kernel K;
   K.lanes = lanes;
@@ -766,6 +769,12 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
+    // tuning override for forward FP64 kernels: waves per workgroup (1, 2, 4 or 8)
+    if (wpw == bcs::kWavesPerWg && !adjoint && !mixed && !grouped && !mech)
+      if (const char* e = std::getenv("BCS_WG_WAVES")) {
+        const int w = std::atoi(e);
+        if (w == 1 || w == 2 || w == 4 || w == 8) wpw = w;
+      }
     // Builds tried in turn, the first that compiles without spilling is kept.
     // Forward FP64 kernels: three waves per SIMD with the rarely used slot
     // vectors in LDS (kSchedLean) and packed gather addresses, then the same
@@ -795,7 +804,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       const Attempt& A = tries[at];
       const bool last = at + 1 == tries.size();
       const bool lean = (A.extra & bcs::kSchedLean) != 0;
-      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, lean);
+      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, lean, wpw);
       if (!layout_fits(K.layout)) {
         if (last) return BCS_ERR_UNSUPPORTED;
         if (verbose())
@@ -818,7 +827,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       }
       const int rc = bcs::jit_kernel(mixed ? "mixed_body" : "fp64_body", adjoint, grouped ? 1 : 0, lanes,
                                      S.flags | A.extra, S.seg.data(), rpl, A.waves, K.lds, &K.jit, err, sizeof(err),
-                                     mech ? &K.mterms : nullptr);
+                                     mech ? &K.mterms : nullptr, wpw);
       if (rc != BCS_OK) return fail(rc, "%s", err);
       if (!last && K.jit.scratch > 0) {
         if (verbose())
@@ -831,6 +840,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.occ = !tries[at].extra ? false : true;
     K.occ_flags = tries[at].extra;
     K.waves = tries[at].waves;
+    K.wpw = wpw;
     // a forward candidate that spills registers is dropped (another lane
     // count serves the pattern); the adjoint and the mixed form keep theirs
     if (K.jit.scratch > 0 && !adjoint && !mixed && force_occ == 0) return BCS_ERR_UNSUPPORTED;
@@ -839,6 +849,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.flags = S.flags;
   } else {
     if (mixed) return BCS_ERR_UNSUPPORTED;  // the mixed form exists only as specialised kernels
+    if (wpw != bcs::kWavesPerWg) return BCS_ERR_UNSUPPORTED;  // precompiled with the default workgroup
     int nv = 0;
     const bcs::Variant* vs = all_variants(&nv);
     const bcs::Variant* best = nullptr;
@@ -1062,7 +1073,7 @@ struct OwnedWorkspace {
 };
 
 int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
-  const int64_t cells_per_wg = (int64_t)bcs::kWavesPerWg * (64 / K.lanes);
+  const int64_t cells_per_wg = (int64_t)K.wpw * (64 / K.lanes);
   const int64_t need = (ncells + cells_per_wg - 1) / cells_per_wg;
   const int64_t cap = (int64_t)K.max_blocks * p->num_cu;
   return (int)std::max<int64_t>(1, std::min(need, cap));
@@ -1436,55 +1447,119 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   const bool jit = p->opt.jit == 1;
   std::vector<int> trp, tci, tpos;
   transpose_pattern(p->n, p->rp, p->ci, trp, tci, tpos);
-  int best_lanes = p->fwd.lanes;
-  double best = 1e300;
   OwnedWorkspace ws;
   int rc = ws.alloc(ws_bytes(ncells));
   if (rc != BCS_OK) return rc;
-  rc = time_launches(p, p->fwd, P, ws.ptr, 2, &best);
-  if (rc != BCS_OK) return rc;
-  if (verbose()) std::fprintf(stderr, "[bcs] autotune (data) lanes=%d: %.1f us\n", p->fwd.lanes, best * 1e6);
   const bool ilu = p->opt.precond == BCS_PRECOND_ILU0;
   const int cand[3] = {16, 32, 64};
-  // Candidates: every lane count's kernel from the build chain, and for
-  // forward FP64 plans also the three-wave builds the chain dropped because
-  // they spill (a few spilled registers can cost less than a wave per SIMD).
+  // Candidates: the plan's kernel (index 0), every lane count's kernel from
+  // the build chain, and for forward FP64 plans also the three-wave builds
+  // the chain dropped because they spill (a few spilled registers can cost
+  // less than a wave per SIMD); then, for the winner, other workgroup sizes.
+  // Launch times drift (clocks, caches), so the candidates are timed in
+  // rounds, each round launching every candidate once, and a challenger
+  // must beat the plan's kernel by a margin: 1%, 3% for a spilling build.
   const bool fp64_fwd = !ilu && p->opt.precision == BCS_FP64 && p->opt.shared_scalars == 0 && jit &&
                         occupancy_build();
+  struct Cand {
+    Kernel K;
+    int force = 0;
+    double t = 1e300;
+  };
+  std::vector<Cand> cs;
+  cs.push_back({p->fwd, 0, 1e300});
+  auto drop_all = [&](size_t keep) {
+    for (size_t i = 1; i < cs.size(); ++i)
+      if (i != keep) free_kernel(&cs[i].K);
+  };
   for (int L : cand) {
     if (!ilu && !adjoint_fits(p->n, trp, tci, tpos, L)) continue;
     for (int force = 0; force <= (fp64_fwd ? 2 : 0); ++force) {
-      if (L == p->fwd.lanes && force == 0) continue;  // the plan's own kernel was timed first
+      if (L == p->fwd.lanes && force == 0) continue;  // the plan's own kernel
       Kernel K;
       g_err.clear();
       int r = ilu ? make_ilu_kernel(p->n, p->rp, p->ci, L, p->opt.ilu_sweeps, &K)
                   : make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K,
                                 false, nullptr, force);
       if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
-      if (r != BCS_OK) return r;
+      if (r != BCS_OK) {
+        drop_all(0);
+        return r;
+      }
       if (force > 0 && K.jit.scratch == 0) {  // the chain keeps such a build itself
         free_kernel(&K);
         continue;
       }
-      double t = 0;
-      r = time_launches(p, K, P, ws.ptr, 2, &t);
-      if (verbose())
-        std::fprintf(stderr, "[bcs] autotune (data) lanes=%d build=%d spill=%d: %.1f us\n", L, force,
-                     K.jit.scratch, t * 1e6);
-      if (r != BCS_OK) {
-        free_kernel(&K);
-        return r;
-      }
-      if (t < best) {
-        best = t;
-        best_lanes = L;
-        free_kernel(&p->fwd);
-        p->fwd = K;
-      } else {
-        free_kernel(&K);
-      }
+      cs.push_back({K, force, 1e300});
     }
   }
+  auto time_rounds = [&](const std::vector<size_t>& idx) -> int {
+    for (size_t i : idx) cs[i].t = 1e300;
+    for (int round = 0; round < 3; ++round)
+      for (size_t i : idx) {
+        double t = 0;
+        const int r = time_launches(p, cs[i].K, P, ws.ptr, round == 0 ? 2 : 1, &t);
+        if (r != BCS_OK) return r;
+        cs[i].t = std::min(cs[i].t, t);
+      }
+    return BCS_OK;
+  };
+  std::vector<size_t> all(cs.size());
+  for (size_t i = 0; i < cs.size(); ++i) all[i] = i;
+  rc = time_rounds(all);
+  if (rc != BCS_OK) {
+    drop_all(0);
+    return rc;
+  }
+  if (verbose())
+    for (const Cand& c : cs)
+      std::fprintf(stderr, "[bcs] autotune (data) lanes=%d build=%d spill=%d: %.1f us\n", c.K.lanes, c.force,
+                   c.K.jit.scratch, c.t * 1e6);
+  size_t w = 0;
+  for (size_t i = 1; i < cs.size(); ++i) {
+    const double margin = cs[i].K.jit.scratch > 0 ? 0.97 : 0.99;
+    if (cs[i].t < cs[0].t * margin && cs[i].t < cs[w].t) w = i;
+  }
+  // waves per workgroup for the winner (the waves share only the schedule
+  // copy, so the count sets how often that copy is made and how LDS and
+  // registers round into whole workgroups per CU)
+  if (fp64_fwd && !cs[w].K.occ && cs[w].K.var == nullptr && cs[w].K.jit.scratch == 0) {
+    const size_t first = cs.size();
+    for (int wpw : {2, 8}) {
+      if (wpw == cs[w].K.wpw) continue;
+      Kernel K;
+      g_err.clear();
+      int r = make_kernel(p->n, p->rp, p->ci, pos, cs[w].K.lanes, 0, jit, 0, false, &K, false, nullptr, 0, wpw);
+      if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
+      if (r != BCS_OK) {
+        drop_all(0);
+        return r;
+      }
+      cs.push_back({K, 0, 1e300});
+    }
+    std::vector<size_t> idx{w};  // the winner, timed again beside the workgroup sizes
+    for (size_t i = first; i < cs.size(); ++i) idx.push_back(i);
+    rc = time_rounds(idx);
+    if (rc != BCS_OK) {
+      drop_all(0);
+      return rc;
+    }
+    if (verbose())
+      for (size_t i : idx)
+        std::fprintf(stderr, "[bcs] autotune (data) lanes=%d waves/workgroup=%d: %.1f us\n", cs[i].K.lanes,
+                     cs[i].K.wpw, cs[i].t * 1e6);
+    // a workgroup size replaces the winner only by the same margin
+    size_t w2 = w;
+    for (size_t i = first; i < cs.size(); ++i)
+      if (cs[i].t < cs[w].t * 0.99 && cs[i].t < cs[w2].t) w2 = i;
+    w = w2;
+  }
+  drop_all(w);
+  if (w != 0) {
+    free_kernel(&p->fwd);
+    p->fwd = cs[w].K;
+  }
+  const int best_lanes = p->fwd.lanes;
   if (!ilu && p->adj.lanes != best_lanes) {
     Kernel A;
     g_err.clear();
@@ -1504,7 +1579,7 @@ int bcs_plan_info(const bcs_plan* p, int32_t* lanes, int32_t* rpl, int32_t* step
   if (lanes) *lanes = p->fwd.lanes;
   if (rpl) *rpl = p->fwd.rpl;
   if (steps) *steps = p->fwd.ksteps;
-  if (cells_per_wg) *cells_per_wg = bcs::kWavesPerWg * (64 / p->fwd.lanes);
+  if (cells_per_wg) *cells_per_wg = p->fwd.wpw * (64 / p->fwd.lanes);
   return BCS_OK;
 }
 

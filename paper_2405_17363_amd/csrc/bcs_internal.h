@@ -74,7 +74,7 @@ struct JitKernel {
 // BCS_OK or an error code with the message in `err`.
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
                int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err, size_t errlen,
-               const std::vector<int>* mech_terms = nullptr);
+               const std::vector<int>* mech_terms = nullptr, int wg_waves = kWavesPerWg);
 
 // Prologue of every solve (bcs_order.hip), on `stream`: zero the work queue
 // (kQueueWords words) and, when `order` is not null, fill order[0, ncells)

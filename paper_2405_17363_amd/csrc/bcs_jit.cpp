@@ -138,7 +138,7 @@ namespace {
 // Compile (or load from the caches) `source`, whose kernel is `name`;
 // `ilp` adds the FP64 bodies' scheduling option.
 int load_source(const std::string& source, const char* name, bool ilp, size_t lds_bytes, JitKernel* out, char* err,
-                size_t errlen) {
+                size_t errlen, int threads = kWgThreads) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     snprintf(err, errlen, "no HIP device");
@@ -192,7 +192,7 @@ int load_source(const std::string& source, const char* name, bool ilp, size_t ld
   }
   JitKernel k = it->second;
   int nb = 0;
-  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.fn, kWgThreads, lds_bytes) != hipSuccess) {
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.fn, threads, lds_bytes) != hipSuccess) {
     snprintf(err, errlen, "occupancy query failed");
     return BCS_ERR_HIP;
   }
@@ -208,8 +208,9 @@ int load_source(const std::string& source, const char* name, bool ilp, size_t ld
 // BCS_DEBUG_VISITS set (not "0") in the environment, the per-cell output
 // counter of bcs_debug_count_visits, which costs registers and is left out
 // otherwise.
-void preamble(std::ostringstream& src) {
+void preamble(std::ostringstream& src, int wg_waves = kWavesPerWg) {
   src << "// device sources " << kJitSourceHash << "\n";
+  if (wg_waves != kWavesPerWg) src << "#define BCS_WG_WAVES " << wg_waves << "\n";
   const char* v = std::getenv("BCS_DEBUG_VISITS");
   if (v && std::string(v) != "0") src << "#define BCS_COUNT_VISITS 1\n";
 }
@@ -224,10 +225,11 @@ void sched_type(std::ostringstream& src, int lanes, int flags, const int* seg, i
 
 int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags, const int* seg, int rpl,
                int waves_per_eu,
-               size_t lds_bytes, JitKernel* out, char* err, size_t errlen, const std::vector<int>* mech_terms) {
+               size_t lds_bytes, JitKernel* out, char* err, size_t errlen, const std::vector<int>* mech_terms,
+               int wg_waves) {
   const bool mech = mech_terms != nullptr;
   std::ostringstream src;
-  preamble(src);
+  preamble(src, wg_waves);
   src << "#include \"bcs_fp64.h\"\n#include \"bcs_mixed.h\"\n"
       << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
   if (waves_per_eu > 0) src << ", " << waves_per_eu;
@@ -249,7 +251,7 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
     }
   }
   src << ">(P);\n}\n";
-  return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen);
+  return load_source(src.str(), name, fp64, lds_bytes, out, err, errlen, 64 * wg_waves);
 }
 
 int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,

@@ -27,9 +27,14 @@ constexpr int kNonfinite = 3;
 constexpr int kJGamma = 0;
 constexpr int kADirect = 1;
 
-// Waves per workgroup of every solve kernel.  Each wave works on its own
-// cells with its own LDS slice; the waves synchronise once, at kernel start.
-constexpr int kWavesPerWg = 4;
+// Waves per workgroup of the solve kernels (a forward kernel compiled per
+// pattern may be built with another count, BCS_WG_WAVES defined in its
+// source).  Each wave works on its own cells with its own LDS slice; the
+// waves synchronise once, at kernel start.
+#ifndef BCS_WG_WAVES
+#define BCS_WG_WAVES 4
+#endif
+constexpr int kWavesPerWg = BCS_WG_WAVES;
 constexpr int kWgThreads = 64 * kWavesPerWg;
 
 // Schedule entry: value position in the cell's CSR array, plus flags.
