@@ -1548,10 +1548,11 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
       for (size_t i : idx)
         std::fprintf(stderr, "[bcs] autotune (data) lanes=%d waves/workgroup=%d: %.1f us\n", cs[i].K.lanes,
                      cs[i].K.wpw, cs[i].t * 1e6);
-    // a workgroup size replaces the winner only by the same margin
+    // a workgroup size replaces the winner only if 3% faster (sizes measured
+    // within about 1% of each other, with that much noise between runs)
     size_t w2 = w;
     for (size_t i = first; i < cs.size(); ++i)
-      if (cs[i].t < cs[w].t * 0.99 && cs[i].t < cs[w2].t) w2 = i;
+      if (cs[i].t < cs[w].t * 0.97 && cs[i].t < cs[w2].t) w2 = i;
     w = w2;
   }
   drop_all(w);

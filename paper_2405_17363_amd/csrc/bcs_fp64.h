@@ -290,9 +290,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
                   kv[g] = lds_load<double>(ka);
                 } else {
                   const uint32_t r = (ka - kb) >> 3;
-                  const bool real = r < (uint32_t)P.mr;
-                  const double v = kc[real ? r : 0];
-                  kv[g] = real ? v : 0.0;
+                  kv[g] = kc[r < (uint32_t)P.mr ? r : 0];  // a padding term's k is zeroed below
                 }
                 yv[g] = lds_load<double>(xaddr + (w[g].x >> 16));
               }
@@ -303,7 +301,9 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
                 constexpr int g = decltype(gg)::value;
                 constexpr int q = MT::pos_of(u0 + g);
                 const double sf = __builtin_bit_cast(double, (uint64_t)w[g].y << 32);
-                const double d = __builtin_amdgcn_ldexp(kv[g] * yv[g], (int)(w[g].x & 1u));
+                double k = kv[g];
+                if constexpr (!SHARED) k = ((w[g].x & 0xfff8u) - kb) >> 3 < (uint32_t)P.mr ? k : 0.0;
+                const double d = __builtin_amdgcn_ldexp(k * yv[g], (int)(w[g].x & 1u));
                 if constexpr (q < KMAX)
                   a[q] = fmat(sf, d, a[q]);
                 else
