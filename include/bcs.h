@@ -128,7 +128,13 @@ typedef struct bcs_options {
                                    z <- D^-1 (y - U_s z) (L_s, U_s the strict parts,
                                    D = diag(U)), the truncated Neumann series of each
                                    factor.  Must be 0 for other preconditioners    */
-  int32_t reserved[1];          /* must be zero                                       */
+  int32_t waves_per_group;      /* waves per workgroup of the forward FP64 kernel
+                                   (Section 3.2's threads per block; a workgroup's
+                                   waves share only its copy of the schedule): 0 =
+                                   4, which bcs_plan_autotune may change to 2 or 8
+                                   when that is more than 3% faster; 1, 2, 4 or 8
+                                   fix it (jit = 1, FP64, not ILU0, no
+                                   shared_scalars, else BCS_ERR_UNSUPPORTED)       */
 } bcs_options;
 
 typedef struct bcs_plan bcs_plan; /* opaque; immutable after creation, except for the

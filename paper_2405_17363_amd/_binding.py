@@ -55,7 +55,7 @@ class _Options(ctypes.Structure):
         ("shared_scalars", ctypes.c_int32),
         ("refine_budget", ctypes.c_int32),
         ("ilu_sweeps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("waves_per_group", ctypes.c_int32),
     ]
 
 
@@ -218,7 +218,8 @@ class Plan:
                  matrix_kind: str = "j_gamma", lanes_per_cell: int = 0, residual_replacement: bool = True,
                  breakdown_restarts: int = 1, inner_rtol: float = 1e-4, max_refine: int = 10,
                  jit: bool = True, autotune: bool = True, cell_order: bool = True,
-                 shared_scalars: bool = False, refine_budget: str = "inner", ilu_sweeps: int = 0):
+                 shared_scalars: bool = False, refine_budget: str = "inner", ilu_sweeps: int = 0,
+                 waves_per_group: int = 0):
         L = lib()
         rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
         ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
@@ -241,6 +242,7 @@ class Plan:
         opt.shared_scalars = int(bool(shared_scalars))
         opt.refine_budget = _BUDGET[refine_budget]
         opt.ilu_sweeps = int(ilu_sweeps)
+        opt.waves_per_group = int(waves_per_group)
         self.options = opt
         self.precision, self.precond, self.matrix_kind = precision, precond, matrix_kind
         h = ctypes.c_void_p()

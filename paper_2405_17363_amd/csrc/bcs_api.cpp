@@ -769,12 +769,6 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     char err[512] = {0};
     if (waves_per_eu == 0)
       if (const char* e = std::getenv("BCS_WAVES_PER_EU")) waves_per_eu = std::max(0, std::atoi(e));
-    // tuning override for forward FP64 kernels: waves per workgroup (1, 2, 4 or 8)
-    if (wpw == bcs::kWavesPerWg && !adjoint && !mixed && !grouped && !mech)
-      if (const char* e = std::getenv("BCS_WG_WAVES")) {
-        const int w = std::atoi(e);
-        if (w == 1 || w == 2 || w == 4 || w == 8) wpw = w;
-      }
     // Builds tried in turn, the first that compiles without spilling is kept.
     // Forward FP64 kernels: three waves per SIMD with the rarely used slot
     // vectors in LDS (kSchedLean) and packed gather addresses, then the same
@@ -1295,7 +1289,12 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     return fail(BCS_ERR_ARG, "shared_scalars needs FP64, jit = 1 and lanes_per_cell 16, 32 or 64");
   if (o.refine_budget != BCS_BUDGET_INNER && o.refine_budget != BCS_BUDGET_CELL)
     return fail(BCS_ERR_ARG, "refine_budget must be BCS_BUDGET_INNER or BCS_BUDGET_CELL");
-  if (o.reserved[0] != 0) return fail(BCS_ERR_ARG, "reserved option fields must be zero");
+  if (o.waves_per_group != 0 && o.waves_per_group != 1 && o.waves_per_group != 2 && o.waves_per_group != 4 &&
+      o.waves_per_group != 8)
+    return fail(BCS_ERR_ARG, "waves_per_group must be 0, 1, 2, 4 or 8 (got %d)", o.waves_per_group);
+  if (o.waves_per_group != 0 && (o.jit != 1 || o.precision != BCS_FP64 || o.precond == BCS_PRECOND_ILU0 ||
+                                 o.shared_scalars == 1))
+    return fail(BCS_ERR_UNSUPPORTED, "waves_per_group needs jit = 1, FP64, no ILU0 and shared_scalars = 0");
 
   const bool need_diag = o.matrix_kind == BCS_J_GAMMA || o.precond == BCS_PRECOND_JACOBI || ilu ||
                          o.precision == BCS_FP32_REFINE;
@@ -1372,7 +1371,8 @@ int bcs_plan_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_
     Kernel K;
     g_err.clear();
     int r = ilu ? make_ilu_kernel(n, p->rp, p->ci, L, o.ilu_sweeps, &K)
-                : make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K, o.shared_scalars == 1);
+                : make_kernel(n, p->rp, p->ci, pos, L, 0, jit, 0, mixed, &K, o.shared_scalars == 1, nullptr, 0,
+                              o.waves_per_group ? o.waves_per_group : bcs::kWavesPerWg);
     if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
     if (r != BCS_OK) {
       rc = r;
@@ -1480,7 +1480,7 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
       g_err.clear();
       int r = ilu ? make_ilu_kernel(p->n, p->rp, p->ci, L, p->opt.ilu_sweeps, &K)
                   : make_kernel(p->n, p->rp, p->ci, pos, L, 0, jit, 0, p->opt.precision == BCS_FP32_REFINE, &K,
-                                false, nullptr, force);
+                                false, nullptr, force, p->fwd.wpw);
       if (r == BCS_ERR_UNSUPPORTED && g_err.empty()) continue;
       if (r != BCS_OK) {
         drop_all(0);
@@ -1523,7 +1523,8 @@ int bcs_plan_autotune(bcs_plan* p, int64_t ncells, const double* values, const d
   // waves per workgroup for the winner (the waves share only the schedule
   // copy, so the count sets how often that copy is made and how LDS and
   // registers round into whole workgroups per CU)
-  if (fp64_fwd && !cs[w].K.occ && cs[w].K.var == nullptr && cs[w].K.jit.scratch == 0) {
+  if (fp64_fwd && p->opt.waves_per_group == 0 && !cs[w].K.occ && cs[w].K.var == nullptr &&
+      cs[w].K.jit.scratch == 0) {
     const size_t first = cs.size();
     for (int wpw : {2, 8}) {
       if (wpw == cs[w].K.wpw) continue;

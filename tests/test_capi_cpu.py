@@ -63,7 +63,8 @@ def test_invalid_patterns_are_rejected(rp, ci, what):
 @pytest.mark.parametrize("field,value", [("precision", 7), ("precond", 5), ("matrix_kind", 3),
                                           ("lanes_per_cell", 8), ("residual_replacement", 2),
                                           ("breakdown_restarts", -1), ("jit", 2), ("autotune", 3), ("cell_order", 2),
-                                          ("shared_scalars", 2), ("refine_budget", 2)])
+                                          ("shared_scalars", 2), ("refine_budget", 2), ("waves_per_group", 3),
+                                          ("waves_per_group", 16)])
 def test_invalid_options_are_rejected(field, value):
     rc, msg, h = _create([0, 1, 2], [0, 1], **{field: value})
     assert rc == -1, msg
@@ -83,6 +84,13 @@ def test_missing_diagonal_allowed_without_jacobi_in_a_mode():
 def test_shared_scalars_needs_fixed_lanes_fp64_and_jit(extra):
     rc, msg, h = _create([0, 1, 2], [0, 1], shared_scalars=1, **extra)
     assert rc == -1 and "shared_scalars" in msg
+    assert not h.value
+
+
+@pytest.mark.parametrize("extra", [dict(jit=0), dict(precision=1), dict(precond=2)])
+def test_waves_per_group_needs_a_forward_fp64_kernel_compiled_per_pattern(extra):
+    rc, msg, h = _create([0, 1, 2], [0, 1], waves_per_group=2, **extra)
+    assert rc == -3 and "waves_per_group" in msg
     assert not h.value
 
 

@@ -551,15 +551,15 @@ def test_work_queue_hands_every_cell_out_exactly_once(form, monkeypatch):
 
 
 @pytest.mark.parametrize("waves", [1, 2, 8])
-def test_waves_per_workgroup_leave_results_bitwise_unchanged(waves, monkeypatch):
-    """A forward kernel built for another workgroup size (the autotuner tries
-    2 and 8 waves): every cell's arithmetic is its slot's, so the results
-    are bitwise those of the default four-wave workgroup."""
+def test_waves_per_workgroup_leave_results_bitwise_unchanged(waves):
+    """A forward kernel built for another workgroup size (the waves_per_group
+    option; the autotuner tries 2 and 8 waves): every cell's arithmetic is its
+    slot's, so the results are bitwise those of the default four-wave
+    workgroup."""
     mech, cells = config_inputs(3, ncells=20000)[0]
     V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
     ref = bcs.solve_batch(bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, autotune=False), V, G, B, RTOL, 200)
-    monkeypatch.setenv("BCS_WG_WAVES", str(waves))
-    plan = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, autotune=False)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, autotune=False, waves_per_group=waves)
     assert plan.info()["cells_per_wg"] == 2 * waves
     got = bcs.solve_batch(plan, V, G, B, RTOL, 200)
     torch.cuda.synchronize()
