@@ -380,64 +380,80 @@ void free_kernel(Kernel* K) {
 }
 
 // J term program of a kernel that assembles J while staging a cell (the
-// mechanism's J gather lists rearranged for the kernel's schedule).  Lane l
+// mechanism's J gather lists rearranged for the kernel's schedule).  Every
+// lane first evaluates CSR position 0 (terms[0] terms): the plain kernel
+// loads position 0's value for a padding step of the schedule, and the J
+// kernel keeps that value in the slot's operand block for them.  Then lane l
 // evaluates P = ksteps + rpl positions: the value position of each of its
-// schedule steps, then the diagonal position of each of its rows (of row 0
-// for a padding row, as the staging code reads them).  Position p has
-// terms[p] terms on every lane, the largest count among the lanes; entry
-// (p, t, l) is the word pair (start(p) + t) * lanes + l: the LDS byte address
-// of the term's rate constant (the rate constants sit at mtbase doubles,
-// followed by a zero that padding terms read) | factor 2 in bit 0 | the byte
-// offset of the y factor in the cell's operand block (the other reactant, or
-// element n + 1, which holds 1, for a first-order term and for padding) <<
-// 16, then the high word of S as a double (0 for padding).  False if the
-// rate constants lie beyond 16-bit LDS addresses.
+// schedule steps (a padding step: one term that takes the kept value), then
+// the diagonal position of each of its rows (nothing for a padding row,
+// whose diagonal the staging code discards).  Position p has terms[1 + p]
+// terms on every lane, the largest count among the lanes; entry (t, l) of
+// the program is the word pair t * lanes + l (terms numbered from position 0
+// on): the LDS byte address of the term's rate constant (the rate constants
+// sit at mtbase doubles, followed by a zero that padding terms read and a
+// one) | factor 2 in bit 0 | the byte offset of the y factor in the cell's
+// operand block (the other reactant; element n + 1, which holds 1, for a
+// first-order term and for padding; element n + 2 for the kept position-0
+// value) << 16, then the high word of S as a double (0 for padding).  False
+// if the constants lie beyond 16-bit LDS addresses.
 bool mech_program(const HostSchedule& S, int n, int lanes, int rpl, const std::vector<int>& rp,
                   const std::vector<int>& ci, const bcs_mechanism& m, int mtbase, std::vector<int>* terms,
                   std::vector<int32_t>* prog) {
-  if ((size_t)(mtbase + m.R + 1) * sizeof(double) > 65536) return false;
+  if ((size_t)(mtbase + m.R + 2) * sizeof(double) > 65536) return false;
   std::vector<int> diag(n, 0);
   for (int i = 0; i < n; ++i)
     for (int k = rp[i]; k < rp[i + 1]; ++k)
       if (ci[k] == i) diag[i] = k;
   const int np = S.ksteps + rpl;
-  std::vector<int> posq((size_t)np * lanes);  // position of (p, l)
+  constexpr int kPadStep = -1, kNone = -2;  // a padding step; no terms
+  std::vector<int> posq((size_t)np * lanes);  // position of (p, l), or kPadStep / kNone
   for (int l = 0; l < lanes; ++l) {
-    for (int st = 0; st < S.ksteps; ++st) posq[(size_t)st * lanes + l] = S.ent[(size_t)st * lanes + l] & bcs::kEntPosMask;
+    for (int st = 0; st < S.ksteps; ++st) {
+      const int32_t e = S.ent[(size_t)st * lanes + l];
+      posq[(size_t)st * lanes + l] = (e & bcs::kEntPad) ? kPadStep : (e & bcs::kEntPosMask);
+    }
     for (int j = 0; j < rpl; ++j) {
       const int rj = S.row[(size_t)j * lanes + l];
-      const int row = rj >= 0 ? rj : n;
-      posq[(size_t)(S.ksteps + j) * lanes + l] = diag[row < n ? row : 0] & bcs::kEntPosMask;
+      posq[(size_t)(S.ksteps + j) * lanes + l] = (rj >= 0 && rj < n) ? (diag[rj] & bcs::kEntPosMask) : kNone;
     }
   }
   const int32_t* jofs = m.htab.data() + m.jofs_at;
   const int32_t* jterm = m.htab.data() + m.jterm_at;
-  terms->assign(np, 0);
+  auto count = [&](int q) { return q == kPadStep ? 1 : q == kNone ? 0 : jofs[q + 1] - jofs[q]; };
+  terms->assign(1 + np, 0);
+  (*terms)[0] = jofs[1] - jofs[0];
   for (int p = 0; p < np; ++p)
-    for (int l = 0; l < lanes; ++l) {
-      const int q = posq[(size_t)p * lanes + l];
-      (*terms)[p] = std::max((*terms)[p], jofs[q + 1] - jofs[q]);
-    }
+    for (int l = 0; l < lanes; ++l) (*terms)[1 + p] = std::max((*terms)[1 + p], count(posq[(size_t)p * lanes + l]));
   prog->clear();
   const uint32_t one = (uint32_t)(n + 1) * 8u;
+  const uint32_t pad_word = (uint32_t)(mtbase + m.R) * 8u | one << 16;                  // k = 0, y factor 1
+  const uint32_t keep_word = (uint32_t)(mtbase + m.R + 1) * 8u | (uint32_t)(n + 2) * 8u << 16;  // 1 x kept value
+  auto push = [&](uint32_t w0, double sf) {
+    uint64_t sbits;
+    std::memcpy(&sbits, &sf, sizeof(sbits));
+    prog->push_back((int32_t)w0);
+    prog->push_back((int32_t)(uint32_t)(sbits >> 32));  // the low word of a small integer is 0
+  };
+  auto push_term = [&](int k) {
+    const uint32_t w1 = (uint32_t)jterm[2 * k + 1];
+    const uint32_t other = w1 & 0xffffu;
+    push((uint32_t)(mtbase + jterm[2 * k]) * 8u | (w1 >> 24 ? 1u : 0u) |
+             (other == (uint32_t)bcs::kNoSpecies ? one : other * 8u) << 16,
+         (double)((int)((w1 >> 16) & 0xffu) - 128));
+  };
+  for (int t = 0; t < (*terms)[0]; ++t)
+    for (int l = 0; l < lanes; ++l) push_term(jofs[0] + t);
   for (int p = 0; p < np; ++p)
-    for (int t = 0; t < (*terms)[p]; ++t)
+    for (int t = 0; t < (*terms)[1 + p]; ++t)
       for (int l = 0; l < lanes; ++l) {
         const int q = posq[(size_t)p * lanes + l];
-        const int k = jofs[q] + t;
-        uint32_t w0 = (uint32_t)(mtbase + m.R) * 8u | one << 16;  // k = 0, y factor 1
-        double sf = 0.0;
-        if (k < jofs[q + 1]) {
-          const uint32_t w1 = (uint32_t)jterm[2 * k + 1];
-          const uint32_t other = w1 & 0xffffu;
-          w0 = (uint32_t)(mtbase + jterm[2 * k]) * 8u | (w1 >> 24 ? 1u : 0u) |
-               (other == (uint32_t)bcs::kNoSpecies ? one : other * 8u) << 16;
-          sf = (double)((int)((w1 >> 16) & 0xffu) - 128);
-        }
-        uint64_t sbits;
-        std::memcpy(&sbits, &sf, sizeof(sbits));
-        prog->push_back((int32_t)w0);
-        prog->push_back((int32_t)(uint32_t)(sbits >> 32));  // the low word of a small integer is 0
+        if (q == kPadStep && t == 0)
+          push(keep_word, 1.0);
+        else if (q >= 0 && jofs[q] + t < jofs[q + 1])
+          push_term(jofs[q] + t);
+        else
+          push(pad_word, 0.0);
       }
   return true;
 }
@@ -813,7 +829,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
         K.mtbase = (int)(K.layout.tbase + table_doubles(n, lanes, S.ksteps));
         const bool fits = mech_program(S, n, lanes, rpl, rp, ci, *mech, K.mtbase, &K.mterms, &mprog);
         K.mwords = (int)mprog.size();
-        K.lds = ((size_t)K.mtbase + mech->R + 1 + mprog.size() / 2) * sizeof(double);
+        K.lds = ((size_t)K.mtbase + mech->R + 2 + mprog.size() / 2) * sizeof(double);
         if (!fits || K.lds > device_max_lds()) {
           if (last) return BCS_ERR_UNSUPPORTED;
           continue;

@@ -452,15 +452,18 @@ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v);
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 
 // Shape of the J term program of a kernel that assembles J while staging a
-// cell: the lane's KMAX schedule positions, then its RPL rows' diagonal
-// positions, and for each of these P positions the number of terms T[p]
-// every lane evaluates (the largest term count among the lanes; shorter
-// lists are padded with terms that add nothing).  The program itself, two
-// words per (position, term, lane), is data (KParams::mtab); its shape is
+// cell: first the J0 terms of CSR position 0, which every lane evaluates (a
+// padding step of the schedule takes that value, as the plain kernel loads
+// position 0 for it), then the lane's KMAX schedule positions and its RPL
+// rows' diagonal positions, and for each of these P positions the number of
+// terms T[p] every lane evaluates (the largest count among the lanes;
+// shorter lists are padded with terms that add nothing).  The program
+// itself, two words per (term, lane), is data (KParams::mtab); its shape is
 // compiled in so that every term's LDS address is a constant offset.
-template <int... T>
+template <int J0, int... T>
 struct MechTerms {
   static constexpr bool kOn = true;
+  static constexpr int kJ0 = J0;
   static constexpr int kP = sizeof...(T);
   static constexpr int count(int p) {
     constexpr int t[] = {T...};
@@ -483,6 +486,7 @@ struct MechTerms {
 };
 struct NoMechTerms {
   static constexpr bool kOn = false;
+  static constexpr int kJ0 = 0;
   static constexpr int kP = 0;
 };
 

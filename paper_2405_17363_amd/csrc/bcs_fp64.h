@@ -250,19 +250,59 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
               if (gl + j * LANES < n) xb[gl + j * LANES] = yl[j];
           }
           wave_sync();
-          const uint2* prog = (const uint2*)(lds + P.mtbase + P.mr + 1) + gl;
+          const uint2* prog = (const uint2*)(lds + P.mtbase + P.mr + 2) + gl;
           const uint32_t xaddr = lds_addr(xb);
-          // Rate constants from LDS (shared; a padding term reads the zero
-          // after them) or from the cell's row in memory: two copies of the
-          // program, each with its address space.  A term takes no branch:
-          // the y factor of a first-order term is the 1 at xb[n + 1], the
-          // factor 2 an exact ldexp by 1 or 0.  k y rounds once and S d is
-          // exact in the FMA, as in the assembly kernel, so the sums are
-          // bitwise its sums.
+          // Rate constants from LDS (shared; after them a zero, which padding
+          // terms read, and a one) or from the cell's row in memory: two
+          // copies of the program, each with its address space.  A term takes
+          // no branch: the y factor of a first-order term is the 1 at
+          // xb[n + 1], the factor 2 an exact ldexp by 1 or 0.  k y rounds once
+          // and S d is exact in the FMA, as in the assembly kernel, so the
+          // sums are bitwise its sums.  First every lane evaluates position 0
+          // and the slot's first lane keeps it at xb[n + 2]; a padding step's
+          // single term then reads it there (1 x J0, S = 1: exactly J0).
           auto jprog = [&](auto mode) {
             constexpr bool SHARED = decltype(mode)::value == 0;
             const double* kc = P.kr + cell * P.k_stride;
             const uint32_t kb = (uint32_t)P.mtbase * 8u;
+            auto term = [&](uint2 w, double kv, double yv, double acc) {
+              const double sf = __builtin_bit_cast(double, (uint64_t)w.y << 32);
+              double k = kv;
+              if constexpr (!SHARED) {
+                const uint32_t r = ((w.x & 0xfff8u) - kb) >> 3;
+                k = r < (uint32_t)P.mr ? k : (r == (uint32_t)P.mr + 1 ? 1.0 : 0.0);
+              }
+              return fmat(sf, __builtin_amdgcn_ldexp(k * yv, (int)(w.x & 1u)), acc);
+            };
+            auto kload = [&](uint2 w) -> double {
+              const uint32_t ka = w.x & 0xfff8u;
+              if constexpr (SHARED) {
+                return lds_load<double>(ka);
+              } else {
+                const uint32_t r = (ka - kb) >> 3;
+                return kc[r < (uint32_t)P.mr ? r : 0];  // the constants after them are taken in term()
+              }
+            };
+            {
+              constexpr int J0 = MT::kJ0;
+              double j0 = 0.0;
+              if constexpr (J0 > 0) {
+                uint2 w[J0];
+                double kv[J0], yv[J0];
+#pragma unroll
+                for (int t = 0; t < J0; ++t) w[t] = prog[t * LANES];
+#pragma unroll
+                for (int t = 0; t < J0; ++t) {
+                  kv[t] = kload(w[t]);
+                  yv[t] = lds_load<double>(xaddr + (w[t].x >> 16));
+                }
+#pragma unroll
+                for (int t = 0; t < J0; ++t) j0 = term(w[t], kv[t], yv[t], j0);
+              }
+              if (gl == 0) xb[n + 2] = j0;
+              wave_sync();
+            }
+            const uint2* mprog = prog + MT::kJ0 * LANES;
 #pragma unroll
             for (int q = 0; q < KMAX; ++q) a[q] = 0.0;
 #pragma unroll
@@ -274,7 +314,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
             uint2 wn[kJTermChunk];
 #pragma unroll
             for (int g = 0; g < kJTermChunk; ++g)
-              if (g < U) wn[g] = prog[g * LANES];
+              if (g < U) wn[g] = mprog[g * LANES];
             for_pos<0, (U + kJTermChunk - 1) / kJTermChunk>([&](auto chunk) {
               constexpr int u0 = decltype(chunk)::value * kJTermChunk;
               constexpr int G = U - u0 < kJTermChunk ? U - u0 : kJTermChunk;
@@ -285,29 +325,19 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
               for (int g = 0; g < G; ++g) w[g] = wn[g];
 #pragma unroll
               for (int g = 0; g < G; ++g) {
-                const uint32_t ka = w[g].x & 0xfff8u;
-                if constexpr (SHARED) {
-                  kv[g] = lds_load<double>(ka);
-                } else {
-                  const uint32_t r = (ka - kb) >> 3;
-                  kv[g] = kc[r < (uint32_t)P.mr ? r : 0];  // a padding term's k is zeroed below
-                }
+                kv[g] = kload(w[g]);
                 yv[g] = lds_load<double>(xaddr + (w[g].x >> 16));
               }
 #pragma unroll
               for (int g = 0; g < kJTermChunk; ++g)
-                if (u1 + g < U) wn[g] = prog[(u1 + g) * LANES];
+                if (u1 + g < U) wn[g] = mprog[(u1 + g) * LANES];
               for_pos<0, G>([&](auto gg) {
                 constexpr int g = decltype(gg)::value;
                 constexpr int q = MT::pos_of(u0 + g);
-                const double sf = __builtin_bit_cast(double, (uint64_t)w[g].y << 32);
-                double k = kv[g];
-                if constexpr (!SHARED) k = ((w[g].x & 0xfff8u) - kb) >> 3 < (uint32_t)P.mr ? k : 0.0;
-                const double d = __builtin_amdgcn_ldexp(k * yv[g], (int)(w[g].x & 1u));
                 if constexpr (q < KMAX)
-                  a[q] = fmat(sf, d, a[q]);
+                  a[q] = term(w[g], kv[g], yv[g], a[q]);
                 else
-                  dv[q - KMAX] = fmat(sf, d, dv[q - KMAX]);
+                  dv[q - KMAX] = term(w[g], kv[g], yv[g], dv[q - KMAX]);
               });
             });
           };
@@ -545,10 +575,13 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
   for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
   if constexpr (MECH) {
-    // the shared rate constants, a zero, and the kernel's J term program
+    // the shared rate constants, a zero, a one, and the kernel's J term program
     for (int i = threadIdx.x; i < P.mk; i += kWgThreads) lds[P.mtbase + i] = P.kr[i];
-    if (threadIdx.x == 0) lds[P.mtbase + P.mr] = 0.0;
-    int32_t* mt = (int32_t*)(lds + P.mtbase + P.mr + 1);
+    if (threadIdx.x == 0) {
+      lds[P.mtbase + P.mr] = 0.0;
+      lds[P.mtbase + P.mr + 1] = 1.0;
+    }
+    int32_t* mt = (int32_t*)(lds + P.mtbase + P.mr + 2);
     for (int i = threadIdx.x; i < P.mtab_words; i += kWgThreads) mt[i] = P.mtab[i];
   }
   __syncthreads();

@@ -165,11 +165,12 @@ struct KParams {
   // assembled per cell from the concentrations y [ncells, n] and rate
   // constants (k[c * k_stride + r]) while the cell is staged, by the kernel's
   // J term program.  LDS from mtbase (doubles): the mr rate constants (copied
-  // when shared: mk = mr, else mk = 0), a zero, then the program, two words
-  // per (position, term, lane): the LDS byte address of the term's rate
-  // constant (of the zero for a padding term; a multiple of 8) | factor 2 (bit
-  // 0) | the byte offset of its y factor in the operand block << 16; then the
-  // high word of S as a double (S is a small integer: the low word is 0).
+  // when shared: mk = mr, else mk = 0), a zero, a one, then the program, two
+  // words per (term, lane): the LDS byte address of the term's rate constant
+  // (of the zero for a padding term, of the one for a padding step's term; a
+  // multiple of 8) | factor 2 (bit 0) | the byte offset of its y factor in the
+  // operand block << 16; then the high word of S as a double (S is a small
+  // integer: the low word is 0).
   const double* y;
   const double* kr;
   int64_t k_stride;
