@@ -422,11 +422,13 @@ int bcs_assemble(const bcs_mechanism* mech, int64_t ncells, const double* y, con
  * paper's next step, the rest of the BDF step inside the Block-cells kernel,
  * Section 6).  The mechanism must outlive the plan.  Options as in
  * bcs_plan_create, limited to FP64, no or Jacobi preconditioning, J_GAMMA,
- * jit = 1, shared_scalars = 0 (else BCS_ERR_UNSUPPORTED; also when no lane
- * count's kernel fits the rate constants and the J term program, 8 bytes per
- * lane for every term of every schedule position, in the LDS).  The plan also serves bcs_solve_batch, the adjoint
- * and the tuners like any other; bcs_plan_autotune keeps its mechanism kernel
- * at the chosen lanes. */
+ * jit = 1, shared_scalars = 0 (else BCS_ERR_UNSUPPORTED; also when, at the
+ * plan's lanes per cell, the solve's layout, the rate constants (within the
+ * first 64 KiB) and the J term program, 8 bytes per lane for every term of
+ * every schedule position, do not fit the device's LDS per workgroup, 160 KiB
+ * on gfx950).  The plan also serves bcs_solve_batch, the adjoint and the
+ * tuners like any other; bcs_plan_autotune keeps its mechanism kernel at the
+ * chosen lanes. */
 int bcs_plan_create_mech(const bcs_mechanism* mech, const bcs_options* opt, bcs_plan** out);
 
 /* Solve (I - gamma_c J(y_c)) x_c = b_c for every cell, J assembled from the

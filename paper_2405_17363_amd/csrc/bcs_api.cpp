@@ -289,6 +289,17 @@ size_t device_max_lds() {
   return std::min<size_t>((size_t)v, 65536);
 }
 
+// The device's whole LDS per workgroup (160 KiB on gfx950), for kernels
+// whose region beyond the first 64 KiB is read through 32-bit addresses
+// only: the J term program of the kernels that assemble J.
+size_t device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                                               hipSuccess || v <= 0)
+    return 65536;
+  return (size_t)v;
+}
+
 bool layout_fits(const WgLayout& L) { return L.operand_bytes <= 65536 && L.bytes <= device_max_lds(); }
 
 // Whether a specialised kernel of ksteps steps and rpl rows per lane is worth
@@ -830,7 +841,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
         const bool fits = mech_program(S, n, lanes, rpl, rp, ci, *mech, K.mtbase, &K.mterms, &mprog);
         K.mwords = (int)mprog.size();
         K.lds = ((size_t)K.mtbase + mech->R + 2 + mprog.size() / 2) * sizeof(double);
-        if (!fits || K.lds > device_max_lds()) {
+        if (!fits || K.lds > device_lds_limit()) {
           if (last) return BCS_ERR_UNSUPPORTED;
           continue;
         }
