@@ -376,6 +376,10 @@ struct StaticSched {
     constexpr int W = (FLAGS & kSchedWin8) ? 8 : kGatherChunk;
     T acc0 = DIAG ? dg[0] * in[0] : T(0), acc1 = 0;
     T g[W];
+    // The SIMD's other wave is usually in its reductions or updates: while
+    // this wave gathers, it issues first (measured 0.8% faster on the n = 80
+    // workload; raising the reductions' priority as well lost that again).
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int s = 0; s < W; ++s)
       if (s < KMAX) g[s] = lds_load<T>(step_addr<PACK>(ad, s));
@@ -396,6 +400,7 @@ struct StaticSched {
         acc1 = 0;
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if constexpr (SPAN) {
       out[0] = fmat(sm, out[1], out[0]);
       out[1] = (T(1) - sm) * out[1];
