@@ -67,11 +67,15 @@ def check_mixed(mech, cells, out, budget, lu_sample, x0=None):
     return out, ref
 
 
+@pytest.mark.parametrize("lanes", [0, 32])
 @pytest.mark.parametrize("budget", ["inner", "cell"])
 @pytest.mark.parametrize("cfg,nc", [(1, None), (2, 4000)])
-def test_mixed_matches_emulation_and_lu(cfg, nc, budget):
+def test_mixed_matches_emulation_and_lu(cfg, nc, budget, lanes):
+    """lanes 0: the tuner's choice (one cell per wave, the kernel's nested
+    loops); 32: two cells per wave (each slot in its own phase)."""
     mech, cells = config_inputs(cfg, ncells=nc)[0]
-    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precision="fp32_refine", refine_budget=budget)
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, precision="fp32_refine", refine_budget=budget,
+                    lanes_per_cell=lanes)
     out = run_mixed(plan, cells)
     C = len(out[3])
     check_mixed(mech, cells, out, budget, np.arange(0, C, max(1, C // 300)))
