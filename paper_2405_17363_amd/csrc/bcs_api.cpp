@@ -249,6 +249,7 @@ HostSchedule build_schedule_jit(int n, const std::vector<int>& rp, const std::ve
 // 32-bit words.
 struct WgLayout {
   int xs = 0, wxs = 0, bbase = 0, bs = 0, wbs = 0, yoff = 0, tbase = 0;
+  int coobase = 0;  // adjoint kernels: each position's (row, column), after the tables
   size_t operand_bytes = 0, bytes = 0;
 };
 
@@ -265,9 +266,8 @@ void slot_sizes(int n, int lanes, int rpl, bool lean, int* xs, int* bs) {
 size_t table_doubles(int n, int lanes, int ksteps) { return ((size_t)ksteps * lanes + (size_t)n + 1) / 2; }
 
 WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint, bool lean = false,
-                   int wpw = bcs::kWavesPerWg) {
+                   int wpw = bcs::kWavesPerWg, int nnz = 0) {
   WgLayout L;
-  (void)adjoint;
   slot_sizes(n, lanes, rpl, lean, &L.xs, &L.bs);
   L.yoff = lean ? bcs::kSlotVecs * rpl * lanes : 0;
   L.wxs = (64 / lanes) * L.xs;
@@ -276,6 +276,11 @@ WgLayout wg_layout(int n, int lanes, int rpl, int ksteps, int adjoint, bool lean
   L.tbase = L.bbase + wpw * L.wbs;
   L.operand_bytes = (size_t)L.bbase * sizeof(double);
   L.bytes = ((size_t)L.tbase + table_doubles(n, lanes, ksteps)) * sizeof(double);
+  if (adjoint) {
+    // the gradient epilogue's table: row | column << 16 of every position
+    L.coobase = (int)(L.tbase + table_doubles(n, lanes, ksteps));
+    L.bytes += (((size_t)nnz + 1) / 2) * sizeof(double);
+  }
   return L;
 }
 
@@ -502,7 +507,8 @@ bool adjoint_fits(int n, const std::vector<int>& trp, const std::vector<int>& tc
                   int lanes) {
   const int rpl = (n + lanes - 1) / lanes;
   const HostSchedule T = build_schedule_jit(n, trp, tci, tpos, lanes, rpl, sched_allowed(false));
-  return T.ksteps > 0 && jit_feasible(T.ksteps, rpl) && layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1));
+  return T.ksteps > 0 && jit_feasible(T.ksteps, rpl) &&
+         layout_fits(wg_layout(n, lanes, rpl, T.ksteps, 1, false, bcs::kWavesPerWg, (int)tci.size()));
 }
 
 // ---- ILU(0) preconditioning (kernel body in bcs_ilu.h) ----
@@ -825,7 +831,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       const Attempt& A = tries[at];
       const bool last = at + 1 == tries.size();
       const bool lean = (A.extra & bcs::kSchedLean) != 0;
-      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, lean, wpw);
+      K.layout = wg_layout(n, lanes, rpl, S.ksteps, adjoint, lean, wpw, rp[n]);
       if (!layout_fits(K.layout)) {
         if (last) return BCS_ERR_UNSUPPORTED;
         if (verbose())
@@ -878,7 +884,9 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
       const bcs::Variant& v = vs[q];
       if (v.lanes != lanes || v.rpl < rpl) continue;
       HostSchedule T = build_schedule(n, rp, ci, pos, lanes, v.rpl, v.kmax);
-      if (T.ksteps > v.kmax || !layout_fits(wg_layout(n, lanes, v.rpl, v.kmax, adjoint))) continue;
+      if (T.ksteps > v.kmax ||
+          !layout_fits(wg_layout(n, lanes, v.rpl, v.kmax, adjoint, false, bcs::kWavesPerWg, rp[n])))
+        continue;
       if (!best || v.rpl < best->rpl || (v.rpl == best->rpl && v.kmax < best->kmax)) {
         best = &v;
         S = std::move(T);
@@ -888,7 +896,7 @@ int make_kernel(int n, const std::vector<int>& rp, const std::vector<int>& ci, c
     K.var = best;
     K.rpl = best->rpl;
     K.ksteps = best->kmax;
-    K.layout = wg_layout(n, lanes, best->rpl, best->kmax, adjoint);
+    K.layout = wg_layout(n, lanes, best->rpl, best->kmax, adjoint, false, bcs::kWavesPerWg, rp[n]);
     K.lds = K.layout.bytes;
     int nb = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, best->fp64_kernel, bcs::kWgThreads, K.lds));
@@ -1113,6 +1121,7 @@ int launch(const bcs_plan* p, const Kernel& K, bcs::KParams P, hipStream_t strea
   P.wbs = L.wbs;
   P.yoff = L.yoff;
   P.tbase = L.tbase;
+  P.coobase = L.coobase;
   P.mtbase = K.mtbase;
   if (K.ilu) {
     P.schedL = K.dL;

@@ -161,13 +161,30 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         xb[rows[j]] = xv[j];
       }
       wave_sync();
+      // and the forward solution x through the slot's SpMV result block (free
+      // once the last SpMV is done; RPL x LANES >= n words)
+      {
+        const double* xc = P.xin + cell * n;
+        double xl[RPL];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) xl[j] = gl + j * LANES < n ? xc[gl + j * LANES] : 0.0;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j)
+          if (gl + j * LANES < n) yb[gl + j * LANES] = xl[j];
+      }
+      wave_sync();
       // entry k = (i, j): lambda_i x_j; dL/dA_k = -lambda_i x_j, and in J mode
-      // dL/dJ_k = gamma lambda_i x_j and dL/dgamma = sum_k J_k lambda_i x_j
+      // dL/dJ_k = gamma lambda_i x_j and dL/dgamma = sum_k J_k lambda_i x_j.
+      // Consecutive lanes write consecutive positions; (i, j) of each position
+      // come from the workgroup's LDS copy.
       const bool to_j = P.grad_kind == 1 && P.kind == kJGamma;
       const double* vals = P.values + cell * nnz;
+      const uint32_t* coo = (const uint32_t*)(lds + P.coobase);
       double gpart = 0;
+#pragma unroll 4
       for (int k = gl; k < nnz; k += LANES) {
-        const double lx = xb[P.coo_row[k]] * P.xin[cell * n + P.coo_col[k]];
+        const uint32_t w = coo[k];
+        const double lx = xb[w & 0xffffu] * yb[w >> 16];
         P.grad_vals[cell * nnz + k] = to_j ? gam * lx : -lx;
         if (P.grad_gamma) gpart = __builtin_fma(vals[k], lx, gpart);
       }
@@ -574,6 +591,12 @@ __device__ __forceinline__ void fp64_body(const KParams& P) {
   int32_t* diag_lds = ent_lds + S::KMAX * S::LANES;
   for (int i = threadIdx.x; i < S::KMAX * S::LANES; i += kWgThreads) ent_lds[i] = P.sched.ent[i];
   for (int i = threadIdx.x; i < P.n; i += kWgThreads) diag_lds[i] = P.diag_pos[i] & kEntPosMask;
+  if (ADJ == 1 || (ADJ < 0 && P.adjoint)) {
+    // the adjoint epilogue's (row, column) of every position
+    uint32_t* coo = (uint32_t*)(lds + P.coobase);
+    for (int i = threadIdx.x; i < P.nnz; i += kWgThreads)
+      coo[i] = (uint32_t)(uint16_t)P.coo_row[i] | (uint32_t)(uint16_t)P.coo_col[i] << 16;
+  }
   if constexpr (MECH) {
     // the shared rate constants, a zero, a one, and the kernel's J term program
     for (int i = threadIdx.x; i < P.mk; i += kWgThreads) lds[P.mtbase + i] = P.kr[i];

@@ -151,6 +151,7 @@ struct KParams {
   int32_t bbase, bs, wbs;   // state blocks: start, stride, stride per wave
   int32_t yoff;             // offset of the SpMV result block (RPL x LANES) within the state block
   int32_t tbase;            // start of the schedule tables
+  int32_t coobase;          // adjoint: start of the (row | column << 16) word of every position
   // ILU(0) preconditioning (kernels compiled per pattern only).  The strict
   // lower and strict upper parts of the factors each have their own
   // schedule (rows dealt by their own lengths); the factorization program
