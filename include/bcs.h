@@ -99,7 +99,11 @@ typedef struct bcs_options {
                                    kernels on the solve's stream), handed out
                                    alternately from the large-gamma and the
                                    small-gamma end, so that expensive cells start
-                                   early.  Results are identical to index order.
+                                   early.  Applied only when the batch has more
+                                   cells than the launch has cell slots (with
+                                   fewer, every cell starts at once in its own
+                                   slot, in index order, and no sort runs).
+                                   Results are identical to index order.
                                    0: index order                                  */
   int32_t shared_scalars;       /* 1: Block-cells (N) of Section 3, an experiment
                                    mode: each run of 64 / lanes_per_cell consecutive

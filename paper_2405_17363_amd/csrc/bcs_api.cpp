@@ -1060,14 +1060,20 @@ size_t ws_bytes(int64_t ncells) {
 
 // Prologue of a solve on `stream`: point the kernel at its work queue in the
 // workspace and clear it, and, with cell_order on, cells solved on their own
-// (not shared_scalars), per-cell gamma and at least two cells, sort the cells
-// by gamma into the workspace's order array and point the solve at it.
-int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream) {
+// (not shared_scalars), per-cell gamma and more cells than the launch has
+// slots (`slots`; 0 = not known), sort the cells by gamma into the
+// workspace's order array and point the solve at it.  When every cell has a
+// slot of its own from the start, the order cannot even out anything: the
+// cells are then claimed one at a time in index order, each by its own
+// slot, instead of in pairs by half of the slots, and the two sort launches
+// are skipped.
+int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream, int64_t slots) {
   char* w = (char*)ws;
   P->queue = (unsigned long long*)w;
   P->order = nullptr;
   const bool use_order = p->opt.cell_order == 1 && p->opt.shared_scalars == 0 && p->opt.matrix_kind == BCS_J_GAMMA &&
-                         P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX;
+                         P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX &&
+                         (slots <= 0 || P->ncells > slots);
   int32_t* order = use_order ? (int32_t*)(w + bcs::kWsOrderOffset) : nullptr;
   const hipError_t e = bcs::launch_solve_prologue(P->queue, P->gamma, P->gamma_stride, P->ncells,
                                                   (uint32_t*)(w + bcs::kWsStateOffset), order, stream);
@@ -1106,6 +1112,11 @@ int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
   const int64_t need = (ncells + cells_per_wg - 1) / cells_per_wg;
   const int64_t cap = (int64_t)K.max_blocks * p->num_cu;
   return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+// Cell slots of a launch of kernel K over ncells cells.
+int64_t slots_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
+  return (int64_t)grid_for(p, K, ncells) * K.wpw * (64 / K.lanes);
 }
 
 // Fill the launch-specific fields and launch kernel K (forward or adjoint);
@@ -1152,7 +1163,7 @@ int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P0, vo
   for (int rep = 0; rep <= reps && rc == BCS_OK; ++rep) {
     (void)hipEventRecord(e0, nullptr);
     bcs::KParams P = P0;
-    rc = prologue(p, &P, ws, nullptr);
+    rc = prologue(p, &P, ws, nullptr, slots_for(p, K, P.ncells));
     if (rc == BCS_OK) rc = launch(p, K, P, nullptr);
     (void)hipEventRecord(e1, nullptr);
     if (rc != BCS_OK) break;
@@ -1732,7 +1743,7 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   P.resid = resid;
   P.status = status;
   P.refinements = refinements;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream);
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd, ncells));
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd, P, (hipStream_t)stream);
 }
@@ -1789,7 +1800,7 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream);
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->adj, ncells));
   if (rc != BCS_OK) return rc;
   return launch(p, p->adj, P, (hipStream_t)stream);
 }
@@ -1913,7 +1924,7 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.yoff = lay[q].yoff;
     P.tbase = M.ent_off[q];
     P.x0 = nullptr;
-    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream);  // each mechanism in its cost order
+    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream, 0);  // each mechanism in its cost order
     if (rc != BCS_OK) return rc;
     M.m[q] = P;
     const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
@@ -2100,7 +2111,7 @@ int bcs_solve_batch_mech(const bcs_plan* p, int64_t ncells, const double* y, con
   P.mtab_words = p->fwd_mech.mwords;
   P.mk = k_stride == 0 ? p->mech->R : 0;
   P.mr = p->mech->R;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream);
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd_mech, ncells));
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd_mech, P, (hipStream_t)stream);
 }

@@ -418,12 +418,15 @@ def test_cost_order_gives_index_order_results():
     """Handing cells out sorted by gamma changes only where and when a cell is
     solved: every output is bitwise the index-order output, every cell is
     written (outputs start as NaN), also for a second, smaller batch that
-    reuses the plan's order array, and for the adjoint."""
+    reuses the plan's order array (9,001 cells: more than the 8,192 cell
+    slots even four resident 32-lane workgroups per CU give), for a batch of
+    100 cells (fewer cells than slots: no sort, one cell per slot), and for
+    the adjoint."""
     mech, cells = config_inputs(2)[0]
     V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
     p0 = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, cell_order=False)
     p1 = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=32, cell_order=True)
-    for C in (V.shape[0], 3001):
+    for C in (V.shape[0], 9001, 100):
         ref = bcs.solve_batch(p0, V[:C], G[:C], B[:C], RTOL, 200)
         out = [torch.full((C, mech.n), float("nan"), dtype=torch.float64, device="cuda"),
                torch.full((C,), -1, dtype=torch.int32, device="cuda"),
@@ -509,16 +512,20 @@ def test_warm_start_matches_the_oracle_and_saves_iterations():
     assert np.array_equal(xin.cpu().numpy(), x)
 
 
-@pytest.mark.parametrize("form", ["fp64", "adjoint", "mixed", "ilu0"])
+@pytest.mark.parametrize("form", ["fp64", "fp64_small", "adjoint", "mixed", "ilu0"])
 def test_work_queue_hands_every_cell_out_exactly_once(form, monkeypatch):
     """Debug counter (bcs_debug_count_visits, compiled in with
     BCS_DEBUG_VISITS): on the 100k-cell workload, in the cost order, every
     cell's outputs are written exactly once, and the outputs (pre-filled
-    with sentinels) are all written."""
+    with sentinels) are all written.  fp64_small: 1,000 of the cells, fewer
+    than the launch's slots, claimed one at a time without the order."""
     monkeypatch.setenv("BCS_DEBUG_VISITS", "1")
     mech, cells = config_inputs(3)[0]
+    if form == "fp64_small":
+        cells = {k: v[:1000] for k, v in cells.items()}
     C = cells["b"].shape[0]
-    kw = {"fp64": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"}, "ilu0": {"precond": "ilu0"}}[form]
+    kw = {"fp64": {}, "fp64_small": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"},
+          "ilu0": {"precond": "ilu0"}}[form]
     plan = bcs.Plan(mech.row_ptr, mech.col_idx, **kw)
     V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
     counts = torch.zeros(C, dtype=torch.int32, device="cuda")
