@@ -101,8 +101,9 @@ typedef struct bcs_options {
                                    small-gamma end, so that expensive cells start
                                    early.  Applied only when the batch has more
                                    cells than the launch has cell slots (with
-                                   fewer, every cell starts at once in its own
-                                   slot, in index order, and no sort runs).
+                                   no more, slot k solves cell k: every cell
+                                   starts at once, and nothing runs before the
+                                   solve kernel).
                                    Results are identical to index order.
                                    0: index order                                  */
   int32_t shared_scalars;       /* 1: Block-cells (N) of Section 3, an experiment

@@ -1063,17 +1063,20 @@ size_t ws_bytes(int64_t ncells) {
 // (not shared_scalars), per-cell gamma and more cells than the launch has
 // slots (`slots`; 0 = not known), sort the cells by gamma into the
 // workspace's order array and point the solve at it.  When every cell has a
-// slot of its own from the start, the order cannot even out anything: the
-// cells are then claimed one at a time in index order, each by its own
-// slot, instead of in pairs by half of the slots, and the two sort launches
-// are skipped.
+// slot of its own from the start, the order cannot even out anything: slot
+// k then solves cell k and nothing else (no queue, no claims: P->queue is
+// null and nothing is launched here), instead of half of the slots taking
+// the cells in pairs.  Block-cells (N) runs keep the queue.
 int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream, int64_t slots) {
   char* w = (char*)ws;
-  P->queue = (unsigned long long*)w;
   P->order = nullptr;
+  if (slots > 0 && P->ncells <= slots && p->opt.shared_scalars == 0) {
+    P->queue = nullptr;
+    return BCS_OK;
+  }
+  P->queue = (unsigned long long*)w;
   const bool use_order = p->opt.cell_order == 1 && p->opt.shared_scalars == 0 && p->opt.matrix_kind == BCS_J_GAMMA &&
-                         P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX &&
-                         (slots <= 0 || P->ncells > slots);
+                         P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX;
   int32_t* order = use_order ? (int32_t*)(w + bcs::kWsOrderOffset) : nullptr;
   const hipError_t e = bcs::launch_solve_prologue(P->queue, P->gamma, P->gamma_stride, P->ncells,
                                                   (uint32_t*)(w + bcs::kWsStateOffset), order, stream);

@@ -206,6 +206,17 @@ constexpr int kJTermChunk = 8;
 // Cells a slot takes per claim when the cells come in a cost order.
 constexpr int kClaimGroup = 2;
 
+// The one cell of slot `grp` of wave `wv` when the launch has a slot for
+// every cell and no work queue (queue null): slots are numbered workgroup by
+// workgroup, wave by wave, slot by slot, and slot k takes cell k.  -1 when
+// there is a queue, or no cell for this slot.
+__device__ __forceinline__ int32_t static_cell(const unsigned long long* queue, int64_t ncells, int wv, int grp,
+                                               int slots_per_wave) {
+  if (queue) return -1;
+  const int64_t c = ((int64_t)blockIdx.x * kWavesPerWg + wv) * slots_per_wave + grp;
+  return c < ncells ? (int32_t)c : -1;
+}
+
 // Claim the next cell for a slot (LANES lanes starting at lane `leader`):
 // one atomic on the queue's claim counter by the slot's first lane,
 // broadcast to the slot.  Returns false once every cell has been handed out.
@@ -214,7 +225,9 @@ constexpr int kClaimGroup = 2;
 // cells (queue position k is the cell of rank k/2 from the expensive end for
 // even k, from the cheap end for odd k) are read from the order in one
 // memory round trip; the first is solved now, the others are kept in
-// held[] (-1 when none) and solved next without another claim.
+// held[] (-1 when none) and solved next without another claim.  Without a
+// queue (null: the launch has a slot for every cell) a slot solves only the
+// cell static_cell put in held[0].
 __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int32_t* order, int64_t ncells,
                                            int leader, bool is_leader, int64_t& cell,
                                            int32_t (&held)[kClaimGroup - 1]) {
@@ -225,6 +238,7 @@ __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int3
     held[kClaimGroup - 2] = -1;
     return true;
   }
+  if (!queue) return false;
   unsigned long long c = 0;
   if (is_leader) c = atomicAdd(queue, order ? (unsigned long long)kClaimGroup : 1ull);
   c = __shfl(c, leader, 64);

@@ -135,6 +135,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
+  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
 
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {

@@ -168,6 +168,7 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
   int32_t held[kClaimGroup - 1];
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
+  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
 
   auto finish = [&](int st, double res) {
     if (warm) {

@@ -139,7 +139,7 @@ struct KParams {
   const int16_t* coo_row;   // [nnz] row of each CSR position (adjoint gradient)
   const int16_t* coo_col;   // [nnz] column of each CSR position
   int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
-  unsigned long long* queue;  // claim counter (workspace word 0), zeroed before the launch
+  unsigned long long* queue;  // claim counter (workspace word 0), zeroed before the launch; null: slot k solves cell k
   const int32_t* order;       // cells in decreasing cost order, or null for index order
   // Workgroup LDS, in doubles: the operand block of slot g of wave w at
   // w * wxs + g * xs (the only region gathers address, kept below 64 KiB

@@ -77,6 +77,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
+  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
 
   auto finish = [&](int st, double res) {
 #pragma unroll
