@@ -1066,10 +1066,16 @@ size_t ws_bytes(int64_t ncells) {
 // slot of its own from the start, the order cannot even out anything: slot
 // k then solves cell k and nothing else (no queue, no claims: P->queue is
 // null and nothing is launched here), instead of half of the slots taking
-// the cells in pairs.  Block-cells (N) runs keep the queue.
-int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream, int64_t slots) {
+// the cells in pairs.  Block-cells (N) runs keep the queue.  With more cells
+// than slots (and `slots` known) and a kernel built with the path
+// (`first_claims`), the slots' first claims are handed out without the
+// counter (slot k takes the positions from k * cells per claim) and the
+// counter starts past them, so the launch does not open with every slot's
+// atomic on one address at once.
+int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream, int64_t slots, bool first_claims) {
   char* w = (char*)ws;
   P->order = nullptr;
+  P->qfirst = 0;
   if (slots > 0 && P->ncells <= slots && p->opt.shared_scalars == 0) {
     P->queue = nullptr;
     return BCS_OK;
@@ -1078,8 +1084,11 @@ int prologue(const bcs_plan* p, bcs::KParams* P, void* ws, hipStream_t stream, i
   const bool use_order = p->opt.cell_order == 1 && p->opt.shared_scalars == 0 && p->opt.matrix_kind == BCS_J_GAMMA &&
                          P->gamma_stride != 0 && P->ncells >= 2 && P->ncells <= INT32_MAX;
   int32_t* order = use_order ? (int32_t*)(w + bcs::kWsOrderOffset) : nullptr;
-  const hipError_t e = bcs::launch_solve_prologue(P->queue, P->gamma, P->gamma_stride, P->ncells,
-                                                  (uint32_t*)(w + bcs::kWsStateOffset), order, stream);
+  if (first_claims && slots > 0 && p->opt.shared_scalars == 0)
+    P->qfirst = slots * (use_order ? bcs::kClaimGroup : 1);
+  const hipError_t e = bcs::launch_solve_prologue(P->queue, (unsigned long long)P->qfirst, P->gamma,
+                                                  P->gamma_stride, P->ncells, (uint32_t*)(w + bcs::kWsStateOffset),
+                                                  order, stream);
   if (e != hipSuccess) return fail(BCS_ERR_HIP, "solve prologue launch: %s", hipGetErrorString(e));
   P->order = order;
   return BCS_OK;
@@ -1116,6 +1125,12 @@ int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
   const int64_t cap = (int64_t)K.max_blocks * p->num_cu;
   return (int)std::max<int64_t>(1, std::min(need, cap));
 }
+
+// Whether kernel K's slots take their first claims without the counter (the
+// FP64 kernels with Jacobi or no preconditioner; the ILU(0) and mixed
+// kernels are built without that path: it cost the 64-lane ILU(0) kernel
+// its second wave per SIMD, and the mixed kernel's code got slower).
+bool first_claims(const bcs_plan* p, const Kernel& K) { return !K.ilu && p->opt.precision == BCS_FP64; }
 
 // Cell slots of a launch of kernel K over ncells cells.
 int64_t slots_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
@@ -1166,7 +1181,7 @@ int time_launches(const bcs_plan* p, const Kernel& K, const bcs::KParams& P0, vo
   for (int rep = 0; rep <= reps && rc == BCS_OK; ++rep) {
     (void)hipEventRecord(e0, nullptr);
     bcs::KParams P = P0;
-    rc = prologue(p, &P, ws, nullptr, slots_for(p, K, P.ncells));
+    rc = prologue(p, &P, ws, nullptr, slots_for(p, K, P.ncells), first_claims(p, K));
     if (rc == BCS_OK) rc = launch(p, K, P, nullptr);
     (void)hipEventRecord(e1, nullptr);
     if (rc != BCS_OK) break;
@@ -1746,7 +1761,7 @@ int bcs_solve_batch(const bcs_plan* p, int64_t ncells, const double* values, con
   P.resid = resid;
   P.status = status;
   P.refinements = refinements;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd, ncells));
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd, ncells), first_claims(p, p->fwd));
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd, P, (hipStream_t)stream);
 }
@@ -1803,7 +1818,7 @@ int bcs_solve_batch_adjoint(const bcs_plan* p, int64_t ncells, const double* val
   P.resid = resid;
   P.status = status;
   P.refinements = nullptr;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->adj, ncells));
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->adj, ncells), first_claims(p, p->adj));
   if (rc != BCS_OK) return rc;
   return launch(p, p->adj, P, (hipStream_t)stream);
 }
@@ -1927,7 +1942,7 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.yoff = lay[q].yoff;
     P.tbase = M.ent_off[q];
     P.x0 = nullptr;
-    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream, 0);  // each mechanism in its cost order
+    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream, 0, false);  // each mechanism in its cost order
     if (rc != BCS_OK) return rc;
     M.m[q] = P;
     const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
@@ -2114,7 +2129,7 @@ int bcs_solve_batch_mech(const bcs_plan* p, int64_t ncells, const double* y, con
   P.mtab_words = p->fwd_mech.mwords;
   P.mk = k_stride == 0 ? p->mech->R : 0;
   P.mr = p->mech->R;
-  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd_mech, ncells));
+  rc = prologue(p, &P, workspace, (hipStream_t)stream, slots_for(p, p->fwd_mech, ncells), first_claims(p, p->fwd_mech));
   if (rc != BCS_OK) return rc;
   return launch(p, p->fwd_mech, P, (hipStream_t)stream);
 }

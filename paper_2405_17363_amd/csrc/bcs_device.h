@@ -203,17 +203,23 @@ constexpr int kGatherChunk = 16;
 // J terms evaluated together when a kernel assembles J while staging a cell.
 constexpr int kJTermChunk = 8;
 
-// Cells a slot takes per claim when the cells come in a cost order.
-constexpr int kClaimGroup = 2;
+// Slots are numbered workgroup by workgroup, wave by wave, slot by slot.
+__device__ __forceinline__ int64_t slot_index(int wv, int grp, int slots_per_wave) {
+  return ((int64_t)blockIdx.x * kWavesPerWg + wv) * slots_per_wave + grp;
+}
 
-// The one cell of slot `grp` of wave `wv` when the launch has a slot for
-// every cell and no work queue (queue null): slots are numbered workgroup by
-// workgroup, wave by wave, slot by slot, and slot k takes cell k.  -1 when
-// there is a queue, or no cell for this slot.
-__device__ __forceinline__ int32_t static_cell(const unsigned long long* queue, int64_t ncells, int wv, int grp,
-                                               int slots_per_wave) {
-  if (queue) return -1;
-  const int64_t c = ((int64_t)blockIdx.x * kWavesPerWg + wv) * slots_per_wave + grp;
+// held[0] of a slot whose first claim is handed out without the counter.
+constexpr int32_t kFirstClaim = -2;
+
+// A slot's held[0] at kernel start.  Without a work queue (queue null: the
+// launch has a slot for every cell) slot k takes cell k, -1 if there is no
+// such cell.  With a queue whose counter starts at qfirst > 0, the slots'
+// first claims take the positions below qfirst without the counter
+// (kFirstClaim; slot k from k * cells per claim).  Else -1.
+__device__ __forceinline__ int32_t initial_held(const unsigned long long* queue, int64_t qfirst, int64_t ncells, int wv,
+                                                int grp, int slots_per_wave) {
+  if (queue) return qfirst > 0 ? kFirstClaim : -1;
+  const int64_t c = slot_index(wv, grp, slots_per_wave);
   return c < ncells ? (int32_t)c : -1;
 }
 
@@ -227,10 +233,14 @@ __device__ __forceinline__ int32_t static_cell(const unsigned long long* queue, 
 // memory round trip; the first is solved now, the others are kept in
 // held[] (-1 when none) and solved next without another claim.  Without a
 // queue (null: the launch has a slot for every cell) a slot solves only the
-// cell static_cell put in held[0].
+// cell initial_held put in held[0].  A slot whose held[0] is kFirstClaim
+// takes its first claim's positions from its slot index (wv, grp,
+// slots_per_wave) instead of the counter (FIRST: kernels built without that
+// path, whose launches always start the counter at 0, leave it out).
+template <bool FIRST = true>
 __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int32_t* order, int64_t ncells,
                                            int leader, bool is_leader, int64_t& cell,
-                                           int32_t (&held)[kClaimGroup - 1]) {
+                                           int32_t (&held)[kClaimGroup - 1], int wv, int grp, int slots_per_wave) {
   if (held[0] >= 0) {
     cell = held[0];
 #pragma unroll
@@ -240,8 +250,13 @@ __device__ __forceinline__ bool claim_cell(unsigned long long* queue, const int3
   }
   if (!queue) return false;
   unsigned long long c = 0;
-  if (is_leader) c = atomicAdd(queue, order ? (unsigned long long)kClaimGroup : 1ull);
-  c = __shfl(c, leader, 64);
+  if (FIRST && held[0] == kFirstClaim) {
+    c = (unsigned long long)slot_index(wv, grp, slots_per_wave) * (order ? kClaimGroup : 1);
+    held[0] = -1;
+  } else {
+    if (is_leader) c = atomicAdd(queue, order ? (unsigned long long)kClaimGroup : 1ull);
+    c = __shfl(c, leader, 64);
+  }
   if (c >= (unsigned long long)ncells) return false;
   if (order) {
     int32_t v[kClaimGroup];

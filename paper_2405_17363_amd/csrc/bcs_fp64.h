@@ -135,7 +135,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
-  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
+  held[0] = initial_held(P.queue, P.qfirst, P.ncells, wv, grp, 64 / LANES);
 
   // Write the cell's outputs and free the slot.
   auto finish = [&](int st, double res) {
@@ -234,7 +234,7 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         pad = cell >= P.ncells;
         if (pad) cell = 0;  // loads stay in bounds; the data is zeroed below
       } else {
-        claimed = claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held);
+        claimed = claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES);
       }
       if (!claimed) {
         dead = true;

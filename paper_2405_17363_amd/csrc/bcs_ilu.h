@@ -168,7 +168,7 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
   int32_t held[kClaimGroup - 1];
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
-  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
+  held[0] = initial_held(P.queue, 0, P.ncells, wv, grp, 64 / LANES);  // no first claims without the counter
 
   auto finish = [&](int st, double res) {
     if (warm) {
@@ -243,7 +243,7 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held)) {
+      if (!claim_cell<false>(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES)) {
         dead = true;
       } else {
         // 1. A into the factor block: -(gamma J) at every position, then

@@ -77,11 +77,11 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
                const std::vector<int>* mech_terms = nullptr, int wg_waves = kWavesPerWg);
 
 // Prologue of every solve (bcs_order.hip), on `stream`: zero the work queue
-// (kQueueWords words) and, when `order` is not null, fill order[0, ncells)
+// (kQueueWords words; the claim counter, word 0, set to qstart) and, when `order` is not null, fill order[0, ncells)
 // with the cell indices sorted by a bucket of gamma[c * stride], largest
 // first (state: kOrderStateWords words of scratch).
-hipError_t launch_solve_prologue(unsigned long long* queue, const double* gamma, int64_t stride, int64_t ncells,
-                                 uint32_t* state, int32_t* order, hipStream_t stream);
+hipError_t launch_solve_prologue(unsigned long long* queue, unsigned long long qstart, const double* gamma,
+                                 int64_t stride, int64_t ncells, uint32_t* state, int32_t* order, hipStream_t stream);
 
 // The ILU(0) kernel for one pattern: schedules of A, L_s and U_s (flags,
 // segment lengths, rows per lane each) and the factorisation program's step

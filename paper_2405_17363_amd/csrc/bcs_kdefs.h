@@ -71,6 +71,8 @@ constexpr int kWsQueueBytes = kQueueWords * 8;
 // odd k, so expensive cells start early while cheap ones keep the refill rate
 // even.  The sort state is the bucket counts, then the bucket cursors.
 constexpr int kOrderBuckets = 128;
+// Cells a slot takes per claim when the cells come in a cost order.
+constexpr int kClaimGroup = 2;
 constexpr int kOrderStateWords = 2 * kOrderBuckets;
 constexpr int kWsStateOffset = kWsQueueBytes;
 constexpr int kWsOrderOffset = kWsStateOffset + kOrderStateWords * 4;
@@ -141,6 +143,7 @@ struct KParams {
   int32_t adjoint;          // 1: solve with A^T, write grad_b = lambda and grad_A
   unsigned long long* queue;  // claim counter (workspace word 0), zeroed before the launch; null: slot k solves cell k
   const int32_t* order;       // cells in decreasing cost order, or null for index order
+  int64_t qfirst;             // > 0: slots' first claims take queue positions [0, qfirst) without the counter, which starts at qfirst
   // Workgroup LDS, in doubles: the operand block of slot g of wave w at
   // w * wxs + g * xs (the only region gathers address, kept below 64 KiB
   // for 16-bit addresses), its state block at bbase + w * wbs + g * bs, then

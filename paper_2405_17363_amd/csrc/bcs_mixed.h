@@ -77,7 +77,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
   int32_t held[kClaimGroup - 1];  // cells claimed and not yet started
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
-  held[0] = static_cell(P.queue, P.ncells, wv, grp, 64 / LANES);
+  held[0] = initial_held(P.queue, 0, P.ncells, wv, grp, 64 / LANES);  // no first claims without the counter
 
   auto finish = [&](int st, double res) {
 #pragma unroll
@@ -141,7 +141,7 @@ __device__ __forceinline__ void mixed_body(const KParams& P) {
 
   // Take the next cell and stage it (sets dead when the queue is empty).
   auto claim_and_stage = [&]() {
-    if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held)) {
+    if (!claim_cell<false>(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES)) {
       dead = true;
     } else {
       const double* vals = P.values + cell * nnz;

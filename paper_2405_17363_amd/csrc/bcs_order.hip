@@ -25,11 +25,13 @@ __device__ __forceinline__ int gamma_bucket(double g) {
   return b < 0 ? 0 : (b >= kOrderBuckets ? kOrderBuckets - 1 : (int)b);
 }
 
-// Pass 0: clear the solve's work queue and (when a cost order is built) the
-// sort state.  A kernel, not a memset, so that the whole prologue is plain
+// Pass 0: clear the solve's work queue (the claim counter starts at qstart,
+// the positions the slots' first claims take without it) and, when a cost
+// order is built, the sort state.  A kernel, not a memset, so that the whole prologue is plain
 // kernel launches on the solve's stream.
-__global__ void __launch_bounds__(kOrderThreads) k_order_clear(unsigned long long* queue, uint32_t* state) {
-  for (int i = threadIdx.x; i < kQueueWords; i += kOrderThreads) queue[i] = 0ull;
+__global__ void __launch_bounds__(kOrderThreads) k_order_clear(unsigned long long* queue, unsigned long long qstart,
+                                                               uint32_t* state) {
+  for (int i = threadIdx.x; i < kQueueWords; i += kOrderThreads) queue[i] = i == 0 ? qstart : 0ull;
   if (state)
     for (int i = threadIdx.x; i < kOrderStateWords; i += kOrderThreads) state[i] = 0u;
 }
@@ -91,9 +93,9 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_scatter(const double* g
 
 }  // namespace
 
-hipError_t launch_solve_prologue(unsigned long long* queue, const double* gamma, int64_t stride, int64_t ncells,
-                                 uint32_t* state, int32_t* order, hipStream_t stream) {
-  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(kOrderThreads), 0, stream, queue, order ? state : nullptr);
+hipError_t launch_solve_prologue(unsigned long long* queue, unsigned long long qstart, const double* gamma,
+                                 int64_t stride, int64_t ncells, uint32_t* state, int32_t* order, hipStream_t stream) {
+  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(kOrderThreads), 0, stream, queue, qstart, order ? state : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !order) return e;
   const int blocks = (int)((ncells + kCellsPerBlock - 1) / kCellsPerBlock);

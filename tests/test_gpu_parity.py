@@ -512,20 +512,21 @@ def test_warm_start_matches_the_oracle_and_saves_iterations():
     assert np.array_equal(xin.cpu().numpy(), x)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp64_small", "adjoint", "mixed", "ilu0"])
+@pytest.mark.parametrize("form", ["fp64", "fp64_small", "adjoint", "adjoint_small", "mixed", "mixed_small", "ilu0",
+                                  "ilu0_small"])
 def test_work_queue_hands_every_cell_out_exactly_once(form, monkeypatch):
     """Debug counter (bcs_debug_count_visits, compiled in with
     BCS_DEBUG_VISITS): on the 100k-cell workload, in the cost order, every
     cell's outputs are written exactly once, and the outputs (pre-filled
-    with sentinels) are all written.  fp64_small: 1,000 of the cells, fewer
-    than the launch's slots, claimed one at a time without the order."""
+    with sentinels) are all written.  The _small forms: 1,000 of the cells,
+    no more than the launch's slots, so slot k solves cell k with no queue."""
     monkeypatch.setenv("BCS_DEBUG_VISITS", "1")
     mech, cells = config_inputs(3)[0]
-    if form == "fp64_small":
+    if form.endswith("_small"):
         cells = {k: v[:1000] for k, v in cells.items()}
+        form = form[:-len("_small")]
     C = cells["b"].shape[0]
-    kw = {"fp64": {}, "fp64_small": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"},
-          "ilu0": {"precond": "ilu0"}}[form]
+    kw = {"fp64": {}, "adjoint": {}, "mixed": {"precision": "fp32_refine"}, "ilu0": {"precond": "ilu0"}}[form]
     plan = bcs.Plan(mech.row_ptr, mech.col_idx, **kw)
     V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
     counts = torch.zeros(C, dtype=torch.int32, device="cuda")
