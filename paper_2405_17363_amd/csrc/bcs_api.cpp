@@ -1922,6 +1922,11 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
   if (rc != BCS_OK) return fail(rc, "%s", err);
   int64_t need = 0;
   for (int q = 0; q < nm; ++q) {
+    const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / plans[order[q]]->fwd.lanes);
+    need += (ncells[order[q]] + cpw - 1) / cpw;
+  }
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)jk.max_blocks * plans[order[0]]->num_cu));
+  for (int q = 0; q < nm; ++q) {
     const int m = order[q];
     const bcs_plan* p = plans[m];
     bcs::KParams P = base_params(p, ncells[m], values[m], gamma[m], gamma_stride[m], rtol, maxit);
@@ -1942,13 +1947,16 @@ int bcs_solve_multi(int32_t nmech, const bcs_plan* const* plans, const int64_t* 
     P.yoff = lay[q].yoff;
     P.tbase = M.ent_off[q];
     P.x0 = nullptr;
-    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream, 0, false);  // each mechanism in its cost order
+    // Every wave starts on the first mechanism: its cells are handed out
+    // like a single mechanism's (slot k's first claim without the counter,
+    // or slot k solves cell k when the grid has a slot for each); the
+    // waves reach the others at different times and claim from their
+    // counters, in each mechanism's own cost order.
+    const int64_t slots = q == 0 ? (int64_t)grid * bcs::kWavesPerWg * (64 / p->fwd.lanes) : 0;
+    rc = prologue(p, &P, (char*)workspace + ws_off[m], (hipStream_t)stream, slots, q == 0);
     if (rc != BCS_OK) return rc;
     M.m[q] = P;
-    const int64_t cpw = (int64_t)bcs::kWavesPerWg * (64 / p->fwd.lanes);
-    need += (ncells[m] + cpw - 1) / cpw;
   }
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)jk.max_blocks * plans[order[0]]->num_cu));
   void* args[] = {&M};
   const hipError_t e = hipModuleLaunchKernel(jk.fn, grid, 1, 1, bcs::kWgThreads, 1, 1, (unsigned)lds,
                                              (hipStream_t)stream, args, nullptr);
