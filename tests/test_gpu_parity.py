@@ -573,3 +573,37 @@ def test_waves_per_workgroup_leave_results_bitwise_unchanged(waves):
     torch.cuda.synchronize()
     for a, b in zip(got[:4], ref[:4]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("lanes", [32, 64])
+def test_batch_sizes_around_the_slot_count(lanes, monkeypatch):
+    """A launch gives every cell a slot of its own when the batch fits the
+    resident grid (no queue), and otherwise hands out the slots' first claims
+    without the counter and the rest through it.  Around each possible slot
+    count (1-4 resident workgroups per CU) every cell is written exactly
+    once, and every output is bitwise the same cell's output in a
+    10,000-cell batch (a cell's result depends on nothing else)."""
+    monkeypatch.setenv("BCS_DEBUG_VISITS", "1")
+    mech, cells = config_inputs(3, ncells=10000)[0]
+    V, G, B = gpu(cells["values"]), gpu(cells["gamma"]), gpu(cells["b"])
+    plan = bcs.Plan(mech.row_ptr, mech.col_idx, lanes_per_cell=lanes)
+    full = [t.cpu().numpy() for t in bcs.solve_batch(plan, V, G, B, RTOL, 200)[:4]]
+    cpw = plan.info()["cells_per_wg"]
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    L = bcs.lib()
+    sizes = sorted({c for k in (1, 2, 3, 4) for c in (cpw * ncu * k - 1, cpw * ncu * k, cpw * ncu * k + 1)
+                    if c <= V.shape[0]})
+    assert len(sizes) >= 6
+    for C in sizes:
+        counts = torch.zeros(C, dtype=torch.int32, device="cuda")
+        L.bcs_debug_count_visits(counts.data_ptr())
+        try:
+            got = bcs.solve_batch(plan, V[:C], G[:C], B[:C], RTOL, 200)
+            torch.cuda.synchronize()
+        finally:
+            L.bcs_debug_count_visits(None)
+        c = counts.cpu().numpy()
+        assert np.all(c == 1), (C, np.bincount(c))
+        for a, b in zip(full, got[:4]):
+            b = b.cpu().numpy()
+            assert np.array_equal(a[:C], b, equal_nan=b.dtype.kind == "f"), C
