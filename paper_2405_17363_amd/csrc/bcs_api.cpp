@@ -732,9 +732,15 @@ int make_ilu_kernel(int n, const std::vector<int>& rp, const std::vector<int>& c
   const int* segs[3] = {SA.seg.data(), SL.seg.data(), SU.seg.data()};
   const int rpls[3] = {rpl, rpl, rpl};
   char err[512] = {0};
-  const int rc = bcs::jit_ilu_kernel(lanes, flags, segs, rpls, nnz, prog.widths.data(), (int)prog.widths.size(),
-                                     K.lds, &K.jit, err, sizeof(err));
-  if (rc != BCS_OK) return fail(rc, "%s", err);
+  // First built for two waves per SIMD (at most 256 VGPRs: the 64-lane body
+  // of the benchmark pattern sits at that limit, and the bound keeps it
+  // there); a build that spills under the bound is rebuilt without it.
+  for (const int waves : {2, 0}) {
+    const int rc = bcs::jit_ilu_kernel(lanes, flags, segs, rpls, nnz, prog.widths.data(), (int)prog.widths.size(),
+                                       waves, K.lds, &K.jit, err, sizeof(err));
+    if (rc != BCS_OK) return fail(rc, "%s", err);
+    if (K.jit.scratch == 0) break;
+  }
   if (K.jit.scratch > 0) return BCS_ERR_UNSUPPORTED;  // spills: another lane count serves the pattern
   K.max_blocks = K.jit.max_blocks;
   if (const char* e = std::getenv("BCS_BLOCKS_PER_CU")) {

@@ -85,9 +85,10 @@ hipError_t launch_solve_prologue(unsigned long long* queue, unsigned long long q
 
 // The ILU(0) kernel for one pattern: schedules of A, L_s and U_s (flags,
 // segment lengths, rows per lane each) and the factorisation program's step
-// widths.
+// widths; waves_per_eu > 0 adds that launch bound.
 int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,
-                   const int* widths, int nstep, size_t lds_bytes, JitKernel* out, char* err, size_t errlen);
+                   const int* widths, int nstep, int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err,
+                   size_t errlen);
 
 // The multi-mechanism kernel for mechanisms with the given layouts, in order.
 int jit_multi_kernel(int nmech, const int* lanes, const int* flags, const int* const* seg, const int* rpl,

@@ -255,11 +255,14 @@ int jit_kernel(const char* body, int adjoint, int grouped, int lanes, int flags,
 }
 
 int jit_ilu_kernel(int lanes, const int* flags, const int* const* seg, const int* rpl, int nnz,
-                   const int* widths, int nstep, size_t lds_bytes, JitKernel* out, char* err, size_t errlen) {
+                   const int* widths, int nstep, int waves_per_eu, size_t lds_bytes, JitKernel* out, char* err,
+                   size_t errlen) {
   std::ostringstream src;
   preamble(src);
   src << "#include \"bcs_ilu.h\"\n"
-      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads) bcs_solve_ilu0(bcs::KParams P) {\n"
+      << "extern \"C\" __global__ void __launch_bounds__(bcs::kWgThreads";
+  if (waves_per_eu > 0) src << ", " << waves_per_eu;
+  src << ") bcs_solve_ilu0(bcs::KParams P) {\n"
       << "  bcs::ilu_body<";
   for (int m = 0; m < 3; ++m) {
     sched_type(src, lanes, flags[m], seg[m], rpl[m]);
