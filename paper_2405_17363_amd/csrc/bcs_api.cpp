@@ -1133,10 +1133,12 @@ int grid_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {
 }
 
 // Whether kernel K's slots take their first claims without the counter (the
-// FP64 kernels with Jacobi or no preconditioner; the ILU(0) and mixed
-// kernels are built without that path: it cost the 64-lane ILU(0) kernel
-// its second wave per SIMD, and the mixed kernel's code got slower).
-bool first_claims(const bcs_plan* p, const Kernel& K) { return !K.ilu && p->opt.precision == BCS_FP64; }
+// FP64 kernels; the mixed kernel is built without that path: with it, its
+// code got slower).
+bool first_claims(const bcs_plan* p, const Kernel& K) {
+  (void)K;
+  return p->opt.precision == BCS_FP64;
+}
 
 // Cell slots of a launch of kernel K over ncells cells.
 int64_t slots_for(const bcs_plan* p, const Kernel& K, int64_t ncells) {

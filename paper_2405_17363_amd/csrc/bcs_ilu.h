@@ -168,7 +168,7 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
   int32_t held[kClaimGroup - 1];
 #pragma unroll
   for (int q = 0; q < kClaimGroup - 1; ++q) held[q] = -1;
-  held[0] = initial_held(P.queue, 0, P.ncells, wv, grp, 64 / LANES);  // no first claims without the counter
+  held[0] = initial_held(P.queue, P.qfirst, P.ncells, wv, grp, 64 / LANES);
 
   auto finish = [&](int st, double res) {
     if (warm) {
@@ -243,9 +243,15 @@ __device__ __forceinline__ void ilu_body(const KParams& P) {
 
   for (;;) {
     if (!active && !dead) {
-      if (!claim_cell<false>(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES)) {
+      if (!claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES)) {
         dead = true;
       } else {
+        if constexpr (LANES == 64) {
+          // one cell per wave: keep its index in scalar registers
+          const uint64_t u = (uint64_t)cell;
+          cell = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+        }
         // 1. A into the factor block: -(gamma J) at every position, then
         //    1 + that on the diagonal (which rounds as 1 - gamma J does)
         const double* vals = P.values + cell * NNZ;
