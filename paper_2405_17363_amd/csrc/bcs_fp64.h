@@ -235,6 +235,12 @@ __device__ __forceinline__ void fp64_run(const KParams& P, double* lds, int wv, 
         if (pad) cell = 0;  // loads stay in bounds; the data is zeroed below
       } else {
         claimed = claim_cell(P.queue, P.order, P.ncells, grp * LANES, gl == 0, cell, held, wv, grp, 64 / LANES);
+        if constexpr (LANES == 64) {
+          // one cell per wave: keep its index in scalar registers
+          const uint64_t u = (uint64_t)cell;
+          cell = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+        }
       }
       if (!claimed) {
         dead = true;
